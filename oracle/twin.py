@@ -1,0 +1,100 @@
+"""Numpy twin of the C oracle (TEST INFRASTRUCTURE ONLY).
+
+A second, independent transcription of the same recurrences as
+``sbs_oracle.c``: each row of the interleaved (n, m) array is one numpy
+expression, evaluated with the same IEEE operations in the same order (a
+product, then a difference, then a true division; numpy never fuses a
+multiply into an add).  The C oracle and this twin must therefore agree bit
+for bit, which pins each against transcription slips in the other.
+
+Band convention and out-of-matrix coefficients are as in the C file:
+tridiagonal row i is a_i x_{i-1} + b_i x_i + c_i x_{i+1}; pentadiagonal row i
+is a_i x_{i-2} + b_i x_{i-1} + c_i x_i + d_i x_{i+1} + e_i x_{i+2}.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+class PivotError(ArithmeticError):
+    """A zero or non-finite pivot at ``row`` (0-based)."""
+
+    def __init__(self, row: int):
+        super().__init__(f"zero or non-finite pivot at row {row}")
+        self.row = row
+
+
+def _check(p: float, i: int) -> None:
+    if not (np.isfinite(p) and p != 0.0):
+        raise PivotError(i)
+
+
+def tri_factor(a, b, c):
+    """Section 3.1 pre-factorisation: returns (den, chat) with
+    den_0 = b_0, den_i = b_i - a_i chat_{i-1}, chat_i = c_i / den_i and
+    chat_{n-1} = 0 (c_{n-1} is outside the matrix)."""
+    n = len(b)
+    den = np.zeros(n)
+    chat = np.zeros(n)
+    den[0] = b[0]
+    _check(den[0], 0)
+    chat[0] = c[0] / den[0] if n > 1 else 0.0
+    for i in range(1, n):
+        den[i] = b[i] - a[i] * chat[i - 1]
+        _check(den[i], i)
+        chat[i] = c[i] / den[i] if i < n - 1 else 0.0
+    return den, chat
+
+
+def tri_solve(a, b, c, d):
+    """Section 3.1 forward and backward sweeps over interleaved d (n, m)."""
+    den, chat = tri_factor(a, b, c)
+    x = np.array(d, dtype=np.float64, copy=True)
+    n = x.shape[0]
+    x[0] = x[0] / den[0]
+    for i in range(1, n):
+        x[i] = (x[i] - a[i] * x[i - 1]) / den[i]
+    for i in range(n - 2, -1, -1):
+        x[i] = x[i] - chat[i] * x[i + 1]
+    return x
+
+
+def penta_factor(a, b, c, d, e):
+    """Section 4.1 factorisation A = L R with all out-of-matrix terms 0.
+    Returns a dict of the five factor vectors."""
+    n = len(c)
+    al, be, ga, de, ep = (np.zeros(n) for _ in range(5))
+    for i in range(n):
+        ai = a[i] if i >= 2 else 0.0
+        bi = b[i] if i >= 1 else 0.0
+        di = d[i] if i <= n - 2 else 0.0
+        ei = e[i] if i <= n - 3 else 0.0
+        gm2 = ga[i - 2] if i >= 2 else 0.0
+        gm1 = ga[i - 1] if i >= 1 else 0.0
+        dm2 = de[i - 2] if i >= 2 else 0.0
+        dm1 = de[i - 1] if i >= 1 else 0.0
+        be[i] = bi - ai * gm2
+        al[i] = c[i] - ai * dm2 - be[i] * gm1
+        _check(al[i], i)
+        ga[i] = (di - be[i] * dm1) / al[i]
+        de[i] = ei / al[i]
+        ep[i] = ai
+    return {"alpha": al, "beta": be, "gamma": ga, "delta": de, "eps": ep}
+
+
+def penta_solve(a, b, c, d, e, f):
+    """Section 4.1: L g = f forward, then R x = g backward, interleaved (n, m)."""
+    F = penta_factor(a, b, c, d, e)
+    al, be, ga, de, ep = F["alpha"], F["beta"], F["gamma"], F["delta"], F["eps"]
+    x = np.array(f, dtype=np.float64, copy=True)
+    n = x.shape[0]
+    zero = np.zeros_like(x[0])
+    for i in range(n):
+        g2 = x[i - 2] if i >= 2 else zero
+        g1 = x[i - 1] if i >= 1 else zero
+        x[i] = (x[i] - ep[i] * g2 - be[i] * g1) / al[i]
+    for i in range(n - 1, -1, -1):
+        x1 = x[i + 1] if i + 1 < n else zero
+        x2 = x[i + 2] if i + 2 < n else zero
+        x[i] = x[i] - ga[i] * x1 - de[i] * x2
+    return x
