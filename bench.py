@@ -1,0 +1,208 @@
+"""Benchmark: shared-LHS batched solves on one MI355X.
+
+Headline (the JSON line's `value`): right-hand-side unknowns solved per
+second for the pentadiagonal FP64 workload -- n = 1024 unknowns, m = 65536
+systems sharing one matrix (1-D hyperdiffusion Crank--Nicolson step, s = 0.5)
+-- one in-place solve per step, inputs resident in HBM.  Beside it: the
+roofline of the sweep kernel (algorithmic 16 B per unknown against 8 TB/s),
+the oracle timed on the host cores, and the other workloads (tridiagonal
+n=256 batch, 2-D ADI step, mixed-precision refinement, serving).
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--only headline]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def timed_steps(step, K, W, torch):
+    """W untimed steps, then K timed steps bracketed by synchronisation; HIP
+    events on the launch stream give the device time of the same region."""
+    for _ in range(W):
+        step()
+    torch.cuda.synchronize()
+    s = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(s)
+    for _ in range(K):
+        step()
+    e1.record(s)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / K
+    dev = e0.elapsed_time(e1) * 1e-3 / K
+    return wall, dev
+
+
+def cpu_baseline(kind, bands, rhs_sample, target_s=10.0):
+    """The oracle (C, OpenMP over column blocks) on a bounded sample."""
+    import oracle
+    threads = oracle.max_threads()
+    X = rhs_sample.copy()
+    n, m = X.shape
+    oracle.solve_inplace_mt(kind, bands, X, threads)       # warm
+    reps, t0 = 0, time.perf_counter()
+    while True:
+        X[...] = rhs_sample
+        t = time.perf_counter()
+        oracle.solve_inplace_mt(kind, bands, X, threads)
+        reps += 1
+        el = time.perf_counter() - t0
+        if el >= target_s or reps >= 1000:
+            break
+    # time only the solves (the copy back to the pristine input is excluded)
+    t_solve = 0.0
+    for _ in range(3):
+        X[...] = rhs_sample
+        t = time.perf_counter()
+        oracle.solve_inplace_mt(kind, bands, X, threads)
+        t_solve += time.perf_counter() - t
+    per = t_solve / 3
+    return {"value": n * m / per, "unit": "unknowns/s", "cores": threads, "kind": "oracle",
+            "sample": f"n={n}, m={m} columns of the same workload (seeded), {reps} solves over "
+                      f"{el:.1f} s, median-free mean of 3 timed solves"}
+
+
+def bench_headline(args, torch, sbs, W):
+    wl = W.config1()
+    n, m = wl.n, wl.m
+    rhs = torch.from_numpy(wl.rhs).to("cuda:0")
+    lhs = sbs.SharedLhs(5, wl.bands)
+    variant = {"auto": 0, "resident": 1, "chunked": 2, "stream": 3}[args.variant]
+    step = lambda: lhs.solve(rhs, variant)
+    wall, dev = timed_steps(step, args.steps, args.warmup, torch)
+    unknowns = n * m
+    achieved = 16.0 * unknowns / dev / 1e9
+    res = {
+        "wall_s": wall, "dev_s": dev, "unknowns": unknowns,
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None},
+        "cpu_sample": wl.rhs[:, :8192].copy(), "bands": wl.bands,
+    }
+    lhs.close()
+    del rhs
+    return res
+
+
+def bench_tri256(args, torch, sbs, W):
+    wl = W.config0()
+    rhs = torch.from_numpy(wl.rhs).to("cuda:0")
+    lhs = sbs.SharedLhs(3, wl.bands)
+    wall, dev = timed_steps(lambda: lhs.solve(rhs), 200, 20, torch)
+    lhs.close()
+    u = wl.n * wl.m
+    return {"workload": "tri_f64_n256_m1024", "unknowns_per_s": u / dev, "us_per_solve": dev * 1e6,
+            "hbm_frac_16B": round(16 * u / dev / 1e9 / HBM_PEAK_GBS, 4), "bound": "latency (16 waves)"}
+
+
+def bench_adi(args, torch, sbs, W):
+    wl = W.config2()
+    g = torch.from_numpy(wl.rhs).to("cuda:0")
+    work = torch.empty_like(g)
+    hy, hx = sbs.SharedLhs(3, wl.bands), sbs.SharedLhs(3, wl.extra["bands_x"])
+    step = lambda: sbs.sbs_adi_step(hy.handle, hx.handle, g, work)
+    wall, dev = timed_steps(step, 20, 3, torch)
+    hy.close()
+    hx.close()
+    pts = wl.n * wl.m
+    return {"workload": "adi_f64_2048x2048", "points_per_s": pts / dev, "unknowns_per_s": 2 * pts / dev,
+            "ms_per_step": dev * 1e3, "hbm_frac_32B_per_point": round(32 * pts / dev / 1e9 / HBM_PEAK_GBS, 4),
+            "bound": "latency (32 waves per sweep)"}
+
+
+def bench_refined(args, torch, sbs, W):
+    wl = W.config3()
+    n, m = wl.n, wl.m
+    b = torch.from_numpy(wl.rhs).to("cuda:0")
+    x = torch.empty((n, m), dtype=torch.float64, device="cuda:0")
+    lhs = sbs.SharedLhs(3, wl.bands)
+    work = torch.empty(sbs.sbs_refined_workspace_bytes(lhs.handle, m), dtype=torch.uint8, device="cuda:0")
+    step = lambda: lhs.solve_refined(b, sweeps=2, x=x, work=work)
+    wall, dev = timed_steps(step, 5, 2, torch)
+    u = n * m
+    out = {"workload": "tri_refine_f32in_f64out_n512_m1048576", "unknowns_per_s": u / dev, "ms_per_solve": dev * 1e3,
+           "hbm_frac_12B_io_min": round(12 * u / dev / 1e9 / HBM_PEAK_GBS, 4)}
+    # plain FP64 on the same shape, for comparison
+    x.copy_(b)
+    wall, dev64 = timed_steps(lambda: lhs.solve(x), 5, 2, torch)
+    out["plain_f64_unknowns_per_s"] = u / dev64
+    out["plain_f64_hbm_frac_16B"] = round(16 * u / dev64 / 1e9 / HBM_PEAK_GBS, 4)
+    # accuracy on sampled columns against the FP64 oracle of double(b32)
+    import oracle
+    cols = np.random.default_rng(3).choice(m, 64, replace=False)
+    xs = lhs.solve_refined(b, sweeps=2, x=x, work=work)[:, torch.from_numpy(cols).cuda()].cpu().numpy()
+    ref = oracle.refine_reference(3, wl.bands, wl.rhs[:, cols])
+    out["max_col_rel_err_vs_oracle"] = float(np.max(np.max(np.abs(xs - ref), axis=0) / np.max(np.abs(ref), axis=0)))
+    lhs.close()
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--variant", default="auto", choices=["auto", "resident", "chunked", "stream"])
+    ap.add_argument("--only", default="", help="'headline' skips the other workloads")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: the batched solve shards over systems with no exchange "
+              "; run it with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1909_04539_amd import sbs, workloads as W
+    sbs.lib()
+    log("headline: penta f64 n=1024 m=65536")
+    h = bench_headline(args, torch, sbs, W)
+    extra = {}
+    if args.only != "headline":
+        for name, fn in (("tri_n256_m1024", bench_tri256), ("adi_2048", bench_adi), ("refined_n512_m1M", bench_refined)):
+            log(f"workload {name}")
+            try:
+                extra[name] = fn(args, torch, sbs, W)
+            except Exception as e:  # report, do not hide
+                extra[name] = {"error": repr(e)}
+    log("cpu baseline (oracle)")
+    cpu = cpu_baseline(5, h["bands"], h["cpu_sample"], args.cpu_seconds)
+    line = {
+        "metric": "RHS unknowns solved/s (pentadiagonal FP64, shared LHS)",
+        "value": h["unknowns"] / h["wall_s"],
+        "unit": "unknowns/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": h["wall_s"] * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic (seeded): rhs = A x_true, x_true ~ N(0,1)",
+        "config": {"workload": "penta_f64_n1024_m65536_shared_lhs", "n": 1024, "m": 65536,
+                   "matrix": "I + s(1,-4,6,-4,1), s=0.5, truncated ends", "variant": args.variant},
+        "roofline": h["roofline"],
+        "cpu_baseline": cpu,
+        "kernel_ms": h["dev_s"] * 1e3,
+        "other_workloads": extra,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

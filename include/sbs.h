@@ -1,0 +1,241 @@
+/*
+ * sbs.h -- batched solves of many right-hand sides against ONE shared
+ * tridiagonal or pentadiagonal matrix, on an AMD Instinct MI355X (gfx950).
+ *
+ * Method: Gloster, Carroll, Bustamante, O Naraigh, "Efficient Interleaved
+ * Batch Matrix Solvers for CUDA" (arXiv:1909.04539).  One copy of the
+ * factored left-hand side is shared by every system (Section 2); the
+ * right-hand sides are interleaved so that unknown i of system j lives at
+ * element i*m + j (Section 2, and the storage paragraphs closing Sections
+ * 3.1 and 4.1); each GPU lane runs one system's forward sweep and backward
+ * sweep (Section 2): the Thomas recurrences of Section 3.1 for tridiagonal
+ * matrices and the L R recurrences of Section 4.1 for pentadiagonal ones.
+ *
+ * Conventions for every call:
+ *  - Every function returns an sbs_status; no exception or abort crosses the
+ *    ABI.  Argument errors are detected before any device work is queued.
+ *  - "host" pointers are ordinary CPU memory; "device" pointers are HIP
+ *    device memory of the current device.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *    Solves are queued asynchronously on it; a failed launch returns
+ *    SBS_ERR_DEVICE, faults inside kernels surface at the next synchronisation.
+ *  - A handle is immutable after it is created, so any number of solves may
+ *    use it concurrently on any streams.  It must outlive every solve queued
+ *    with it (release it after synchronising).
+ *  - Every call is thread-safe except that a handle must not be released
+ *    while another thread still uses it.
+ */
+#ifndef SBS_H
+#define SBS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum sbs_status {
+    SBS_OK = 0,
+    SBS_ERR_INVALID_ARG = 1, /* bad kind/dtype/size, null pointer, unknown id  */
+    SBS_ERR_ZERO_PIVOT = 2,  /* a factor pivot is zero or not finite          */
+    SBS_ERR_NONFINITE = 3,   /* a matrix coefficient is NaN or infinite        */
+    SBS_ERR_DEVICE = 4,      /* a HIP call failed (no device, launch failure)  */
+    SBS_ERR_NO_MEMORY = 5,   /* device or host allocation failed               */
+    SBS_ERR_BUDGET = 6,      /* request larger than the server's whole budget  */
+    SBS_ERR_NOT_FOUND = 7,   /* unknown ticket                                 */
+    SBS_ERR_TIMEOUT = 8,     /* wait timed out; the request is still pending   */
+    SBS_ERR_SHUTDOWN = 9     /* server is shutting down                        */
+} sbs_status;
+
+typedef enum sbs_kind { SBS_TRI = 3, SBS_PENTA = 5 } sbs_kind;
+typedef enum sbs_dtype { SBS_F64 = 0, SBS_F32 = 1 } sbs_dtype;
+
+/* Sweep variants (all compute the same recurrences; they differ only in how
+ * a lane keeps its column between the forward and the backward sweep). */
+typedef enum sbs_variant {
+    SBS_VARIANT_AUTO = 0,     /* chosen from n and dtype                      */
+    SBS_VARIANT_RESIDENT = 1, /* whole column in registers (n <= 64)          */
+    SBS_VARIANT_CHUNKED = 2,  /* checkpoint every chunk, recompute backwards  */
+    SBS_VARIANT_STREAM = 3    /* forward result written over the rhs, re-read */
+} sbs_variant;
+
+typedef struct sbs_lhs *sbs_handle;
+
+/* Human-readable name of a status code (static storage, never NULL). */
+const char *sbs_status_str(sbs_status s);
+
+/* Library version string (static storage). */
+const char *sbs_version(void);
+
+/*
+ * Factor the shared matrix once, in FP64, on the host, and upload the factor.
+ * Sections 3.1 (tridiagonal pre-factorisation: chat_i and the denominators
+ * b_i - a_i chat_{i-1}) and 4.1 (pentadiagonal A = L R: alpha, beta, gamma,
+ * delta, epsilon).  The paper performs this step on the CPU (Section 2).
+ *
+ *  kind     SBS_TRI or SBS_PENTA.
+ *  n        number of unknowns per system, n >= 1.
+ *  bands    host, kind*n doubles, band-major and row-aligned: band k, entry i
+ *           is the coefficient in row i.  Tridiagonal row i reads
+ *           a_i x_{i-1} + b_i x_i + c_i x_{i+1}  (bands a, b, c);
+ *           pentadiagonal row i reads a_i x_{i-2} + b_i x_{i-1} + c_i x_i
+ *           + d_i x_{i+1} + e_i x_{i+2}  (bands a, b, c, d, e).
+ *           Entries outside the matrix (tri a_0, c_{n-1}; penta a_0, a_1, b_0,
+ *           d_{n-1}, e_{n-2}, e_{n-1}) are ignored.  The array is copied; the
+ *           caller keeps ownership.
+ *  out      receives the new handle (owned by the caller; free with
+ *           sbs_release).  Set to NULL on every error.
+ *  bad_row  optional (may be NULL): on SBS_ERR_ZERO_PIVOT or
+ *           SBS_ERR_NONFINITE the 0-based offending row, else -1.
+ * There is no pivoting (the paper has none): a zero or non-finite pivot is
+ * reported as SBS_ERR_ZERO_PIVOT.  Diagonally dominant and symmetric
+ * positive definite matrices never produce one.
+ * Errors: SBS_ERR_INVALID_ARG (kind, n < 1, NULL bands/out),
+ *         SBS_ERR_NONFINITE, SBS_ERR_ZERO_PIVOT, SBS_ERR_NO_MEMORY,
+ *         SBS_ERR_DEVICE.
+ */
+sbs_status sbs_factor_shared_lhs(int32_t kind, int64_t n, const double *bands,
+                                 sbs_handle *out, int64_t *bad_row);
+
+/*
+ * Solve m systems in place: forward sweep then backward sweep per system
+ * (Section 3.1 for SBS_TRI, Section 4.1 for SBS_PENTA), one GPU lane per
+ * system, the shared factor read by all lanes (Section 2).
+ *
+ *  rhs    device, n*m elements of `dtype`, interleaved: element i*m + j is
+ *         unknown i of system j.  Overwritten with the solution.
+ *  m      number of systems, m >= 0 (m == 0 queues nothing and returns OK).
+ *  dtype  SBS_F64 (FP64 throughout) or SBS_F32 (FP32 storage and FP32
+ *         arithmetic with the FP32 rounding of the FP64 factor).
+ * Errors: SBS_ERR_INVALID_ARG (NULL handle/rhs with m > 0, m < 0, dtype),
+ *         SBS_ERR_DEVICE.
+ */
+sbs_status sbs_solve_batch(sbs_handle h, void *rhs, int64_t m, int32_t dtype,
+                           void *stream);
+
+/* As sbs_solve_batch with an explicit sweep variant (SBS_VARIANT_*).  The
+ * resident variant needs n <= 64; otherwise SBS_ERR_INVALID_ARG. */
+sbs_status sbs_solve_batch_variant(sbs_handle h, void *rhs, int64_t m,
+                                   int32_t dtype, int32_t variant, void *stream);
+
+/*
+ * Mixed precision: FP32 right-hand sides, FP64 solution.
+ * x0 = FP32 solve of b; then `sweeps` times: r = b - A x in FP64 with the
+ * original FP64 bands, delta = FP32 solve of fl32(r), x += delta in FP64.
+ * The FP32 solves use the FP32 rounding of the FP64 factor.
+ *
+ *  b          device, n*m floats, interleaved, read only.
+ *  x          device, n*m doubles, interleaved, written (may not alias b).
+ *  sweeps     number of corrections, 0..8 (2 is the usual choice).
+ *  work       device scratch of at least sbs_refined_workspace_bytes(h, m)
+ *             bytes (caller-owned; contents on return are unspecified).
+ * Errors: SBS_ERR_INVALID_ARG, SBS_ERR_DEVICE.
+ */
+sbs_status sbs_solve_batch_refined(sbs_handle h, const float *b, double *x,
+                                   int64_t m, int32_t sweeps, void *work,
+                                   size_t work_bytes, void *stream);
+
+/* Bytes of device scratch sbs_solve_batch_refined needs for m systems
+ * (0 for an invalid handle). */
+size_t sbs_refined_workspace_bytes(sbs_handle h, int64_t m);
+
+/*
+ * Out-of-place transpose: dst[c*rows + r] = src[r*cols + c].  Bit-exact
+ * copy of 8-byte (SBS_F64) or 4-byte (SBS_F32) elements.  Converts a
+ * row-major grid into the interleaved layout of its other direction.
+ * src and dst are device buffers of rows*cols elements and must not overlap.
+ */
+sbs_status sbs_transpose(const void *src, void *dst, int64_t rows,
+                         int64_t cols, int32_t dtype, void *stream);
+
+/*
+ * One alternating-direction step on a row-major FP64 grid g[y*nx + x]:
+ * solve along y with hy (n == ny; the columns are already interleaved with
+ * m = nx), transpose into `work`, solve along x with hx (n == nx, m = ny),
+ * transpose back into g.  Both handles must be SBS_TRI or SBS_PENTA.
+ *  grid  device, ny*nx doubles, overwritten.
+ *  work  device scratch, ny*nx doubles (caller-owned).
+ */
+sbs_status sbs_adi_step(sbs_handle hy, sbs_handle hx, double *grid,
+                        double *work, int64_t ny, int64_t nx, void *stream);
+
+/* Release a handle and its device memory.  NULL is accepted (no-op). */
+sbs_status sbs_release(sbs_handle h);
+
+/*
+ * Query a handle.  Any output pointer may be NULL.  device_bytes is the
+ * device memory the handle owns: O(kind * n), independent of how many
+ * systems are later solved with it (the storage argument of Sections 3.1
+ * and 4.1).
+ */
+sbs_status sbs_handle_info(sbs_handle h, int32_t *kind, int64_t *n,
+                           int64_t *device_bytes);
+
+/* ---------------------------------------------------------------------------
+ * Serving: a request loop over registered shared matrices.
+ *
+ * The server owns a device arena of `budget_bytes`.  Each request reserves
+ * its result buffer (n*m doubles) plus its scratch in the arena when it is
+ * admitted, in arrival order, as soon as the bytes are free; a request
+ * larger than the whole budget is rejected with SBS_ERR_BUDGET.  Admitted
+ * requests are coalesced into shared launches (many requests, any n and m,
+ * one kernel) that run on several streams at once, so requests that arrive
+ * while others run are admitted and overlap them on the device.
+ * FP64 requests get the plain FP64 solve; FP32 requests get the mixed
+ * precision solve with 2 corrections.  Either way the result is FP64.
+ */
+typedef struct sbs_server sbs_server;
+
+typedef struct sbs_server_stats {
+    uint64_t submitted, completed, rejected, launches;
+    uint64_t queued;           /* waiting for admission now                 */
+    uint64_t in_flight;        /* admitted, not yet complete                */
+    uint64_t bytes_reserved;   /* arena bytes held by admitted requests     */
+    uint64_t budget_bytes;
+    double p50_us, p99_us, max_us; /* submit -> completion latency so far   */
+    double unknowns;           /* sum of n*m over completed requests        */
+} sbs_server_stats;
+
+/* max_streams: concurrent launch streams (1..16; 0 = default 4).
+ * max_batch_requests: cap on requests coalesced into one launch (0 = 4096). */
+sbs_status sbs_server_create(size_t budget_bytes, int32_t max_streams,
+                             int32_t max_batch_requests, sbs_server **out);
+
+/* Register a factored matrix; the server keeps a reference, the caller still
+ * owns the handle and must keep it alive until sbs_server_destroy. */
+sbs_status sbs_server_register(sbs_server *srv, sbs_handle h, int32_t *lhs_id);
+
+/* Queue a request.  rhs: device, n*m elements of dtype (interleaved),
+ * read-only, must stay valid until the request completes.  Returns at once
+ * with a ticket.  Errors: SBS_ERR_INVALID_ARG, SBS_ERR_BUDGET,
+ * SBS_ERR_SHUTDOWN. */
+sbs_status sbs_server_submit(sbs_server *srv, int32_t lhs_id, const void *rhs,
+                             int64_t m, int32_t dtype, uint64_t *ticket);
+
+/* Wait up to timeout_us (< 0: forever) for a request.  On completion
+ * *x_device points at its FP64 solution (n*m doubles, interleaved) inside
+ * the arena; it stays valid until sbs_server_release(ticket).  *latency_us
+ * (optional) is submit -> completion.  Returns SBS_ERR_TIMEOUT if still
+ * pending, SBS_ERR_NOT_FOUND for an unknown ticket. */
+sbs_status sbs_server_wait(sbs_server *srv, uint64_t ticket, int64_t timeout_us,
+                           const double **x_device, double *latency_us);
+
+/* Copy a completed request's FP64 solution (n*m doubles) to the device
+ * buffer dst, asynchronously on `stream`; the request must not be released
+ * before that copy has finished. */
+sbs_status sbs_server_fetch(sbs_server *srv, uint64_t ticket, double *dst, void *stream);
+
+/* Give a completed request's arena bytes back (admits waiting requests). */
+sbs_status sbs_server_release(sbs_server *srv, uint64_t ticket);
+
+sbs_status sbs_server_stats_get(sbs_server *srv, sbs_server_stats *out);
+
+/* Drain all work, then free the arena and the server. */
+sbs_status sbs_server_destroy(sbs_server *srv);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SBS_H */

@@ -1,0 +1,265 @@
+// C-ABI entry points: argument checking, the host-side FP64 factorisation of
+// the shared matrix, its upload, and dispatch to the HIP kernels.
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "internal.h"
+
+using namespace sbs;
+
+namespace {
+
+bool finite_nonzero(double p) { return std::isfinite(p) && p != 0.0; }
+
+// Coefficient k of row i of a row-aligned band array, 0 outside the matrix.
+double coef(const double *bands, int kind, int64_t n, int k, int64_t i) {
+    const int64_t col = i + k - kind / 2;
+    if (col < 0 || col >= n) return 0.0;
+    return bands[(int64_t)k * n + i];
+}
+
+// Host FP64 factorisation, Section 3.1.  den_i = b_i - a_i chat_{i-1},
+// chat_i = c_i / den_i; rows hold {a_i/den_i, chat_i, 1/den_i}.
+sbs_status factor_tri(const double *B, int64_t n, std::vector<TriRow<double>> &rows, int64_t *bad) {
+    double chat_prev = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        const double a = coef(B, 3, n, 0, i), b = coef(B, 3, n, 1, i), c = coef(B, 3, n, 2, i);
+        const double den = b - a * chat_prev;
+        if (!finite_nonzero(den)) {
+            *bad = i;
+            return SBS_ERR_ZERO_PIVOT;
+        }
+        const double chat = c / den;
+        rows[i] = {a / den, chat, 1.0 / den, 0.0};
+        chat_prev = chat;
+    }
+    return SBS_OK;
+}
+
+// Host FP64 factorisation A = L R, Section 4.1.  With everything outside the
+// matrix equal to zero, one recurrence covers every row:
+//   beta_i = b_i - a_i gamma_{i-2}
+//   alpha_i = c_i - a_i delta_{i-2} - beta_i gamma_{i-1}
+//   gamma_i = (d_i - beta_i delta_{i-1}) / alpha_i,  delta_i = e_i / alpha_i,
+//   eps_i = a_i.
+// Rows hold {eps_i/alpha_i, beta_i/alpha_i, 1/alpha_i, gamma_i, delta_i}.
+sbs_status factor_penta(const double *B, int64_t n, std::vector<PentaRow<double>> &rows, int64_t *bad) {
+    double g1 = 0.0, g2 = 0.0, d1 = 0.0, d2 = 0.0;  // gamma/delta at i-1 and i-2
+    for (int64_t i = 0; i < n; ++i) {
+        const double a = coef(B, 5, n, 0, i), b = coef(B, 5, n, 1, i), c = coef(B, 5, n, 2, i);
+        const double d = coef(B, 5, n, 3, i), e = coef(B, 5, n, 4, i);
+        const double beta = b - a * g2;
+        const double alpha = c - a * d2 - beta * g1;
+        if (!finite_nonzero(alpha)) {
+            *bad = i;
+            return SBS_ERR_ZERO_PIVOT;
+        }
+        const double gamma = (d - beta * d1) / alpha;
+        const double delta = e / alpha;
+        rows[i] = {a / alpha, beta / alpha, 1.0 / alpha, gamma, delta, 0.0, 0.0, 0.0};
+        g2 = g1;
+        g1 = gamma;
+        d2 = d1;
+        d1 = delta;
+    }
+    return SBS_OK;
+}
+
+template <typename Row32, typename Row64>
+Row32 narrow(const Row64 &r);
+template <>
+TriRow<float> narrow(const TriRow<double> &r) {
+    return {(float)r.a_s, (float)r.chat, (float)r.inv, 0.0f};
+}
+template <>
+PentaRow<float> narrow(const PentaRow<double> &r) {
+    return {(float)r.eps_s, (float)r.beta_s, (float)r.inv, (float)r.gamma, (float)r.delta, 0.f, 0.f, 0.f};
+}
+
+template <typename Row64, typename Row32>
+sbs_status upload(sbs_lhs *h, const std::vector<Row64> &r64, const double *B) {
+    const int64_t rows = h->rows;
+    const size_t b64 = sizeof(Row64) * rows, b32 = sizeof(Row32) * rows, bb = sizeof(BandRow) * rows;
+    const size_t total = b64 + b32 + bb;
+    std::vector<unsigned char> host(total, 0);  // padding rows stay zero
+    std::memcpy(host.data(), r64.data(), sizeof(Row64) * h->n);
+    Row32 *p32 = reinterpret_cast<Row32 *>(host.data() + b64);
+    for (int64_t i = 0; i < h->n; ++i) p32[i] = narrow<Row32>(r64[i]);
+    BandRow *pb = reinterpret_cast<BandRow *>(host.data() + b64 + b32);
+    for (int64_t i = 0; i < h->n; ++i)
+        for (int k = 0; k < h->kind; ++k) pb[i].c[k] = coef(B, h->kind, h->n, k, i);
+
+    if (hipGetDevice(&h->device) != hipSuccess) return SBS_ERR_DEVICE;
+    void *dev = nullptr;
+    if (hipMalloc(&dev, total) != hipSuccess) return SBS_ERR_NO_MEMORY;
+    if (hipMemcpy(dev, host.data(), total, hipMemcpyHostToDevice) != hipSuccess) {
+        (void)hipFree(dev);
+        return SBS_ERR_DEVICE;
+    }
+    h->dev = dev;
+    h->fac64 = dev;
+    h->fac32 = static_cast<unsigned char *>(dev) + b64;
+    h->bands = reinterpret_cast<BandRow *>(static_cast<unsigned char *>(dev) + b64 + b32);
+    h->device_bytes = (int64_t)total;
+    return SBS_OK;
+}
+
+bool aligned(const void *p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
+
+}  // namespace
+
+extern "C" {
+
+const char *sbs_status_str(sbs_status s) {
+    switch (s) {
+        case SBS_OK: return "ok";
+        case SBS_ERR_INVALID_ARG: return "invalid argument";
+        case SBS_ERR_ZERO_PIVOT: return "zero or non-finite pivot";
+        case SBS_ERR_NONFINITE: return "non-finite matrix coefficient";
+        case SBS_ERR_DEVICE: return "device error";
+        case SBS_ERR_NO_MEMORY: return "out of memory";
+        case SBS_ERR_BUDGET: return "request exceeds the memory budget";
+        case SBS_ERR_NOT_FOUND: return "not found";
+        case SBS_ERR_TIMEOUT: return "timed out";
+        case SBS_ERR_SHUTDOWN: return "server shutting down";
+    }
+    return "unknown status";
+}
+
+const char *sbs_version(void) { return "sbs 0.1 (gfx950)"; }
+
+sbs_status sbs_factor_shared_lhs(int32_t kind, int64_t n, const double *bands, sbs_handle *out,
+                                 int64_t *bad_row) {
+    int64_t bad = -1;
+    if (bad_row) *bad_row = -1;
+    if (out) *out = nullptr;
+    if (!out || !bands || n < 1 || (kind != SBS_TRI && kind != SBS_PENTA)) return SBS_ERR_INVALID_ARG;
+    if (n > (int64_t(1) << 40)) return SBS_ERR_INVALID_ARG;
+    for (int64_t i = 0; i < n; ++i)
+        for (int k = 0; k < kind; ++k)
+            if (!std::isfinite(coef(bands, kind, n, k, i))) {
+                if (bad_row) *bad_row = i;
+                return SBS_ERR_NONFINITE;
+            }
+    sbs_lhs *h = new (std::nothrow) sbs_lhs();
+    if (!h) return SBS_ERR_NO_MEMORY;
+    h->kind = kind;
+    h->n = n;
+    h->rows = (n + kRowPad - 1) / kRowPad * kRowPad;
+    sbs_status st;
+    try {
+        if (kind == SBS_TRI) {
+            std::vector<TriRow<double>> r(n);
+            st = factor_tri(bands, n, r, &bad);
+            if (st == SBS_OK) st = upload<TriRow<double>, TriRow<float>>(h, r, bands);
+        } else {
+            std::vector<PentaRow<double>> r(n);
+            st = factor_penta(bands, n, r, &bad);
+            if (st == SBS_OK) st = upload<PentaRow<double>, PentaRow<float>>(h, r, bands);
+        }
+    } catch (const std::bad_alloc &) {
+        st = SBS_ERR_NO_MEMORY;
+    }
+    if (st != SBS_OK) {
+        if (bad_row) *bad_row = bad;
+        delete h;
+        return st;
+    }
+    *out = h;
+    return SBS_OK;
+}
+
+sbs_status sbs_release(sbs_handle h) {
+    if (!h) return SBS_OK;
+    sbs_status st = SBS_OK;
+    if (h->dev && hipFree(h->dev) != hipSuccess) st = SBS_ERR_DEVICE;
+    delete h;
+    return st;
+}
+
+sbs_status sbs_handle_info(sbs_handle h, int32_t *kind, int64_t *n, int64_t *device_bytes) {
+    if (!h) return SBS_ERR_INVALID_ARG;
+    if (kind) *kind = h->kind;
+    if (n) *n = h->n;
+    if (device_bytes) *device_bytes = h->device_bytes;
+    return SBS_OK;
+}
+
+sbs_status sbs_solve_batch_variant(sbs_handle h, void *rhs, int64_t m, int32_t dtype, int32_t variant,
+                                   void *stream) {
+    if (!h || m < 0 || (dtype != SBS_F64 && dtype != SBS_F32)) return SBS_ERR_INVALID_ARG;
+    if (variant < SBS_VARIANT_AUTO || variant > SBS_VARIANT_STREAM) return SBS_ERR_INVALID_ARG;
+    if (variant == SBS_VARIANT_RESIDENT && h->n > 64) return SBS_ERR_INVALID_ARG;
+    if (m == 0) return SBS_OK;
+    if (!rhs || !aligned(rhs, dtype == SBS_F64 ? 8 : 4)) return SBS_ERR_INVALID_ARG;
+    if (m > (int64_t)0x7fffffff * kWave) return SBS_ERR_INVALID_ARG;
+    if (variant == SBS_VARIANT_CHUNKED) {
+        const int64_t K = (h->n + 31) / 32;
+        const size_t need = (size_t)K * (h->kind == SBS_TRI ? 1 : 2) * kWave * (dtype == SBS_F64 ? 8 : 4);
+        if (need > 64 * 1024) return SBS_ERR_INVALID_ARG;
+    }
+    const int t = dtype == SBS_F64 ? 0 : 1;
+    hipError_t e = launch_sweep(h, variant, t, t, t, rhs, rhs, m, static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? SBS_OK : SBS_ERR_DEVICE;
+}
+
+sbs_status sbs_solve_batch(sbs_handle h, void *rhs, int64_t m, int32_t dtype, void *stream) {
+    return sbs_solve_batch_variant(h, rhs, m, dtype, SBS_VARIANT_AUTO, stream);
+}
+
+size_t sbs_refined_workspace_bytes(sbs_handle h, int64_t m) {
+    if (!h || m < 0) return 0;
+    // One FP32 residual / correction array of n*m, rounded to 256 bytes.
+    return ((size_t)h->n * (size_t)m * sizeof(float) + 255) / 256 * 256;
+}
+
+sbs_status sbs_solve_batch_refined(sbs_handle h, const float *b, double *x, int64_t m, int32_t sweeps,
+                                   void *work, size_t work_bytes, void *stream) {
+    if (!h || m < 0 || sweeps < 0 || sweeps > 8) return SBS_ERR_INVALID_ARG;
+    if (m == 0) return SBS_OK;
+    if (!b || !x || !work || work_bytes < sbs_refined_workspace_bytes(h, m)) return SBS_ERR_INVALID_ARG;
+    if (!aligned(b, 8) || !aligned(x, 16) || !aligned(work, 8)) return SBS_ERR_INVALID_ARG;
+    const size_t nb = (size_t)h->n * (size_t)m;
+    const char *bx = reinterpret_cast<const char *>(x), *bbp = reinterpret_cast<const char *>(b);
+    if (bx < bbp + nb * 4 && bbp < bx + nb * 8) return SBS_ERR_INVALID_ARG;  // b and x overlap
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    float *r = static_cast<float *>(work);
+    // x0 = FP32 solve of b, written as FP64.
+    hipError_t e = launch_sweep(h, SBS_VARIANT_AUTO, 1, 1, 0, b, x, m, s);
+    for (int k = 0; k < sweeps && e == hipSuccess; ++k) {
+        // r = fl32(b - A x)   (on later passes fused with x += delta)
+        e = launch_refine_step(h, k == 0 ? 0 : 1, b, x, r, r, m, s);
+        if (e == hipSuccess) e = launch_sweep(h, SBS_VARIANT_AUTO, 1, 1, 1, r, r, m, s);  // delta
+    }
+    if (e == hipSuccess && sweeps > 0) e = launch_refine_step(h, 2, b, x, r, nullptr, m, s);  // x += delta
+    return e == hipSuccess ? SBS_OK : SBS_ERR_DEVICE;
+}
+
+sbs_status sbs_transpose(const void *src, void *dst, int64_t rows, int64_t cols, int32_t dtype, void *stream) {
+    if (rows < 0 || cols < 0 || (dtype != SBS_F64 && dtype != SBS_F32)) return SBS_ERR_INVALID_ARG;
+    if (rows == 0 || cols == 0) return SBS_OK;
+    if (!src || !dst) return SBS_ERR_INVALID_ARG;
+    const size_t eb = dtype == SBS_F64 ? 8 : 4;
+    const size_t bytes = (size_t)rows * (size_t)cols * eb;
+    const char *s = static_cast<const char *>(src), *d = static_cast<const char *>(dst);
+    if (s < d + bytes && d < s + bytes) return SBS_ERR_INVALID_ARG;
+    if (!aligned(src, eb) || !aligned(dst, eb)) return SBS_ERR_INVALID_ARG;
+    hipError_t e = launch_transpose(src, dst, rows, cols, (int)eb, static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? SBS_OK : SBS_ERR_DEVICE;
+}
+
+sbs_status sbs_adi_step(sbs_handle hy, sbs_handle hx, double *grid, double *work, int64_t ny, int64_t nx,
+                        void *stream) {
+    if (!hy || !hx || ny < 1 || nx < 1 || hy->n != ny || hx->n != nx) return SBS_ERR_INVALID_ARG;
+    if (!grid || !work) return SBS_ERR_INVALID_ARG;
+    sbs_status st = sbs_solve_batch(hy, grid, nx, SBS_F64, stream);          // along y
+    if (st == SBS_OK) st = sbs_transpose(grid, work, ny, nx, SBS_F64, stream);  // (ny, nx) -> (nx, ny)
+    if (st == SBS_OK) st = sbs_solve_batch(hx, work, ny, SBS_F64, stream);      // along x
+    if (st == SBS_OK) st = sbs_transpose(work, grid, nx, ny, SBS_F64, stream);  // back
+    return st;
+}
+
+}  // extern "C"

@@ -1,0 +1,101 @@
+// Internal declarations shared by the host library and the kernel launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "sbs.h"
+
+namespace sbs {
+
+// Factor rows, one per matrix row, laid out so that a wave reads a whole row
+// with one wave-uniform scalar load (32 B tri / 64 B penta in FP64).
+//
+// Tridiagonal (Section 3.1): with den_i = b_i - a_i chat_{i-1},
+//   forward   y_i = d_i / den_i - (a_i / den_i) y_{i-1}
+//   backward  x_i = y_i - chat_i x_{i+1}
+// so a row stores { a_i / den_i, chat_i, 1 / den_i }.
+template <typename T>
+struct alignas(4 * sizeof(T)) TriRow {
+    T a_s, chat, inv, pad;
+};
+
+// Pentadiagonal (Section 4.1), A = L R:
+//   forward   g_i = f_i / alpha_i - (eps_i / alpha_i) g_{i-2} - (beta_i / alpha_i) g_{i-1}
+//   backward  x_i = g_i - gamma_i x_{i+1} - delta_i x_{i+2}
+// so a row stores { eps_i / alpha_i, beta_i / alpha_i, 1 / alpha_i, gamma_i, delta_i }.
+template <typename T>
+struct alignas(8 * sizeof(T)) PentaRow {
+    T eps_s, beta_s, inv, gamma, delta, p0, p1, p2;
+};
+
+// Original coefficients of row i, for the FP64 residual b - A x:
+// tri {a_i, b_i, c_i, 0}; penta {a_i, b_i, c_i, d_i, e_i, 0, 0, 0}.
+// Coefficients outside the matrix are stored as 0.
+struct alignas(64) BandRow {
+    double c[8];
+};
+
+constexpr int kWave = 64;       // lanes per wavefront on gfx950
+constexpr int kRowPad = 64;     // factor rows are padded with zero rows to a multiple of this
+
+}  // namespace sbs
+
+struct sbs_lhs {
+    int32_t kind = 0;
+    int64_t n = 0;
+    int64_t rows = 0;           // n rounded up to kRowPad
+    void *dev = nullptr;        // one allocation holding the three arrays below
+    void *fac64 = nullptr;      // TriRow<double>[rows] or PentaRow<double>[rows]
+    void *fac32 = nullptr;      // TriRow<float>[rows]  or PentaRow<float>[rows]
+    sbs::BandRow *bands = nullptr;  // BandRow[rows]
+    int64_t device_bytes = 0;
+    int device = 0;
+};
+
+namespace sbs {
+
+struct SweepArgs {
+    const sbs_lhs *h;
+    const void *in;
+    void *out;
+    int64_t m;
+    hipStream_t stream;
+};
+
+// Plain solve (in == out allowed).  tin/tout/tc: 0 = f64, 1 = f32.
+hipError_t launch_sweep(const sbs_lhs *h, int variant, int tc, int tin, int tout,
+                        const void *in, void *out, int64_t m, hipStream_t stream);
+
+// Residual / update kernels of the mixed-precision driver.
+//  mode 0: r = fl32(b - A x)
+//  mode 1: x += delta; r = fl32(b - A x)
+//  mode 2: x += delta
+hipError_t launch_refine_step(const sbs_lhs *h, int mode, const float *b, double *x,
+                              const float *delta, float *r, int64_t m, hipStream_t stream);
+
+hipError_t launch_transpose(const void *src, void *dst, int64_t rows, int64_t cols,
+                            int elem_bytes, hipStream_t stream);
+
+// Which variant AUTO picks, and the checkpoint bytes per wave it needs.
+int choose_variant(const sbs_lhs *h, int tc);
+
+// Serving: heterogeneous tile launches (see server.cpp).
+struct Tile {
+    const void *fac;            // factor rows of this tile's matrix (type per dtype)
+    const BandRow *bands;       // original bands (mixed precision only)
+    const void *in;             // rhs of the request
+    double *x;                  // FP64 result of the request
+    float *scratch;             // FP32 residual scratch (mixed precision only)
+    int64_t n, m, col0;         // system range [col0, col0 + 64) of the request
+    int32_t kind, fp32;
+};
+
+// Runs tiles [0, ntiles), all of one kind and precision, with `grid`
+// persistent waves; *dev_counter must be 0 when the kernel starts.
+hipError_t launch_tiles(int kind, int fp32, const Tile *dev_tiles, int ntiles, int *dev_counter, int grid,
+                        hipStream_t stream);
+
+}  // namespace sbs

@@ -1,0 +1,611 @@
+// HIP kernels for gfx950: the per-system forward / backward sweeps, the
+// mixed-precision residual and update passes, and the tiled transpose.
+//
+// Execution model (Section 2 of the paper, re-done for CDNA4): one lane of a
+// 64-wide wavefront owns one system.  Row i of the interleaved right-hand
+// sides is contiguous across the wave's 64 systems, so each row is one
+// coalesced 512-byte (FP64) access; the shared factor row i is the same for
+// every lane and is read with wave-uniform scalar loads.  Each workgroup is
+// exactly one wavefront.
+#include "internal.h"
+
+namespace sbs {
+namespace {
+
+enum { MODE_RESIDENT = 1, MODE_CHUNKED = 2, MODE_STREAM = 3 };
+
+// ---------------------------------------------------------------------------
+// The two recurrences.  Each forward step carries the previous results of
+// the system (one for tri, two for penta); each backward step carries the
+// next solution values.
+
+template <int KIND, typename T>
+struct Rec;
+
+template <typename T>
+struct Rec<SBS_TRI, T> {
+    using Row = TriRow<T>;
+    static constexpr int S = 1;  // values a checkpoint holds
+    struct Fwd {
+        T y1 = T(0);
+    };
+    struct Bwd {
+        T x1 = T(0);
+    };
+    // y_i = d_i / den_i - (a_i / den_i) y_{i-1}          (Section 3.1, forward)
+    static __device__ __forceinline__ T fwd(const Row *__restrict__ f, int i, T d, Fwd &s) {
+        const T y = fma(-f[i].a_s, s.y1, d * f[i].inv);
+        s.y1 = y;
+        return y;
+    }
+    // x_i = y_i - chat_i x_{i+1}                          (Section 3.1, backward)
+    static __device__ __forceinline__ T bwd(const Row *__restrict__ f, int i, T y, Bwd &s) {
+        const T x = fma(-f[i].chat, s.x1, y);
+        s.x1 = x;
+        return x;
+    }
+    static __device__ __forceinline__ void put(const Fwd &s, T *p) { p[0] = s.y1; }
+    static __device__ __forceinline__ void get(Fwd &s, const T *p) { s.y1 = p[0]; }
+};
+
+template <typename T>
+struct Rec<SBS_PENTA, T> {
+    using Row = PentaRow<T>;
+    static constexpr int S = 2;
+    struct Fwd {
+        T g2 = T(0), g1 = T(0);
+    };
+    struct Bwd {
+        T x1 = T(0), x2 = T(0);
+    };
+    // g_i = (f_i - eps_i g_{i-2} - beta_i g_{i-1}) / alpha_i   (Section 4.1, L g = f)
+    static __device__ __forceinline__ T fwd(const Row *__restrict__ f, int i, T v, Fwd &s) {
+        const Row &r = f[i];
+        const T g = fma(-r.beta_s, s.g1, fma(-r.eps_s, s.g2, v * r.inv));
+        s.g2 = s.g1;
+        s.g1 = g;
+        return g;
+    }
+    // x_i = g_i - gamma_i x_{i+1} - delta_i x_{i+2}            (Section 4.1, R x = g)
+    static __device__ __forceinline__ T bwd(const Row *__restrict__ f, int i, T g, Bwd &s) {
+        const Row &r = f[i];
+        const T x = fma(-r.gamma, s.x1, fma(-r.delta, s.x2, g));
+        s.x2 = s.x1;
+        s.x1 = x;
+        return x;
+    }
+    static __device__ __forceinline__ void put(const Fwd &s, T *p) {
+        p[0] = s.g2;
+        p[kWave] = s.g1;
+    }
+    static __device__ __forceinline__ void get(Fwd &s, const T *p) {
+        s.g2 = p[0];
+        s.g1 = p[kWave];
+    }
+};
+
+// Addressing.  Row r of a wave's 64 columns starts at base + r * rs bytes
+// (`base` is the wave's first system, uniform; rs = m * element size); a lane
+// adds its own 32-bit byte offset `lo`.  Walking rows by adding rs to a
+// uniform pointer keeps every address a scalar base plus a vector offset.
+//
+// Lanes past the last system (m not a multiple of 64) take the offset of the
+// last real system: they read its column, compute bit-identical values and
+// store them to the same addresses in the same instructions, which is
+// harmless and avoids masking every access.
+template <typename E>
+__device__ __forceinline__ E ld(const char *p, uint32_t lo) {
+    return *reinterpret_cast<const E *>(p + lo);
+}
+template <typename E>
+__device__ __forceinline__ void st(char *p, uint32_t lo, E v) {
+    *reinterpret_cast<E *>(p + lo) = v;
+}
+
+template <typename T, typename Tin, int L>
+__device__ __forceinline__ void load_rows(T (&buf)[L], const char *base, uint32_t lo, int r0,
+                                          int n, int64_t rs) {
+    const char *p = base + r0 * rs;
+    if (r0 + L <= n) {
+#pragma unroll
+        for (int t = 0; t < L; ++t) {
+            buf[t] = static_cast<T>(ld<Tin>(p, lo));
+            p += rs;
+        }
+    } else {
+#pragma unroll
+        for (int t = 0; t < L; ++t) {
+            buf[t] = (r0 + t < n) ? static_cast<T>(ld<Tin>(p, lo)) : T(0);
+            p += rs;
+        }
+    }
+}
+
+template <typename T, typename Tout, int L>
+__device__ __forceinline__ void store_rows(const T (&buf)[L], char *base, uint32_t lo, int r0,
+                                           int n, int64_t rs) {
+    char *p = base + r0 * rs;
+#pragma unroll
+    for (int t = 0; t < L; ++t) {
+        if (r0 + t < n) st<Tout>(p, lo, static_cast<Tout>(buf[t]));
+        p += rs;
+    }
+}
+
+// Backward sweep over one chunk held in registers, writing the solution.
+template <int KIND, typename T, typename Tout, int L>
+__device__ __forceinline__ void back_chunk(const typename Rec<KIND, T>::Row *__restrict__ fac,
+                                           const T (&buf)[L], typename Rec<KIND, T>::Bwd &bs,
+                                           char *base, uint32_t lo, int r0, int n,
+                                           int64_t rs) {
+    using R = Rec<KIND, T>;
+    char *p = base + (r0 + L - 1) * rs;
+    if (r0 + L <= n) {
+#pragma unroll
+        for (int t = L - 1; t >= 0; --t) {
+            const T x = R::bwd(fac, r0 + t, buf[t], bs);
+            st<Tout>(p, lo, static_cast<Tout>(x));
+            p -= rs;
+        }
+    } else {
+        // Rows at or beyond n meet zero factor rows and a zero input, so
+        // they produce exact zeros and leave the carried values at zero.
+#pragma unroll
+        for (int t = L - 1; t >= 0; --t) {
+            const T x = R::bwd(fac, r0 + t, buf[t], bs);
+            if (r0 + t < n) st<Tout>(p, lo, static_cast<Tout>(x));
+            p -= rs;
+        }
+    }
+}
+
+template <int KIND, typename T, int L>
+__device__ __forceinline__ void fwd_chunk(const typename Rec<KIND, T>::Row *__restrict__ fac,
+                                          T (&buf)[L], typename Rec<KIND, T>::Fwd &st,
+                                          int r0) {
+    using R = Rec<KIND, T>;
+#pragma unroll
+    for (int t = 0; t < L; ++t) buf[t] = R::fwd(fac, r0 + t, buf[t], st);
+}
+
+// ---------------------------------------------------------------------------
+// One wave solves 64 systems.
+//
+//  RESIDENT (n <= L): the whole column stays in registers; every right-hand
+//    side crosses HBM once in and once out.
+//  CHUNKED: the forward sweep stores only the carried values at the start of
+//    every L-row chunk (in LDS) and keeps the last chunk in registers.  The
+//    backward sweep walks the chunks from last to first, re-reads a chunk's
+//    right-hand side, recomputes its forward values from the checkpoint and
+//    back-substitutes.  In place is safe: a chunk is read before it is
+//    written and lower chunks are untouched until their turn.
+//  STREAM: the forward values of every chunk but the last are written over
+//    the output and read back by the backward sweep.
+//
+// Loads of the next chunk are issued before the current chunk is computed,
+// so L rows (L * 512 B per wave in FP64) are in flight while it computes.
+// The body works on the wave's systems j0 .. j0+63 of an (n, m) array; `ck`
+// is the wave's LDS checkpoint area (CHUNKED only: K * S * 64 values).
+template <int KIND, typename T, typename Tin, typename Tout, int L, int MODE>
+__device__ __forceinline__ void sweep_wave(const typename Rec<KIND, T>::Row *__restrict__ fac, int n,
+                                           const Tin *in, Tout *out, int64_t m, int64_t j0, T *ck) {
+    using R = Rec<KIND, T>;
+    const int lane = threadIdx.x;
+    const int jl = (j0 + lane < m) ? lane : (int)(m - 1 - j0);
+    const char *bin = reinterpret_cast<const char *>(in + j0);
+    char *bout = reinterpret_cast<char *>(out + j0);
+    const uint32_t lin = (uint32_t)jl * sizeof(Tin), lout = (uint32_t)jl * sizeof(Tout);
+    const int64_t rsi = m * (int64_t)sizeof(Tin), rso = m * (int64_t)sizeof(Tout);
+    const int K = (n + L - 1) / L;
+    T *ckp = ck + lane;
+
+    T cur[L];
+    typename R::Fwd st;
+    load_rows<T, Tin, L>(cur, bin, lin, 0, n, rsi);
+
+    if constexpr (MODE == MODE_RESIDENT) {
+        fwd_chunk<KIND, T, L>(fac, cur, st, 0);
+        typename R::Bwd bs;
+        back_chunk<KIND, T, Tout, L>(fac, cur, bs, bout, lout, 0, n, rso);
+        return;
+    } else {
+        T nxt[L];
+        // Forward sweep.
+        for (int k = 0; k < K; ++k) {
+            if constexpr (MODE == MODE_CHUNKED) R::put(st, ckp + k * (R::S * kWave));
+            const bool more = k + 1 < K;
+            if (more) load_rows<T, Tin, L>(nxt, bin, lin, (k + 1) * L, n, rsi);
+            fwd_chunk<KIND, T, L>(fac, cur, st, k * L);
+            if (more) {
+                if constexpr (MODE == MODE_STREAM) store_rows<T, Tout, L>(cur, bout, lout, k * L, n, rso);
+#pragma unroll
+                for (int t = 0; t < L; ++t) cur[t] = nxt[t];
+            }
+        }
+        // Backward sweep; cur holds the forward values of the last chunk.
+        typename R::Bwd bs;
+        if (K >= 2) {
+            if constexpr (MODE == MODE_CHUNKED)
+                load_rows<T, Tin, L>(nxt, bin, lin, (K - 2) * L, n, rsi);
+            else
+                load_rows<T, Tout, L>(nxt, bout, lout, (K - 2) * L, n, rso);
+        }
+        back_chunk<KIND, T, Tout, L>(fac, cur, bs, bout, lout, (K - 1) * L, n, rso);
+        for (int k = K - 2; k >= 0; --k) {
+#pragma unroll
+            for (int t = 0; t < L; ++t) cur[t] = nxt[t];
+            if (k >= 1) {
+                if constexpr (MODE == MODE_CHUNKED)
+                    load_rows<T, Tin, L>(nxt, bin, lin, (k - 1) * L, n, rsi);
+                else
+                    load_rows<T, Tout, L>(nxt, bout, lout, (k - 1) * L, n, rso);
+            }
+            if constexpr (MODE == MODE_CHUNKED) {
+                R::get(st, ckp + k * (R::S * kWave));
+                fwd_chunk<KIND, T, L>(fac, cur, st, k * L);
+            }
+            back_chunk<KIND, T, Tout, L>(fac, cur, bs, bout, lout, k * L, n, rso);
+        }
+    }
+}
+
+template <int KIND, typename T, typename Tin, typename Tout, int L, int MODE>
+__global__ __launch_bounds__(kWave) void k_sweep(const typename Rec<KIND, T>::Row *__restrict__ fac,
+                                                 int n, const Tin *in, Tout *out, int64_t m) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    sweep_wave<KIND, T, Tin, Tout, L, MODE>(fac, n, in, out, m, (int64_t)blockIdx.x * kWave,
+                                            reinterpret_cast<T *>(smem));
+}
+
+// ---------------------------------------------------------------------------
+// Mixed-precision passes.  Lane per system again; a lane walks its column
+// with a window of 2H+1 solution values (H = 1 tri, 2 penta).
+//  MODE 0: r_i = fl32(b_i - (A x)_i)
+//  MODE 1: x_i += delta_i for every row, then r from the updated x
+// (A x)_i is summed left to right over the row's coefficients, in FP64.
+template <int KIND, int MODE>
+__device__ __forceinline__ void residual_wave(const BandRow *__restrict__ bands, int64_t n,
+                                              const float *__restrict__ b, double *__restrict__ x,
+                                              const float *dl, float *r, int64_t m, int64_t j0) {
+    // dl and r may be the same buffer: delta_i is read (when row i enters the
+    // window) before the residual of row i, which depends on it, is written.
+    constexpr int H = KIND / 2;
+    constexpr int U = 8;  // rows per load batch
+    const int lane = threadIdx.x;
+    const int jl = (j0 + lane < m) ? lane : (int)(m - 1 - j0);
+    const uint32_t l4 = (uint32_t)jl * 4, l8 = (uint32_t)jl * 8;
+    const char *pb = reinterpret_cast<const char *>(b + j0);
+    char *px = reinterpret_cast<char *>(x + j0);
+    const char *pd = reinterpret_cast<const char *>(dl + j0);
+    char *pr = reinterpret_cast<char *>(r + j0);
+    const int64_t rs4 = m * 4, rs8 = m * 8;
+
+    // w[0..2H] holds x_{i-H} .. x_{i+H} (updated when MODE == 1), 0 outside.
+    double w[2 * H + 1];
+#pragma unroll
+    for (int q = 0; q < 2 * H + 1; ++q) w[q] = 0.0;
+#pragma unroll
+    for (int q = 0; q < H; ++q) {  // rows 0 .. H-1 enter the window
+        double v = 0.0;
+        if (q < n) {
+            v = ld<double>(px + q * rs8, l8);
+            if constexpr (MODE == 1) {
+                v += (double)ld<float>(pd + q * rs4, l4);
+                st<double>(px + q * rs8, l8, v);
+            }
+        }
+        w[H + 1 + q] = v;  // shifted into place before row 0 is summed
+    }
+    for (int64_t i0 = 0; i0 < n; i0 += U) {
+        double xa[U];
+        float bv[U], dv[U];
+        const char *qx = px + (i0 + H) * rs8;
+        const char *qd = pd + (i0 + H) * rs4;
+        const char *qb = pb + i0 * rs4;
+#pragma unroll
+        for (int t = 0; t < U; ++t) {
+            const bool in_a = i0 + t + H < n;  // row entering the window exists
+            xa[t] = in_a ? ld<double>(qx, l8) : 0.0;
+            if constexpr (MODE == 1) dv[t] = in_a ? ld<float>(qd, l4) : 0.0f;
+            bv[t] = (i0 + t < n) ? ld<float>(qb, l4) : 0.0f;
+            qx += rs8;
+            qd += rs4;
+            qb += rs4;
+        }
+        char *sx = px + (i0 + H) * rs8;
+        char *sr = pr + i0 * rs4;
+#pragma unroll
+        for (int t = 0; t < U; ++t) {
+            const int64_t i = i0 + t;
+            double v = xa[t];
+            if constexpr (MODE == 1) {
+                v += (double)dv[t];
+                if (i + H < n) st<double>(sx, l8, v);
+            }
+#pragma unroll
+            for (int q = 0; q < 2 * H; ++q) w[q] = w[q + 1];
+            w[2 * H] = v;
+            if (i < n) {
+                const BandRow &row = bands[i];
+                double ax = row.c[0] * w[0];
+#pragma unroll
+                for (int q = 1; q < 2 * H + 1; ++q) ax = fma(row.c[q], w[q], ax);
+                st<float>(sr, l4, (float)((double)bv[t] - ax));
+            }
+            sx += rs8;
+            sr += rs4;
+        }
+    }
+}
+
+template <int KIND, int MODE>
+__global__ __launch_bounds__(kWave) void k_residual(const BandRow *__restrict__ bands, int64_t n,
+                                                    const float *__restrict__ b, double *__restrict__ x,
+                                                    const float *dl, float *r, int64_t m) {
+    residual_wave<KIND, MODE>(bands, n, b, x, dl, r, m, (int64_t)blockIdx.x * kWave);
+}
+
+// x += delta over one wave's 64 systems (final correction inside a tile).
+__device__ __forceinline__ void update_wave(double *x, const float *dl, int64_t n, int64_t m, int64_t j0) {
+    const int lane = threadIdx.x;
+    const int jl = (j0 + lane < m) ? lane : (int)(m - 1 - j0);
+    char *px = reinterpret_cast<char *>(x + j0);
+    const char *pd = reinterpret_cast<const char *>(dl + j0);
+    const uint32_t l4 = (uint32_t)jl * 4, l8 = (uint32_t)jl * 8;
+    const int64_t rs4 = m * 4, rs8 = m * 8;
+    for (int64_t i = 0; i < n; ++i) {
+        const double v = ld<double>(px, l8) + (double)ld<float>(pd, l4);
+        st<double>(px, l8, v);
+        px += rs8;
+        pd += rs4;
+    }
+}
+
+// x += delta, elementwise over the whole interleaved array (final correction).
+__global__ __launch_bounds__(256) void k_update(double *__restrict__ x, const float *__restrict__ dl,
+                                                int64_t total) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x * 2;
+    for (int64_t e = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 2; e < total; e += stride) {
+        if (e + 1 < total) {
+            double2 v = *reinterpret_cast<double2 *>(x + e);
+            const float2 d = *reinterpret_cast<const float2 *>(dl + e);
+            v.x += (double)d.x;
+            v.y += (double)d.y;
+            *reinterpret_cast<double2 *>(x + e) = v;
+        } else {
+            x[e] += (double)dl[e];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Serving: one launch runs many requests (any matrix, n, m, precision).  The
+// host cuts every request into tiles of 64 systems; each wave repeatedly
+// takes the next tile from a counter and runs that tile's whole solve --
+// for FP32 requests the FP32 solve, two residual/correction rounds and the
+// final update, all on the tile's own columns -- with the same sweep and
+// residual bodies as the plain entry points, so a request's result is
+// bit-identical whether it runs alone or in a mix.  The loop ends when the
+// counter passes the last tile, so every wave exits.
+constexpr int kTileCk = 4096;  // doubles of LDS checkpoint space per wave (32 KB)
+
+template <int KIND>
+__device__ __forceinline__ void run_tile_f64(const Tile &t, double *ck) {
+    const int n = (int)t.n;
+    constexpr int S = Rec<KIND, double>::S;
+    using Row = typename Rec<KIND, double>::Row;
+    const Row *fac = reinterpret_cast<const Row *>(t.fac);
+    const double *in = reinterpret_cast<const double *>(t.in);
+    if (((n + 31) / 32) * S * kWave <= kTileCk)
+        sweep_wave<KIND, double, double, double, 32, MODE_CHUNKED>(fac, n, in, t.x, t.m, t.col0, ck);
+    else
+        sweep_wave<KIND, double, double, double, 32, MODE_STREAM>(fac, n, in, t.x, t.m, t.col0, ck);
+}
+
+// The phases of an FP32 tile are kept out of line so that each gets its own
+// register allocation instead of one allocation spanning all five.
+template <int KIND, typename Tout, int MODE>
+__device__ __noinline__ void tile_sweep_f32(const typename Rec<KIND, float>::Row *fac, int n, const float *in,
+                                            Tout *out, int64_t m, int64_t j0, float *ck) {
+    sweep_wave<KIND, float, float, Tout, 32, MODE>(fac, n, in, out, m, j0, ck);
+}
+
+template <int KIND, int MODE>
+__device__ __noinline__ void tile_residual(const BandRow *bands, int64_t n, const float *b, double *x,
+                                           float *r, int64_t m, int64_t j0) {
+    residual_wave<KIND, MODE>(bands, n, b, x, r, r, m, j0);
+}
+
+template <int KIND>
+__device__ __forceinline__ void run_tile_f32(const Tile &t, double *ck) {
+    const int n = (int)t.n;
+    constexpr int S = Rec<KIND, float>::S;
+    using Row = typename Rec<KIND, float>::Row;
+    const Row *fac = reinterpret_cast<const Row *>(t.fac);
+    const float *b = reinterpret_cast<const float *>(t.in);
+    float *ckf = reinterpret_cast<float *>(ck);
+    const bool chunk = ((n + 31) / 32) * S * kWave <= 2 * kTileCk;
+    if (chunk)
+        tile_sweep_f32<KIND, double, MODE_CHUNKED>(fac, n, b, t.x, t.m, t.col0, ckf);
+    else
+        tile_sweep_f32<KIND, double, MODE_STREAM>(fac, n, b, t.x, t.m, t.col0, ckf);
+    for (int pass = 0; pass < 2; ++pass) {
+        if (pass == 0)
+            tile_residual<KIND, 0>(t.bands, n, b, t.x, t.scratch, t.m, t.col0);
+        else
+            tile_residual<KIND, 1>(t.bands, n, b, t.x, t.scratch, t.m, t.col0);
+        if (chunk)
+            tile_sweep_f32<KIND, float, MODE_CHUNKED>(fac, n, t.scratch, t.scratch, t.m, t.col0, ckf);
+        else
+            tile_sweep_f32<KIND, float, MODE_STREAM>(fac, n, t.scratch, t.scratch, t.m, t.col0, ckf);
+    }
+    update_wave(t.x, t.scratch, n, t.m, t.col0);
+}
+
+// One kernel per (kind, precision) group of a launch's tiles.
+template <int KIND, int FP32>
+__global__ __launch_bounds__(kWave) void k_tiles(const Tile *__restrict__ tiles, int ntiles, int *counter) {
+    __shared__ __align__(16) double ck[kTileCk];
+    for (;;) {
+        int t = 0;
+        if (threadIdx.x == 0) t = atomicAdd(counter, 1);
+        t = __builtin_amdgcn_readfirstlane(t);
+        if (t >= ntiles) break;
+        const Tile tl = tiles[t];
+        if constexpr (FP32)
+            run_tile_f32<KIND>(tl, ck);
+        else
+            run_tile_f64<KIND>(tl, ck);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// dst[c*rows + r] = src[r*cols + c] through a padded 64 x 64 LDS tile.
+// Elements move as raw integers, so the copy is bit-exact.
+template <typename E>
+__global__ __launch_bounds__(256) void k_transpose(const E *__restrict__ src, E *__restrict__ dst,
+                                                   int64_t rows, int64_t cols, int64_t tiles_c) {
+    __shared__ E tile[64][65];
+    const int64_t tr = blockIdx.x / tiles_c, tc = blockIdx.x % tiles_c;
+    const int64_t r0 = tr * 64, c0 = tc * 64;
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        const int k = ty + 4 * q;
+        const int64_t r = r0 + k, c = c0 + tx;
+        if (r < rows && c < cols) tile[k][tx] = src[r * cols + c];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        const int k = ty + 4 * q;
+        const int64_t c = c0 + k, r = r0 + tx;
+        if (c < cols && r < rows) dst[c * rows + r] = tile[tx][k];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Launch helpers.
+
+constexpr size_t kMaxLdsBytes = 64 * 1024;
+
+template <int KIND, typename T, typename Tin, typename Tout, int L, int MODE>
+hipError_t go(const sbs_lhs *h, const void *fac, const void *in, void *out, int64_t m,
+              hipStream_t s) {
+    using R = Rec<KIND, T>;
+    const int64_t blocks = (m + kWave - 1) / kWave;
+    const int64_t K = (h->n + L - 1) / L;
+    const size_t lds = (MODE == MODE_CHUNKED) ? (size_t)K * R::S * kWave * sizeof(T) : 0;
+    if (lds > kMaxLdsBytes) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_sweep<KIND, T, Tin, Tout, L, MODE>), dim3((unsigned)blocks), dim3(kWave),
+                       lds, s, reinterpret_cast<const typename R::Row *>(fac), (int)h->n,
+                       reinterpret_cast<const Tin *>(in), reinterpret_cast<Tout *>(out), m);
+    return hipGetLastError();
+}
+
+template <int KIND, typename T, typename Tin, typename Tout>
+hipError_t dispatch_mode(const sbs_lhs *h, int mode, const void *fac, const void *in, void *out,
+                         int64_t m, hipStream_t s) {
+    const int64_t n = h->n;
+    if (mode == SBS_VARIANT_RESIDENT) {
+        if (n <= 8) return go<KIND, T, Tin, Tout, 8, MODE_RESIDENT>(h, fac, in, out, m, s);
+        if (n <= 16) return go<KIND, T, Tin, Tout, 16, MODE_RESIDENT>(h, fac, in, out, m, s);
+        if (n <= 32) return go<KIND, T, Tin, Tout, 32, MODE_RESIDENT>(h, fac, in, out, m, s);
+        if (n <= 64) return go<KIND, T, Tin, Tout, 64, MODE_RESIDENT>(h, fac, in, out, m, s);
+        return hipErrorInvalidValue;
+    }
+    if (mode == SBS_VARIANT_CHUNKED) return go<KIND, T, Tin, Tout, 32, MODE_CHUNKED>(h, fac, in, out, m, s);
+    return go<KIND, T, Tin, Tout, 32, MODE_STREAM>(h, fac, in, out, m, s);
+}
+
+template <typename T, typename Tin, typename Tout>
+hipError_t dispatch_kind(const sbs_lhs *h, int mode, const void *fac, const void *in, void *out,
+                         int64_t m, hipStream_t s) {
+    if (h->kind == SBS_TRI) return dispatch_mode<SBS_TRI, T, Tin, Tout>(h, mode, fac, in, out, m, s);
+    return dispatch_mode<SBS_PENTA, T, Tin, Tout>(h, mode, fac, in, out, m, s);
+}
+
+}  // namespace
+
+int choose_variant(const sbs_lhs *h, int tc) {
+    if (h->n <= 64) return SBS_VARIANT_RESIDENT;
+    const size_t elem = tc == 0 ? 8 : 4;
+    const int S = h->kind == SBS_TRI ? 1 : 2;
+    const int64_t K = (h->n + 31) / 32;
+    if ((size_t)K * S * kWave * elem <= kMaxLdsBytes) return SBS_VARIANT_CHUNKED;
+    return SBS_VARIANT_STREAM;
+}
+
+hipError_t launch_sweep(const sbs_lhs *h, int variant, int tc, int tin, int tout, const void *in,
+                        void *out, int64_t m, hipStream_t stream) {
+    if (m <= 0) return hipSuccess;
+    const int mode = variant == SBS_VARIANT_AUTO ? choose_variant(h, tc) : variant;
+    if (tc == 0 && tin == 0 && tout == 0)
+        return dispatch_kind<double, double, double>(h, mode, h->fac64, in, out, m, stream);
+    if (tc == 1 && tin == 1 && tout == 1)
+        return dispatch_kind<float, float, float>(h, mode, h->fac32, in, out, m, stream);
+    if (tc == 1 && tin == 1 && tout == 0)
+        return dispatch_kind<float, float, double>(h, mode, h->fac32, in, out, m, stream);
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_refine_step(const sbs_lhs *h, int mode, const float *b, double *x,
+                              const float *delta, float *r, int64_t m, hipStream_t stream) {
+    if (m <= 0) return hipSuccess;
+    if (mode == 2) {
+        const int64_t total = h->n * m;
+        int64_t blocks = (total / 2 + 255) / 256;
+        if (blocks > 65536) blocks = 65536;
+        if (blocks < 1) blocks = 1;
+        hipLaunchKernelGGL(k_update, dim3((unsigned)blocks), dim3(256), 0, stream, x, delta, total);
+        return hipGetLastError();
+    }
+    const dim3 grid((unsigned)((m + kWave - 1) / kWave));
+    if (h->kind == SBS_TRI) {
+        if (mode == 0)
+            hipLaunchKernelGGL((k_residual<SBS_TRI, 0>), grid, dim3(kWave), 0, stream, h->bands, h->n, b, x, delta, r, m);
+        else
+            hipLaunchKernelGGL((k_residual<SBS_TRI, 1>), grid, dim3(kWave), 0, stream, h->bands, h->n, b, x, delta, r, m);
+    } else {
+        if (mode == 0)
+            hipLaunchKernelGGL((k_residual<SBS_PENTA, 0>), grid, dim3(kWave), 0, stream, h->bands, h->n, b, x, delta, r, m);
+        else
+            hipLaunchKernelGGL((k_residual<SBS_PENTA, 1>), grid, dim3(kWave), 0, stream, h->bands, h->n, b, x, delta, r, m);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_tiles(int kind, int fp32, const Tile *dev_tiles, int ntiles, int *dev_counter, int grid,
+                        hipStream_t stream) {
+    if (ntiles <= 0) return hipSuccess;
+    if (grid > ntiles) grid = ntiles;
+    const dim3 g((unsigned)grid), b(kWave);
+    if (kind == SBS_TRI && !fp32)
+        hipLaunchKernelGGL((k_tiles<SBS_TRI, 0>), g, b, 0, stream, dev_tiles, ntiles, dev_counter);
+    else if (kind == SBS_TRI)
+        hipLaunchKernelGGL((k_tiles<SBS_TRI, 1>), g, b, 0, stream, dev_tiles, ntiles, dev_counter);
+    else if (!fp32)
+        hipLaunchKernelGGL((k_tiles<SBS_PENTA, 0>), g, b, 0, stream, dev_tiles, ntiles, dev_counter);
+    else
+        hipLaunchKernelGGL((k_tiles<SBS_PENTA, 1>), g, b, 0, stream, dev_tiles, ntiles, dev_counter);
+    return hipGetLastError();
+}
+
+hipError_t launch_transpose(const void *src, void *dst, int64_t rows, int64_t cols, int elem_bytes,
+                            hipStream_t stream) {
+    if (rows <= 0 || cols <= 0) return hipSuccess;
+    const int64_t tiles_c = (cols + 63) / 64, tiles_r = (rows + 63) / 64;
+    const int64_t blocks = tiles_c * tiles_r;
+    if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+    if (elem_bytes == 8)
+        hipLaunchKernelGGL(k_transpose<unsigned long long>, dim3((unsigned)blocks), dim3(256), 0, stream,
+                           reinterpret_cast<const unsigned long long *>(src),
+                           reinterpret_cast<unsigned long long *>(dst), rows, cols, tiles_c);
+    else
+        hipLaunchKernelGGL(k_transpose<unsigned int>, dim3((unsigned)blocks), dim3(256), 0, stream,
+                           reinterpret_cast<const unsigned int *>(src), reinterpret_cast<unsigned int *>(dst),
+                           rows, cols, tiles_c);
+    return hipGetLastError();
+}
+
+}  // namespace sbs

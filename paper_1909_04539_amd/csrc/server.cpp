@@ -1,0 +1,464 @@
+// Serving loop: continuous batching of shared-LHS solves.
+//
+// Requests arrive on any thread (sbs_server_submit) and join a FIFO queue.
+// One scheduler thread
+//   1. retires finished launches (event polling) and stamps latencies,
+//   2. admits queued requests, in arrival order, while their result and
+//      scratch bytes fit in the device arena (the HBM budget),
+//   3. coalesces every admitted request into the next launch on a free
+//      stream slot: each request is cut into tiles of 64 systems, the tiles
+//      of one kind and precision go to one persistent tile kernel.
+// Several slots (streams) run at once, so requests admitted while earlier
+// launches are still running start at once and overlap them on the GPU.
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <new>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "internal.h"
+
+using namespace sbs;
+using Clock = std::chrono::steady_clock;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+constexpr int kMaxTilesPerLaunch = 1 << 16;
+constexpr int kGroups = 4;  // (tri, penta) x (fp64, fp32)
+constexpr int kPersistentWaves = 1024;
+
+size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+// First-fit allocator over [0, size) with coalescing of free neighbours.
+class Arena {
+   public:
+    explicit Arena(size_t size) { free_[0] = size; }
+    bool alloc(size_t bytes, size_t *off) {
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second >= bytes) {
+                *off = it->first;
+                const size_t rest = it->second - bytes, at = it->first + bytes;
+                free_.erase(it);
+                if (rest) free_[at] = rest;
+                return true;
+            }
+        }
+        return false;
+    }
+    void release(size_t off, size_t bytes) {
+        auto it = free_.emplace(off, bytes).first;
+        auto nx = std::next(it);
+        if (nx != free_.end() && it->first + it->second == nx->first) {
+            it->second += nx->second;
+            free_.erase(nx);
+        }
+        if (it != free_.begin()) {
+            auto pv = std::prev(it);
+            if (pv->first + pv->second == it->first) {
+                pv->second += it->second;
+                free_.erase(it);
+            }
+        }
+    }
+
+   private:
+    std::map<size_t, size_t> free_;
+};
+
+enum State { QUEUED, ADMITTED, RUNNING, DONE };
+
+struct Req {
+    uint64_t ticket = 0;
+    int32_t lhs = 0;
+    const void *rhs = nullptr;
+    int64_t m = 0;
+    int32_t dtype = SBS_F64;
+    size_t bytes = 0, off = 0;
+    double *x = nullptr;
+    float *scratch = nullptr;
+    State state = QUEUED;
+    sbs_status status = SBS_OK;
+    Clock::time_point t_submit, t_done;
+};
+
+struct Slot {
+    hipStream_t stream = nullptr;
+    hipEvent_t done = nullptr;
+    unsigned char *host = nullptr;  // pinned staging: counters + tiles
+    unsigned char *dev = nullptr;
+    std::vector<Req *> reqs;
+    bool busy = false;
+};
+
+}  // namespace
+
+struct sbs_server {
+    int device = 0;
+    size_t budget = 0;
+    unsigned char *arena_base = nullptr;
+    Arena arena{0};
+    int max_batch = 4096;
+    std::vector<sbs_lhs *> lhs;
+    std::vector<Slot> slots;
+
+    std::mutex mu;
+    std::condition_variable cv_sched, cv_done;
+    std::deque<Req *> queue;
+    std::deque<Req *> ready;
+    std::unordered_map<uint64_t, Req *> reqs;
+    uint64_t next_ticket = 1;
+    uint64_t kicks = 0;  // bumped by submit / release / destroy to wake the scheduler
+    bool stop = false;
+    std::thread worker;
+
+    uint64_t submitted = 0, completed = 0, rejected = 0, launches = 0, in_flight = 0;
+    size_t reserved = 0;
+    double unknowns = 0;
+    std::vector<double> lat_us;
+
+    void loop();
+    void retire();
+    void admit();
+    bool launch(Slot &s);
+};
+
+void sbs_server::retire() {
+    for (Slot &s : slots) {
+        if (!s.busy) continue;
+        const hipError_t q = hipEventQuery(s.done);
+        if (q == hipErrorNotReady) continue;
+        const auto now = Clock::now();
+        for (Req *r : s.reqs) {
+            r->state = DONE;
+            r->t_done = now;
+            if (q != hipSuccess) r->status = SBS_ERR_DEVICE;
+            lat_us.push_back(std::chrono::duration<double, std::micro>(now - r->t_submit).count());
+            ++completed;
+            --in_flight;
+            unknowns += (double)lhs[r->lhs]->n * (double)r->m;
+        }
+        s.reqs.clear();
+        s.busy = false;
+        cv_done.notify_all();
+    }
+}
+
+void sbs_server::admit() {
+    while (!queue.empty()) {
+        Req *r = queue.front();
+        size_t off;
+        if (!arena.alloc(r->bytes, &off)) break;  // FIFO: later requests wait too
+        queue.pop_front();
+        r->off = off;
+        const sbs_lhs *h = lhs[r->lhs];
+        r->x = reinterpret_cast<double *>(arena_base + off);
+        r->scratch = r->dtype == SBS_F32
+                         ? reinterpret_cast<float *>(arena_base + off + round_up((size_t)h->n * r->m * 8, kAlign))
+                         : nullptr;
+        r->state = ADMITTED;
+        reserved += r->bytes;
+        ++in_flight;
+        ready.push_back(r);
+    }
+}
+
+bool sbs_server::launch(Slot &s) {
+    // Take admitted requests in order until the tile table is full.
+    std::vector<Req *> take;
+    int tiles = 0;
+    while (!ready.empty() && (int)take.size() < max_batch) {
+        Req *r = ready.front();
+        const int t = (int)((r->m + kWave - 1) / kWave);
+        if (!take.empty() && tiles + t > kMaxTilesPerLaunch) break;
+        take.push_back(r);
+        tiles += t;
+        ready.pop_front();
+    }
+    if (take.empty()) return false;
+
+    // Group tiles by (kind, precision); inside a group, longest systems first.
+    std::vector<Tile> grp[kGroups];
+    for (Req *r : take) {
+        const sbs_lhs *h = lhs[r->lhs];
+        const int fp32 = r->dtype == SBS_F32;
+        const int g = (h->kind == SBS_PENTA ? 2 : 0) + fp32;
+        for (int64_t c = 0; c < r->m; c += kWave) {
+            Tile t;
+            t.fac = fp32 ? h->fac32 : h->fac64;
+            t.bands = h->bands;
+            t.in = r->rhs;
+            t.x = r->x;
+            t.scratch = r->scratch;
+            t.n = h->n;
+            t.m = r->m;
+            t.col0 = c;
+            t.kind = h->kind;
+            t.fp32 = fp32;
+            grp[g].push_back(t);
+        }
+        r->state = RUNNING;
+    }
+    // Staging layout: kGroups counters (one 64-byte line each), then the tiles.
+    size_t at = kGroups * 64;
+    size_t offs[kGroups];
+    for (int g = 0; g < kGroups; ++g) {
+        std::stable_sort(grp[g].begin(), grp[g].end(), [](const Tile &a, const Tile &b) { return a.n > b.n; });
+        offs[g] = at;
+        std::memcpy(s.host + at, grp[g].data(), grp[g].size() * sizeof(Tile));
+        at += grp[g].size() * sizeof(Tile);
+    }
+    std::memset(s.host, 0, kGroups * 64);
+    hipError_t e = hipMemcpyAsync(s.dev, s.host, at, hipMemcpyHostToDevice, s.stream);
+    for (int g = 0; g < kGroups && e == hipSuccess; ++g) {
+        if (grp[g].empty()) continue;
+        const int kind = g >= 2 ? SBS_PENTA : SBS_TRI;
+        e = launch_tiles(kind, g & 1, reinterpret_cast<const Tile *>(s.dev + offs[g]), (int)grp[g].size(),
+                         reinterpret_cast<int *>(s.dev + g * 64), kPersistentWaves, s.stream);
+    }
+    if (e == hipSuccess) e = hipEventRecord(s.done, s.stream);
+    s.reqs = std::move(take);
+    s.busy = true;
+    ++launches;
+    if (e != hipSuccess) {
+        // Nothing will signal these requests: fail them now.
+        const auto now = Clock::now();
+        for (Req *r : s.reqs) {
+            r->state = DONE;
+            r->status = SBS_ERR_DEVICE;
+            r->t_done = now;
+            ++completed;
+            --in_flight;
+        }
+        s.reqs.clear();
+        s.busy = false;
+        cv_done.notify_all();
+    }
+    return true;
+}
+
+void sbs_server::loop() {
+    (void)hipSetDevice(device);
+    std::unique_lock<std::mutex> lk(mu);
+    uint64_t seen = kicks;
+    for (;;) {
+        seen = kicks;
+        retire();
+        if (!stop) admit();
+        bool any_busy = false;
+        for (Slot &s : slots) {
+            if (!s.busy && !ready.empty()) launch(s);
+            any_busy |= s.busy;
+        }
+        if (stop && !any_busy && ready.empty()) break;
+        if (any_busy)
+            cv_sched.wait_for(lk, std::chrono::microseconds(20));
+        else
+            cv_sched.wait(lk, [&] { return stop || kicks != seen; });
+    }
+}
+
+extern "C" {
+
+sbs_status sbs_server_create(size_t budget_bytes, int32_t max_streams, int32_t max_batch_requests,
+                             sbs_server **out) {
+    if (!out) return SBS_ERR_INVALID_ARG;
+    *out = nullptr;
+    if (budget_bytes < kAlign || max_streams < 0 || max_streams > 16 || max_batch_requests < 0)
+        return SBS_ERR_INVALID_ARG;
+    sbs_server *s = new (std::nothrow) sbs_server();
+    if (!s) return SBS_ERR_NO_MEMORY;
+    s->budget = budget_bytes / kAlign * kAlign;
+    s->arena = Arena(s->budget);
+    s->max_batch = max_batch_requests ? max_batch_requests : 4096;
+    const int ns = max_streams ? max_streams : 4;
+    sbs_status st = SBS_OK;
+    if (hipGetDevice(&s->device) != hipSuccess) st = SBS_ERR_DEVICE;
+    if (st == SBS_OK && hipMalloc(reinterpret_cast<void **>(&s->arena_base), s->budget) != hipSuccess)
+        st = SBS_ERR_NO_MEMORY;
+    const size_t table = kGroups * 64 + (size_t)kMaxTilesPerLaunch * sizeof(Tile);
+    s->slots.resize(ns);
+    for (Slot &sl : s->slots) {
+        if (st != SBS_OK) break;
+        if (hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) != hipSuccess)
+            st = SBS_ERR_DEVICE;
+        else if (hipHostMalloc(reinterpret_cast<void **>(&sl.host), table, hipHostMallocDefault) != hipSuccess ||
+                 hipMalloc(reinterpret_cast<void **>(&sl.dev), table) != hipSuccess)
+            st = SBS_ERR_NO_MEMORY;
+    }
+    if (st != SBS_OK) {
+        for (Slot &sl : s->slots) {
+            if (sl.dev) (void)hipFree(sl.dev);
+            if (sl.host) (void)hipHostFree(sl.host);
+            if (sl.done) (void)hipEventDestroy(sl.done);
+            if (sl.stream) (void)hipStreamDestroy(sl.stream);
+        }
+        if (s->arena_base) (void)hipFree(s->arena_base);
+        delete s;
+        return st;
+    }
+    s->worker = std::thread([s] { s->loop(); });
+    *out = s;
+    return SBS_OK;
+}
+
+sbs_status sbs_server_register(sbs_server *srv, sbs_handle h, int32_t *lhs_id) {
+    if (!srv || !h || !lhs_id) return SBS_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lk(srv->mu);
+    *lhs_id = (int32_t)srv->lhs.size();
+    srv->lhs.push_back(h);
+    return SBS_OK;
+}
+
+sbs_status sbs_server_submit(sbs_server *srv, int32_t lhs_id, const void *rhs, int64_t m, int32_t dtype,
+                             uint64_t *ticket) {
+    if (!srv || !ticket || m < 1 || (dtype != SBS_F64 && dtype != SBS_F32) || !rhs) return SBS_ERR_INVALID_ARG;
+    if ((m + kWave - 1) / kWave > kMaxTilesPerLaunch) return SBS_ERR_INVALID_ARG;
+    if (reinterpret_cast<uintptr_t>(rhs) % (dtype == SBS_F64 ? 8 : 4)) return SBS_ERR_INVALID_ARG;
+    Req *r = new (std::nothrow) Req();
+    if (!r) return SBS_ERR_NO_MEMORY;
+    std::lock_guard<std::mutex> lk(srv->mu);
+    if (srv->stop) {
+        delete r;
+        return SBS_ERR_SHUTDOWN;
+    }
+    if (lhs_id < 0 || lhs_id >= (int32_t)srv->lhs.size()) {
+        delete r;
+        return SBS_ERR_INVALID_ARG;
+    }
+    const sbs_lhs *h = srv->lhs[lhs_id];
+    const size_t nm = (size_t)h->n * (size_t)m;
+    r->bytes = round_up(nm * 8, kAlign) + (dtype == SBS_F32 ? round_up(nm * 4, kAlign) : 0);
+    if (r->bytes > srv->budget) {
+        ++srv->rejected;
+        delete r;
+        return SBS_ERR_BUDGET;
+    }
+    r->ticket = srv->next_ticket++;
+    r->lhs = lhs_id;
+    r->rhs = rhs;
+    r->m = m;
+    r->dtype = dtype;
+    r->t_submit = Clock::now();
+    srv->reqs[r->ticket] = r;
+    srv->queue.push_back(r);
+    ++srv->submitted;
+    *ticket = r->ticket;
+    ++srv->kicks;
+    srv->cv_sched.notify_one();
+    return SBS_OK;
+}
+
+sbs_status sbs_server_wait(sbs_server *srv, uint64_t ticket, int64_t timeout_us, const double **x_device,
+                           double *latency_us) {
+    if (!srv) return SBS_ERR_INVALID_ARG;
+    std::unique_lock<std::mutex> lk(srv->mu);
+    auto it = srv->reqs.find(ticket);
+    if (it == srv->reqs.end()) return SBS_ERR_NOT_FOUND;
+    Req *r = it->second;
+    auto done = [&] { return r->state == DONE; };
+    if (timeout_us < 0)
+        srv->cv_done.wait(lk, done);
+    else if (!srv->cv_done.wait_for(lk, std::chrono::microseconds(timeout_us), done))
+        return SBS_ERR_TIMEOUT;
+    if (x_device) *x_device = r->status == SBS_OK ? r->x : nullptr;
+    if (latency_us) *latency_us = std::chrono::duration<double, std::micro>(r->t_done - r->t_submit).count();
+    return r->status;
+}
+
+sbs_status sbs_server_fetch(sbs_server *srv, uint64_t ticket, double *dst, void *stream) {
+    if (!srv || !dst) return SBS_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lk(srv->mu);
+    auto it = srv->reqs.find(ticket);
+    if (it == srv->reqs.end()) return SBS_ERR_NOT_FOUND;
+    Req *r = it->second;
+    if (r->state != DONE || r->status != SBS_OK) return SBS_ERR_INVALID_ARG;
+    const size_t bytes = (size_t)srv->lhs[r->lhs]->n * (size_t)r->m * sizeof(double);
+    const hipError_t e = hipMemcpyAsync(dst, r->x, bytes, hipMemcpyDeviceToDevice, static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? SBS_OK : SBS_ERR_DEVICE;
+}
+
+sbs_status sbs_server_release(sbs_server *srv, uint64_t ticket) {
+    if (!srv) return SBS_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lk(srv->mu);
+    auto it = srv->reqs.find(ticket);
+    if (it == srv->reqs.end()) return SBS_ERR_NOT_FOUND;
+    Req *r = it->second;
+    if (r->state != DONE) return SBS_ERR_INVALID_ARG;  // only finished requests give bytes back
+    if (r->bytes && r->x) {
+        srv->arena.release(r->off, r->bytes);
+        srv->reserved -= r->bytes;
+    }
+    srv->reqs.erase(it);
+    delete r;
+    ++srv->kicks;
+    srv->cv_sched.notify_one();
+    return SBS_OK;
+}
+
+sbs_status sbs_server_stats_get(sbs_server *srv, sbs_server_stats *out) {
+    if (!srv || !out) return SBS_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lk(srv->mu);
+    std::memset(out, 0, sizeof(*out));
+    out->submitted = srv->submitted;
+    out->completed = srv->completed;
+    out->rejected = srv->rejected;
+    out->launches = srv->launches;
+    out->queued = srv->queue.size();
+    out->in_flight = srv->in_flight;
+    out->bytes_reserved = srv->reserved;
+    out->budget_bytes = srv->budget;
+    out->unknowns = srv->unknowns;
+    if (!srv->lat_us.empty()) {
+        std::vector<double> v = srv->lat_us;
+        auto pct = [&](double p) {
+            const size_t k = std::min(v.size() - 1, (size_t)(p * (double)(v.size() - 1) + 0.5));
+            std::nth_element(v.begin(), v.begin() + k, v.end());
+            return v[k];
+        };
+        out->p50_us = pct(0.50);
+        out->p99_us = pct(0.99);
+        out->max_us = *std::max_element(v.begin(), v.end());
+    }
+    return SBS_OK;
+}
+
+sbs_status sbs_server_destroy(sbs_server *srv) {
+    if (!srv) return SBS_OK;
+    {
+        std::lock_guard<std::mutex> lk(srv->mu);
+        srv->stop = true;
+        // Requests still waiting for admission will never run.
+        for (Req *r : srv->queue) {
+            r->state = DONE;
+            r->status = SBS_ERR_SHUTDOWN;
+            r->t_done = Clock::now();
+        }
+        srv->queue.clear();
+        ++srv->kicks;
+        srv->cv_sched.notify_all();
+        srv->cv_done.notify_all();
+    }
+    if (srv->worker.joinable()) srv->worker.join();  // drains admitted and running work
+    sbs_status st = SBS_OK;
+    for (Slot &sl : srv->slots) {
+        if (sl.stream && hipStreamSynchronize(sl.stream) != hipSuccess) st = SBS_ERR_DEVICE;
+        if (sl.dev) (void)hipFree(sl.dev);
+        if (sl.host) (void)hipHostFree(sl.host);
+        if (sl.done) (void)hipEventDestroy(sl.done);
+        if (sl.stream) (void)hipStreamDestroy(sl.stream);
+    }
+    if (srv->arena_base && hipFree(srv->arena_base) != hipSuccess) st = SBS_ERR_DEVICE;
+    for (auto &kv : srv->reqs) delete kv.second;
+    delete srv;
+    return st;
+}
+
+}  // extern "C"
