@@ -152,6 +152,19 @@ def bench_refined(args, torch, sbs, W):
     return out
 
 
+def copy_probe(args):
+    """Plain device copy of 1 GiB (torch's copy kernel): the practical HBM
+    ceiling, and the calibration run for the FETCH_SIZE / WRITE_SIZE counters
+    (it reads 1 GiB and writes 1 GiB per launch)."""
+    import torch
+    nbytes = 1 << 30
+    a = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda:0").uniform_()
+    b = torch.empty_like(a)
+    wall, dev = timed_steps(lambda: b.copy_(a), args.steps, args.warmup, torch)
+    print(json.dumps({"probe": "copy", "bytes_read": nbytes, "bytes_written": nbytes, "ms": dev * 1e3,
+                      "GBps_read_plus_write": 2 * nbytes / dev / 1e9}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -160,12 +173,16 @@ def main():
     ap.add_argument("--variant", default="auto", choices=["auto", "resident", "chunked", "stream"])
     ap.add_argument("--only", default="", help="'headline' skips the other workloads")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--probe", default="", choices=["", "copy"], help="run a calibration probe instead")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: the batched solve shards over systems with no exchange "
               "; run it with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
+    if args.probe == "copy":
+        copy_probe(args)
+        return
     import torch
     from paper_1909_04539_amd import sbs, workloads as W
     sbs.lib()

@@ -196,11 +196,8 @@ sbs_status sbs_solve_batch_variant(sbs_handle h, void *rhs, int64_t m, int32_t d
     if (m == 0) return SBS_OK;
     if (!rhs || !aligned(rhs, dtype == SBS_F64 ? 8 : 4)) return SBS_ERR_INVALID_ARG;
     if (m > (int64_t)0x7fffffff * kWave) return SBS_ERR_INVALID_ARG;
-    if (variant == SBS_VARIANT_CHUNKED) {
-        const int64_t K = (h->n + 31) / 32;
-        const size_t need = (size_t)K * (h->kind == SBS_TRI ? 1 : 2) * kWave * (dtype == SBS_F64 ? 8 : 4);
-        if (need > 64 * 1024) return SBS_ERR_INVALID_ARG;
-    }
+    if (variant == SBS_VARIANT_CHUNKED && chunked_lds_bytes(h, dtype == SBS_F64 ? 0 : 1) > kMaxLdsBytes)
+        return SBS_ERR_INVALID_ARG;
     const int t = dtype == SBS_F64 ? 0 : 1;
     hipError_t e = launch_sweep(h, variant, t, t, t, rhs, rhs, m, static_cast<hipStream_t>(stream));
     return e == hipSuccess ? SBS_OK : SBS_ERR_DEVICE;

@@ -40,6 +40,7 @@ struct alignas(64) BandRow {
 
 constexpr int kWave = 64;       // lanes per wavefront on gfx950
 constexpr int kRowPad = 64;     // factor rows are padded with zero rows to a multiple of this
+                                // (every chunk length divides it, so chunks never read past the end)
 
 }  // namespace sbs
 
@@ -79,8 +80,11 @@ hipError_t launch_refine_step(const sbs_lhs *h, int mode, const float *b, double
 hipError_t launch_transpose(const void *src, void *dst, int64_t rows, int64_t cols,
                             int elem_bytes, hipStream_t stream);
 
-// Which variant AUTO picks, and the checkpoint bytes per wave it needs.
+// Which variant AUTO picks, and the LDS bytes per wave the chunked variant
+// needs (tc: 0 = f64, 1 = f32).
 int choose_variant(const sbs_lhs *h, int tc);
+size_t chunked_lds_bytes(const sbs_lhs *h, int tc);
+constexpr size_t kMaxLdsBytes = 64 * 1024;
 
 // Serving: heterogeneous tile launches (see server.cpp).
 struct Tile {

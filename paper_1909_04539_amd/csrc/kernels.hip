@@ -7,6 +7,8 @@
 // coalesced 512-byte (FP64) access; the shared factor row i is the same for
 // every lane and is read with wave-uniform scalar loads.  Each workgroup is
 // exactly one wavefront.
+#include <type_traits>
+
 #include "internal.h"
 
 namespace sbs {
@@ -32,15 +34,23 @@ struct Rec<SBS_TRI, T> {
     struct Bwd {
         T x1 = T(0);
     };
+    struct FC {  // forward coefficients of a row
+        T a_s, inv;
+    };
+    struct BC {  // backward coefficients of a row
+        T chat;
+    };
+    static __device__ __forceinline__ FC fc(const Row *f, int i) { return {f[i].a_s, f[i].inv}; }
+    static __device__ __forceinline__ BC bc(const Row *f, int i) { return {f[i].chat}; }
     // y_i = d_i / den_i - (a_i / den_i) y_{i-1}          (Section 3.1, forward)
-    static __device__ __forceinline__ T fwd(const Row *__restrict__ f, int i, T d, Fwd &s) {
-        const T y = fma(-f[i].a_s, s.y1, d * f[i].inv);
+    static __device__ __forceinline__ T fwd(const FC &c, T d, Fwd &s) {
+        const T y = fma(-c.a_s, s.y1, d * c.inv);
         s.y1 = y;
         return y;
     }
     // x_i = y_i - chat_i x_{i+1}                          (Section 3.1, backward)
-    static __device__ __forceinline__ T bwd(const Row *__restrict__ f, int i, T y, Bwd &s) {
-        const T x = fma(-f[i].chat, s.x1, y);
+    static __device__ __forceinline__ T bwd(const BC &c, T y, Bwd &s) {
+        const T x = fma(-c.chat, s.x1, y);
         s.x1 = x;
         return x;
     }
@@ -58,18 +68,24 @@ struct Rec<SBS_PENTA, T> {
     struct Bwd {
         T x1 = T(0), x2 = T(0);
     };
+    struct FC {
+        T eps_s, beta_s, inv;
+    };
+    struct BC {
+        T gamma, delta;
+    };
+    static __device__ __forceinline__ FC fc(const Row *f, int i) { return {f[i].eps_s, f[i].beta_s, f[i].inv}; }
+    static __device__ __forceinline__ BC bc(const Row *f, int i) { return {f[i].gamma, f[i].delta}; }
     // g_i = (f_i - eps_i g_{i-2} - beta_i g_{i-1}) / alpha_i   (Section 4.1, L g = f)
-    static __device__ __forceinline__ T fwd(const Row *__restrict__ f, int i, T v, Fwd &s) {
-        const Row &r = f[i];
-        const T g = fma(-r.beta_s, s.g1, fma(-r.eps_s, s.g2, v * r.inv));
+    static __device__ __forceinline__ T fwd(const FC &c, T v, Fwd &s) {
+        const T g = fma(-c.beta_s, s.g1, fma(-c.eps_s, s.g2, v * c.inv));
         s.g2 = s.g1;
         s.g1 = g;
         return g;
     }
     // x_i = g_i - gamma_i x_{i+1} - delta_i x_{i+2}            (Section 4.1, R x = g)
-    static __device__ __forceinline__ T bwd(const Row *__restrict__ f, int i, T g, Bwd &s) {
-        const Row &r = f[i];
-        const T x = fma(-r.gamma, s.x1, fma(-r.delta, s.x2, g));
+    static __device__ __forceinline__ T bwd(const BC &c, T g, Bwd &s) {
+        const T x = fma(-c.gamma, s.x1, fma(-c.delta, s.x2, g));
         s.x2 = s.x1;
         s.x1 = x;
         return x;
@@ -102,70 +118,230 @@ __device__ __forceinline__ void st(char *p, uint32_t lo, E v) {
     *reinterpret_cast<E *>(p + lo) = v;
 }
 
-template <typename T, typename Tin, int L>
+// Rows of a chunk are read and written with buffer instructions: a uniform
+// resource at the chunk's first row, a uniform row offset and the lane's
+// byte offset -- no per-lane 64-bit address arithmetic.  BIG selects one
+// resource per row for batches whose chunk span exceeds 31-bit offsets.
+using Rsrc = __amdgpu_buffer_rsrc_t;
+constexpr int kRawBufferFlags = 0x00020000;  // raw (untyped) buffer, gfx9-family word 3
+
+__device__ __forceinline__ Rsrc rsrc_at(const char *p) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<char *>(p), (short)0, -1, kRawBufferFlags);
+}
+template <typename E>
+__device__ __forceinline__ E bld(Rsrc r, uint32_t vo, uint32_t so) {
+    if constexpr (sizeof(E) == 8)
+        return __builtin_bit_cast(E, __builtin_amdgcn_raw_buffer_load_b64(r, vo, so, 0));
+    else
+        return __builtin_bit_cast(E, __builtin_amdgcn_raw_buffer_load_b32(r, vo, so, 0));
+}
+template <typename E>
+__device__ __forceinline__ void bst(E v, Rsrc r, uint32_t vo, uint32_t so) {
+    if constexpr (sizeof(E) == 8)
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0, 0, 0)), v), r, vo, so, 0);
+    else
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, vo, so, 0);
+}
+
+// Wave-uniform copies of values that may arrive in vector registers (the
+// arguments of out-of-line device functions): buffer resources must be built
+// from scalar registers.
+__device__ __forceinline__ uint64_t uni64(uint64_t v) {
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
+template <typename P>
+__device__ __forceinline__ P *uni(P *p) {
+    return reinterpret_cast<P *>(uni64(reinterpret_cast<uint64_t>(p)));
+}
+
+// Row offsets are stepped one add at a time and passed through an empty
+// asm, so the compiler cannot precompute all L of them into live registers.
+__device__ __forceinline__ uint32_t step_off(uint32_t so, uint32_t d) {
+    so += d;
+    asm volatile("" : "+s"(so));
+    return so;
+}
+
+template <typename T, typename Tin, int L, bool BIG>
 __device__ __forceinline__ void load_rows(T (&buf)[L], const char *base, uint32_t lo, int r0,
                                           int n, int64_t rs) {
     const char *p = base + r0 * rs;
+    const Rsrc r = rsrc_at(p);
+    uint32_t so = 0;
     if (r0 + L <= n) {
 #pragma unroll
         for (int t = 0; t < L; ++t) {
-            buf[t] = static_cast<T>(ld<Tin>(p, lo));
-            p += rs;
+            if constexpr (BIG)
+                buf[t] = static_cast<T>(bld<Tin>(rsrc_at(p + t * rs), lo, 0));
+            else
+                buf[t] = static_cast<T>(bld<Tin>(r, lo, so));
+            so = step_off(so, (uint32_t)rs);
         }
     } else {
 #pragma unroll
         for (int t = 0; t < L; ++t) {
-            buf[t] = (r0 + t < n) ? static_cast<T>(ld<Tin>(p, lo)) : T(0);
-            p += rs;
+            if (r0 + t < n) {
+                if constexpr (BIG)
+                    buf[t] = static_cast<T>(bld<Tin>(rsrc_at(p + t * rs), lo, 0));
+                else
+                    buf[t] = static_cast<T>(bld<Tin>(r, lo, so));
+            } else {
+                buf[t] = T(0);
+            }
+            so = step_off(so, (uint32_t)rs);
         }
     }
 }
 
-template <typename T, typename Tout, int L>
+template <typename T, typename Tout, int L, bool BIG>
 __device__ __forceinline__ void store_rows(const T (&buf)[L], char *base, uint32_t lo, int r0,
                                            int n, int64_t rs) {
     char *p = base + r0 * rs;
+    const Rsrc r = rsrc_at(p);
+    uint32_t so = 0;
 #pragma unroll
     for (int t = 0; t < L; ++t) {
-        if (r0 + t < n) st<Tout>(p, lo, static_cast<Tout>(buf[t]));
-        p += rs;
+        if (r0 + t < n) {
+            if constexpr (BIG)
+                bst<Tout>(static_cast<Tout>(buf[t]), rsrc_at(p + t * rs), lo, 0);
+            else
+                bst<Tout>(static_cast<Tout>(buf[t]), r, lo, so);
+        }
+        so = step_off(so, (uint32_t)rs);
     }
 }
 
+// The factor coefficients of a chunk are read from LDS four rows at a time,
+// one group ahead of the rows being computed; scheduling barriers keep the
+// compiler from hoisting every read of the chunk to its start (which would
+// hold L rows of coefficients in registers at once).
+constexpr int kGroup = 4;
+
+// Compiler-only fence: `v` must be computed here, and no memory access moves
+// across (emits no instruction).
+template <typename T>
+__device__ __forceinline__ void pin(T &v) {
+    asm volatile("" : "+v"(v) : : "memory");
+}
+
 // Backward sweep over one chunk held in registers, writing the solution.
-template <int KIND, typename T, typename Tout, int L>
-__device__ __forceinline__ void back_chunk(const typename Rec<KIND, T>::Row *__restrict__ fac,
+// `fr` points at the chunk's factor rows (staged in LDS).
+template <int KIND, typename T, typename Tout, int L, bool BIG>
+__device__ __forceinline__ void back_chunk(const typename Rec<KIND, T>::Row *__restrict__ fr,
                                            const T (&buf)[L], typename Rec<KIND, T>::Bwd &bs,
                                            char *base, uint32_t lo, int r0, int n,
                                            int64_t rs) {
     using R = Rec<KIND, T>;
-    char *p = base + (r0 + L - 1) * rs;
-    if (r0 + L <= n) {
+    constexpr int G = L < kGroup ? L : kGroup, NG = L / G;
+    char *p = base + r0 * rs;
+    const Rsrc r = rsrc_at(p);
+    const bool full = r0 + L <= n;
+    uint32_t so = (uint32_t)((L - 1) * rs);
+    typename R::BC c[2][G];
 #pragma unroll
-        for (int t = L - 1; t >= 0; --t) {
-            const T x = R::bwd(fac, r0 + t, buf[t], bs);
-            st<Tout>(p, lo, static_cast<Tout>(x));
-            p -= rs;
-        }
-    } else {
-        // Rows at or beyond n meet zero factor rows and a zero input, so
-        // they produce exact zeros and leave the carried values at zero.
+    for (int u = 0; u < G; ++u) c[(NG - 1) & 1][u] = R::bc(fr, L - 1 - u);
+    // Rows at or beyond n meet zero factor rows and a zero input, so they
+    // produce exact zeros and leave the carried values at zero.
 #pragma unroll
-        for (int t = L - 1; t >= 0; --t) {
-            const T x = R::bwd(fac, r0 + t, buf[t], bs);
-            if (r0 + t < n) st<Tout>(p, lo, static_cast<Tout>(x));
-            p -= rs;
+    for (int g = NG - 1; g >= 0; --g) {
+        if (g > 0) {
+#pragma unroll
+            for (int u = 0; u < G; ++u) c[(g - 1) & 1][u] = R::bc(fr, g * G - 1 - u);
         }
+#pragma unroll
+        for (int u = 0; u < G; ++u) {
+            const int t = g * G + G - 1 - u;
+            const T x = R::bwd(c[g & 1][u], buf[t], bs);
+            if (full || r0 + t < n) {
+                if constexpr (BIG)
+                    bst<Tout>(static_cast<Tout>(x), rsrc_at(p + t * rs), lo, 0);
+                else
+                    bst<Tout>(static_cast<Tout>(x), r, lo, so);
+            }
+            so = step_off(so, (uint32_t)(-rs));
+        }
+        pin(bs.x1);
     }
 }
 
 template <int KIND, typename T, int L>
-__device__ __forceinline__ void fwd_chunk(const typename Rec<KIND, T>::Row *__restrict__ fac,
-                                          T (&buf)[L], typename Rec<KIND, T>::Fwd &st,
-                                          int r0) {
+__device__ __forceinline__ void fwd_chunk(const typename Rec<KIND, T>::Row *__restrict__ fr,
+                                          T (&buf)[L], typename Rec<KIND, T>::Fwd &st) {
     using R = Rec<KIND, T>;
+    constexpr int G = L < kGroup ? L : kGroup, NG = L / G;
+    typename R::FC c[2][G];
 #pragma unroll
-    for (int t = 0; t < L; ++t) buf[t] = R::fwd(fac, r0 + t, buf[t], st);
+    for (int u = 0; u < G; ++u) c[0][u] = R::fc(fr, u);
+#pragma unroll
+    for (int g = 0; g < NG; ++g) {
+        if (g + 1 < NG) {
+#pragma unroll
+            for (int u = 0; u < G; ++u) c[(g + 1) & 1][u] = R::fc(fr, (g + 1) * G + u);
+        }
+#pragma unroll
+        for (int u = 0; u < G; ++u) buf[g * G + u] = R::fwd(c[g & 1][u], buf[g * G + u], st);
+        pin(buf[g * G + G - 1]);
+    }
+}
+
+// A wave's share of one factor chunk (CB bytes = L rows): lane l carries
+// bytes [l*PB, (l+1)*PB).  Chunks move global -> registers -> LDS, so that
+// the sweeps read every factor row with a broadcast LDS read instead of a
+// scalar load whose latency would stall each row.
+template <int CB>
+struct FacPiece {
+    static constexpr int PB = CB >= 256 ? CB / kWave : 4;  // bytes per lane
+    static constexpr int NL = CB / PB;                      // lanes taking part
+    static constexpr int NQ = PB >= 16 ? PB / 16 : 1;       // 16-byte words per lane (or one small word)
+    static_assert(PB == 4 || PB == 8 || PB == 16 || PB == 32 || PB == 64, "factor chunk size");
+    // Native vector types: plain vector loads and stores (HIP's uint4 is a
+    // struct whose copies become memcpy and pin the value in private memory).
+    typedef unsigned int U4 __attribute__((ext_vector_type(4)));
+    typedef unsigned int U2 __attribute__((ext_vector_type(2)));
+    using W = typename std::conditional<PB >= 16, U4, typename std::conditional<PB == 8, U2, uint32_t>::type>::type;
+};
+
+// A factor piece lives in up to four named 16-byte registers (never an
+// array, so it cannot be demoted to private memory).
+template <int CB>
+struct FacRegs {
+    using P = FacPiece<CB>;
+    typename P::W w0, w1, w2, w3;
+    __device__ __forceinline__ void load(const void *rows, int lane) {
+        const typename P::W *src =
+            reinterpret_cast<const typename P::W *>(static_cast<const char *>(rows) + lane * P::PB);
+        if (P::NL == kWave || lane < P::NL) {
+            w0 = src[0];
+            if constexpr (P::NQ >= 2) w1 = src[1];
+            if constexpr (P::NQ >= 4) {
+                w2 = src[2];
+                w3 = src[3];
+            }
+        }
+    }
+    __device__ __forceinline__ void stage(unsigned char *dst, int lane) const {
+        typename P::W *d = reinterpret_cast<typename P::W *>(dst + lane * P::PB);
+        if (P::NL == kWave || lane < P::NL) {
+            d[0] = w0;
+            if constexpr (P::NQ >= 2) d[1] = w1;
+            if constexpr (P::NQ >= 4) {
+                d[2] = w2;
+                d[3] = w3;
+            }
+        }
+    }
+};
+
+// LDS a wave needs: checkpoints (CHUNKED) then two factor-chunk buffers.
+template <int KIND, typename T, int L, int MODE>
+__host__ __device__ constexpr size_t ck_bytes(int K) {
+    return MODE == 2 ? ((size_t)K * Rec<KIND, T>::S * kWave * sizeof(T) + 15) / 16 * 16 : 0;
+}
+template <int KIND, typename T, int L, int MODE>
+__host__ __device__ constexpr size_t wave_lds_bytes(int K) {
+    return ck_bytes<KIND, T, L, MODE>(K) + 2 * L * sizeof(typename Rec<KIND, T>::Row);
 }
 
 // ---------------------------------------------------------------------------
@@ -182,79 +358,101 @@ __device__ __forceinline__ void fwd_chunk(const typename Rec<KIND, T>::Row *__re
 //  STREAM: the forward values of every chunk but the last are written over
 //    the output and read back by the backward sweep.
 //
-// Loads of the next chunk are issued before the current chunk is computed,
-// so L rows (L * 512 B per wave in FP64) are in flight while it computes.
-// The body works on the wave's systems j0 .. j0+63 of an (n, m) array; `ck`
-// is the wave's LDS checkpoint area (CHUNKED only: K * S * 64 values).
-template <int KIND, typename T, typename Tin, typename Tout, int L, int MODE>
+// Pipelining: while chunk k is computed, the right-hand side of chunk k+1
+// and the factor rows of chunk k+2 are in flight, and the factor rows of
+// chunk k+1 (which arrived during chunk k-1) are copied into the LDS buffer
+// that chunk k+1 will read.  A wave thus keeps about L * 512 B (FP64) of
+// loads outstanding, close to the hardware limit of 63 per wave.
+// The body works on the wave's systems j0 .. j0+63 of an (n, m) array; `lds`
+// is the wave's private LDS area of wave_lds_bytes(K) bytes.
+template <int KIND, typename T, typename Tin, typename Tout, int L, int MODE, bool BIG = false>
 __device__ __forceinline__ void sweep_wave(const typename Rec<KIND, T>::Row *__restrict__ fac, int n,
-                                           const Tin *in, Tout *out, int64_t m, int64_t j0, T *ck) {
+                                           const Tin *in, Tout *out, int64_t m, int64_t j0,
+                                           unsigned char *lds) {
     using R = Rec<KIND, T>;
+    using Row = typename R::Row;
+    constexpr int CB = L * (int)sizeof(Row);
     const int lane = threadIdx.x;
+    in = uni(in);
+    out = uni(out);
+    m = (int64_t)uni64((uint64_t)m);
+    j0 = (int64_t)uni64((uint64_t)j0);
+    n = __builtin_amdgcn_readfirstlane(n);
     const int jl = (j0 + lane < m) ? lane : (int)(m - 1 - j0);
     const char *bin = reinterpret_cast<const char *>(in + j0);
     char *bout = reinterpret_cast<char *>(out + j0);
     const uint32_t lin = (uint32_t)jl * sizeof(Tin), lout = (uint32_t)jl * sizeof(Tout);
     const int64_t rsi = m * (int64_t)sizeof(Tin), rso = m * (int64_t)sizeof(Tout);
     const int K = (n + L - 1) / L;
-    T *ckp = ck + lane;
+    T *ckp = reinterpret_cast<T *>(lds) + lane;
+    unsigned char *fb = lds + ck_bytes<KIND, T, L, MODE>(K);
+    auto frow = [&](int k) { return reinterpret_cast<const Row *>(fb + (k & 1) * CB); };
+    FacRegs<CB> fv;
 
     T cur[L];
     typename R::Fwd st;
-    load_rows<T, Tin, L>(cur, bin, lin, 0, n, rsi);
+    fv.load(fac, lane);                                   // factor chunk 0
+    load_rows<T, Tin, L, BIG>(cur, bin, lin, 0, n, rsi);
+    fv.stage(fb, lane);
 
     if constexpr (MODE == MODE_RESIDENT) {
-        fwd_chunk<KIND, T, L>(fac, cur, st, 0);
+        fwd_chunk<KIND, T, L>(frow(0), cur, st);
         typename R::Bwd bs;
-        back_chunk<KIND, T, Tout, L>(fac, cur, bs, bout, lout, 0, n, rso);
+        back_chunk<KIND, T, Tout, L, BIG>(frow(0), cur, bs, bout, lout, 0, n, rso);
         return;
     } else {
         T nxt[L];
+        if (K > 1) fv.load(fac + L, lane);                // factor chunk 1
         // Forward sweep.
         for (int k = 0; k < K; ++k) {
             if constexpr (MODE == MODE_CHUNKED) R::put(st, ckp + k * (R::S * kWave));
             const bool more = k + 1 < K;
-            if (more) load_rows<T, Tin, L>(nxt, bin, lin, (k + 1) * L, n, rsi);
-            fwd_chunk<KIND, T, L>(fac, cur, st, k * L);
+            if (more) load_rows<T, Tin, L, BIG>(nxt, bin, lin, (k + 1) * L, n, rsi);
+            fwd_chunk<KIND, T, L>(frow(k), cur, st);
             if (more) {
-                if constexpr (MODE == MODE_STREAM) store_rows<T, Tout, L>(cur, bout, lout, k * L, n, rso);
+                if constexpr (MODE == MODE_STREAM) store_rows<T, Tout, L, BIG>(cur, bout, lout, k * L, n, rso);
+                fv.stage(fb + ((k + 1) & 1) * CB, lane);  // chunk k+1's factor, loaded one chunk ago
+                if (k + 2 < K) fv.load(fac + (k + 2) * L, lane);
 #pragma unroll
                 for (int t = 0; t < L; ++t) cur[t] = nxt[t];
             }
         }
-        // Backward sweep; cur holds the forward values of the last chunk.
+        // Backward sweep; cur holds the forward values of the last chunk and
+        // buffer (K-1)&1 its factor rows.
         typename R::Bwd bs;
         if (K >= 2) {
+            fv.load(fac + (K - 2) * L, lane);
             if constexpr (MODE == MODE_CHUNKED)
-                load_rows<T, Tin, L>(nxt, bin, lin, (K - 2) * L, n, rsi);
+                load_rows<T, Tin, L, BIG>(nxt, bin, lin, (K - 2) * L, n, rsi);
             else
-                load_rows<T, Tout, L>(nxt, bout, lout, (K - 2) * L, n, rso);
+                load_rows<T, Tout, L, BIG>(nxt, bout, lout, (K - 2) * L, n, rso);
         }
-        back_chunk<KIND, T, Tout, L>(fac, cur, bs, bout, lout, (K - 1) * L, n, rso);
+        back_chunk<KIND, T, Tout, L, BIG>(frow(K - 1), cur, bs, bout, lout, (K - 1) * L, n, rso);
         for (int k = K - 2; k >= 0; --k) {
+            fv.stage(fb + (k & 1) * CB, lane);
 #pragma unroll
             for (int t = 0; t < L; ++t) cur[t] = nxt[t];
             if (k >= 1) {
+                fv.load(fac + (k - 1) * L, lane);
                 if constexpr (MODE == MODE_CHUNKED)
-                    load_rows<T, Tin, L>(nxt, bin, lin, (k - 1) * L, n, rsi);
+                    load_rows<T, Tin, L, BIG>(nxt, bin, lin, (k - 1) * L, n, rsi);
                 else
-                    load_rows<T, Tout, L>(nxt, bout, lout, (k - 1) * L, n, rso);
+                    load_rows<T, Tout, L, BIG>(nxt, bout, lout, (k - 1) * L, n, rso);
             }
             if constexpr (MODE == MODE_CHUNKED) {
                 R::get(st, ckp + k * (R::S * kWave));
-                fwd_chunk<KIND, T, L>(fac, cur, st, k * L);
+                fwd_chunk<KIND, T, L>(frow(k), cur, st);
             }
-            back_chunk<KIND, T, Tout, L>(fac, cur, bs, bout, lout, k * L, n, rso);
+            back_chunk<KIND, T, Tout, L, BIG>(frow(k), cur, bs, bout, lout, k * L, n, rso);
         }
     }
 }
 
-template <int KIND, typename T, typename Tin, typename Tout, int L, int MODE>
+template <int KIND, typename T, typename Tin, typename Tout, int L, int MODE, bool BIG>
 __global__ __launch_bounds__(kWave) void k_sweep(const typename Rec<KIND, T>::Row *__restrict__ fac,
                                                  int n, const Tin *in, Tout *out, int64_t m) {
     extern __shared__ __align__(16) unsigned char smem[];
-    sweep_wave<KIND, T, Tin, Tout, L, MODE>(fac, n, in, out, m, (int64_t)blockIdx.x * kWave,
-                                            reinterpret_cast<T *>(smem));
+    sweep_wave<KIND, T, Tin, Tout, L, MODE, BIG>(fac, n, in, out, m, (int64_t)blockIdx.x * kWave, smem);
 }
 
 // ---------------------------------------------------------------------------
@@ -387,27 +585,31 @@ __global__ __launch_bounds__(256) void k_update(double *__restrict__ x, const fl
 // residual bodies as the plain entry points, so a request's result is
 // bit-identical whether it runs alone or in a mix.  The loop ends when the
 // counter passes the last tile, so every wave exits.
-constexpr int kTileCk = 4096;  // doubles of LDS checkpoint space per wave (32 KB)
+constexpr int kTileLds = 36 * 1024;  // LDS per tile wave: checkpoints + factor staging
+
+template <int KIND, typename T>
+__device__ __forceinline__ bool tile_fits_chunked(int n) {
+    return wave_lds_bytes<KIND, T, 32, MODE_CHUNKED>((n + 31) / 32) <= (size_t)kTileLds;
+}
 
 template <int KIND>
-__device__ __forceinline__ void run_tile_f64(const Tile &t, double *ck) {
+__device__ __forceinline__ void run_tile_f64(const Tile &t, unsigned char *lds) {
     const int n = (int)t.n;
-    constexpr int S = Rec<KIND, double>::S;
     using Row = typename Rec<KIND, double>::Row;
     const Row *fac = reinterpret_cast<const Row *>(t.fac);
     const double *in = reinterpret_cast<const double *>(t.in);
-    if (((n + 31) / 32) * S * kWave <= kTileCk)
-        sweep_wave<KIND, double, double, double, 32, MODE_CHUNKED>(fac, n, in, t.x, t.m, t.col0, ck);
+    if (tile_fits_chunked<KIND, double>(n))
+        sweep_wave<KIND, double, double, double, 32, MODE_CHUNKED>(fac, n, in, t.x, t.m, t.col0, lds);
     else
-        sweep_wave<KIND, double, double, double, 32, MODE_STREAM>(fac, n, in, t.x, t.m, t.col0, ck);
+        sweep_wave<KIND, double, double, double, 32, MODE_STREAM>(fac, n, in, t.x, t.m, t.col0, lds);
 }
 
 // The phases of an FP32 tile are kept out of line so that each gets its own
 // register allocation instead of one allocation spanning all five.
 template <int KIND, typename Tout, int MODE>
 __device__ __noinline__ void tile_sweep_f32(const typename Rec<KIND, float>::Row *fac, int n, const float *in,
-                                            Tout *out, int64_t m, int64_t j0, float *ck) {
-    sweep_wave<KIND, float, float, Tout, 32, MODE>(fac, n, in, out, m, j0, ck);
+                                            Tout *out, int64_t m, int64_t j0, unsigned char *lds) {
+    sweep_wave<KIND, float, float, Tout, 32, MODE>(fac, n, in, out, m, j0, lds);
 }
 
 template <int KIND, int MODE>
@@ -417,27 +619,25 @@ __device__ __noinline__ void tile_residual(const BandRow *bands, int64_t n, cons
 }
 
 template <int KIND>
-__device__ __forceinline__ void run_tile_f32(const Tile &t, double *ck) {
+__device__ __forceinline__ void run_tile_f32(const Tile &t, unsigned char *lds) {
     const int n = (int)t.n;
-    constexpr int S = Rec<KIND, float>::S;
     using Row = typename Rec<KIND, float>::Row;
     const Row *fac = reinterpret_cast<const Row *>(t.fac);
     const float *b = reinterpret_cast<const float *>(t.in);
-    float *ckf = reinterpret_cast<float *>(ck);
-    const bool chunk = ((n + 31) / 32) * S * kWave <= 2 * kTileCk;
+    const bool chunk = tile_fits_chunked<KIND, float>(n);
     if (chunk)
-        tile_sweep_f32<KIND, double, MODE_CHUNKED>(fac, n, b, t.x, t.m, t.col0, ckf);
+        tile_sweep_f32<KIND, double, MODE_CHUNKED>(fac, n, b, t.x, t.m, t.col0, lds);
     else
-        tile_sweep_f32<KIND, double, MODE_STREAM>(fac, n, b, t.x, t.m, t.col0, ckf);
+        tile_sweep_f32<KIND, double, MODE_STREAM>(fac, n, b, t.x, t.m, t.col0, lds);
     for (int pass = 0; pass < 2; ++pass) {
         if (pass == 0)
             tile_residual<KIND, 0>(t.bands, n, b, t.x, t.scratch, t.m, t.col0);
         else
             tile_residual<KIND, 1>(t.bands, n, b, t.x, t.scratch, t.m, t.col0);
         if (chunk)
-            tile_sweep_f32<KIND, float, MODE_CHUNKED>(fac, n, t.scratch, t.scratch, t.m, t.col0, ckf);
+            tile_sweep_f32<KIND, float, MODE_CHUNKED>(fac, n, t.scratch, t.scratch, t.m, t.col0, lds);
         else
-            tile_sweep_f32<KIND, float, MODE_STREAM>(fac, n, t.scratch, t.scratch, t.m, t.col0, ckf);
+            tile_sweep_f32<KIND, float, MODE_STREAM>(fac, n, t.scratch, t.scratch, t.m, t.col0, lds);
     }
     update_wave(t.x, t.scratch, n, t.m, t.col0);
 }
@@ -445,7 +645,7 @@ __device__ __forceinline__ void run_tile_f32(const Tile &t, double *ck) {
 // One kernel per (kind, precision) group of a launch's tiles.
 template <int KIND, int FP32>
 __global__ __launch_bounds__(kWave) void k_tiles(const Tile *__restrict__ tiles, int ntiles, int *counter) {
-    __shared__ __align__(16) double ck[kTileCk];
+    __shared__ __align__(16) unsigned char lds[kTileLds];
     for (;;) {
         int t = 0;
         if (threadIdx.x == 0) t = atomicAdd(counter, 1);
@@ -453,9 +653,9 @@ __global__ __launch_bounds__(kWave) void k_tiles(const Tile *__restrict__ tiles,
         if (t >= ntiles) break;
         const Tile tl = tiles[t];
         if constexpr (FP32)
-            run_tile_f32<KIND>(tl, ck);
+            run_tile_f32<KIND>(tl, lds);
         else
-            run_tile_f64<KIND>(tl, ck);
+            run_tile_f64<KIND>(tl, lds);
     }
 }
 
@@ -487,19 +687,25 @@ __global__ __launch_bounds__(256) void k_transpose(const E *__restrict__ src, E 
 // ---------------------------------------------------------------------------
 // Launch helpers.
 
-constexpr size_t kMaxLdsBytes = 64 * 1024;
-
 template <int KIND, typename T, typename Tin, typename Tout, int L, int MODE>
 hipError_t go(const sbs_lhs *h, const void *fac, const void *in, void *out, int64_t m,
               hipStream_t s) {
     using R = Rec<KIND, T>;
     const int64_t blocks = (m + kWave - 1) / kWave;
-    const int64_t K = (h->n + L - 1) / L;
-    const size_t lds = (MODE == MODE_CHUNKED) ? (size_t)K * R::S * kWave * sizeof(T) : 0;
+    const size_t lds = wave_lds_bytes<KIND, T, L, MODE>((int)((h->n + L - 1) / L));
     if (lds > kMaxLdsBytes) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_sweep<KIND, T, Tin, Tout, L, MODE>), dim3((unsigned)blocks), dim3(kWave),
-                       lds, s, reinterpret_cast<const typename R::Row *>(fac), (int)h->n,
-                       reinterpret_cast<const Tin *>(in), reinterpret_cast<Tout *>(out), m);
+    // Row offsets inside a chunk must fit the 31-bit buffer offset, with room
+    // for the lane offset; wider batches take one buffer resource per row.
+    const int64_t span = (int64_t)L * m * (int64_t)(sizeof(Tin) > sizeof(Tout) ? sizeof(Tin) : sizeof(Tout));
+    const auto *f = reinterpret_cast<const typename R::Row *>(fac);
+    const auto *pi = reinterpret_cast<const Tin *>(in);
+    auto *po = reinterpret_cast<Tout *>(out);
+    if (span < (int64_t(1) << 31) - 4096)
+        hipLaunchKernelGGL((k_sweep<KIND, T, Tin, Tout, L, MODE, false>), dim3((unsigned)blocks), dim3(kWave), lds, s,
+                           f, (int)h->n, pi, po, m);
+    else
+        hipLaunchKernelGGL((k_sweep<KIND, T, Tin, Tout, L, MODE, true>), dim3((unsigned)blocks), dim3(kWave), lds, s,
+                           f, (int)h->n, pi, po, m);
     return hipGetLastError();
 }
 
@@ -527,12 +733,18 @@ hipError_t dispatch_kind(const sbs_lhs *h, int mode, const void *fac, const void
 
 }  // namespace
 
+size_t chunked_lds_bytes(const sbs_lhs *h, int tc) {
+    const int K = (int)((h->n + 31) / 32);
+    if (h->kind == SBS_TRI)
+        return tc == 0 ? wave_lds_bytes<SBS_TRI, double, 32, MODE_CHUNKED>(K)
+                       : wave_lds_bytes<SBS_TRI, float, 32, MODE_CHUNKED>(K);
+    return tc == 0 ? wave_lds_bytes<SBS_PENTA, double, 32, MODE_CHUNKED>(K)
+                   : wave_lds_bytes<SBS_PENTA, float, 32, MODE_CHUNKED>(K);
+}
+
 int choose_variant(const sbs_lhs *h, int tc) {
     if (h->n <= 64) return SBS_VARIANT_RESIDENT;
-    const size_t elem = tc == 0 ? 8 : 4;
-    const int S = h->kind == SBS_TRI ? 1 : 2;
-    const int64_t K = (h->n + 31) / 32;
-    if ((size_t)K * S * kWave * elem <= kMaxLdsBytes) return SBS_VARIANT_CHUNKED;
+    if (chunked_lds_bytes(h, tc) <= kMaxLdsBytes) return SBS_VARIANT_CHUNKED;
     return SBS_VARIANT_STREAM;
 }
 

@@ -33,6 +33,15 @@ def bands_for(kind, n, seed):
     return W.zero_outside(B)
 
 
+def chunked_fits(kind, n, elem=8):
+    """The chunked variant keeps per-chunk checkpoints plus two factor chunks
+    in one workgroup's LDS, at most 64 KiB."""
+    K = (n + 31) // 32
+    S = 1 if kind == 3 else 2
+    row = (4 if kind == 3 else 8) * elem
+    return K * S * 64 * elem + 2 * 32 * row <= 64 * 1024
+
+
 def gpu_solve(kind, B, rhs, variant=sbs.VARIANT_AUTO, dtype=torch.float64):
     with sbs.SharedLhs(kind, B) as lhs:
         x = torch.from_numpy(np.ascontiguousarray(rhs)).to(DEV, dtype)
@@ -55,6 +64,11 @@ def test_fp64_matches_oracle(kind, variant, n, m):
     print(f"case kind={kind} variant={variant} n={n} m={m}", flush=True)
     B = bands_for(kind, n, 1000 * kind + n)
     rhs = np.random.default_rng(n * 7 + m).uniform(-1, 1, (n, m))
+    if variant == sbs.VARIANT_CHUNKED and not chunked_fits(kind, n):
+        with pytest.raises(sbs.SbsError) as e:
+            gpu_solve(kind, B, rhs, variant)
+        assert e.value.status == 1
+        return
     got = gpu_solve(kind, B, rhs, variant)
     assert colrel(got, oracle.solve(kind, B, rhs)) <= TOL64
 
