@@ -24,6 +24,23 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_sweep_penta_f64_n1024_m65536.json")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_1909_04539_amd", "csrc", "kernels.hip")
+
+
+def measured_traffic():
+    """HBM bytes per launch of the headline kernel from the committed
+    rocprofv3 FETCH_SIZE / WRITE_SIZE runs (scaled by the copy calibration),
+    or None if the kernel source has changed since they were taken."""
+    import hashlib
+    try:
+        rec = json.load(open(TRAFFIC_FILE))
+        sha = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    if rec.get("kernel_source_sha256") != sha:
+        return None
+    return round(rec["traffic_bytes_per_launch"])
 
 
 def log(*a):
@@ -91,7 +108,7 @@ def bench_headline(args, torch, sbs, W):
     res = {
         "wall_s": wall, "dev_s": dev, "unknowns": unknowns,
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None},
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic()},
         "cpu_sample": wl.rhs[:, :8192].copy(), "bands": wl.bands,
     }
     lhs.close()
@@ -152,6 +169,136 @@ def bench_refined(args, torch, sbs, W):
     return out
 
 
+class _Server:
+    """Minimal client of the C-ABI serving loop (argument marshalling only)."""
+
+    def __init__(self, sbs, budget, streams=4):
+        import ctypes
+        self.ct, self.L = ctypes, sbs.lib()
+        self.p = ctypes.c_void_p()
+        st = self.L.sbs_server_create(budget, streams, 0, ctypes.byref(self.p))
+        if st:
+            raise RuntimeError(f"sbs_server_create: {st}")
+
+    def register(self, h):
+        i = self.ct.c_int32()
+        assert self.L.sbs_server_register(self.p, h, self.ct.byref(i)) == 0
+        return i.value
+
+    def submit(self, lhs, ptr, m, dtype):
+        tk = self.ct.c_uint64()
+        st = self.L.sbs_server_submit(self.p, lhs, ptr, m, dtype, self.ct.byref(tk))
+        if st:
+            raise RuntimeError(f"sbs_server_submit: {st}")
+        return tk.value
+
+    def wait_release(self, tk):
+        x, lat = self.ct.c_void_p(), self.ct.c_double()
+        st = self.L.sbs_server_wait(self.p, tk, -1, self.ct.byref(x), self.ct.byref(lat))
+        self.L.sbs_server_release(self.p, tk)
+        return st, lat.value
+
+    def stats(self, sbs):
+        s = sbs.ServerStats()
+        self.L.sbs_server_stats_get(self.p, self.ct.byref(s))
+        return s
+
+    def close(self):
+        self.L.sbs_server_destroy(self.p)
+
+
+def bench_serving(args, torch, sbs, W):
+    """Serving form: 64 shared matrices (n log-uniform 64..8192), requests with
+    m log-uniform 1..4096, FP32 or FP64.  Right-hand sides are read-only
+    slices of a resident random pool (inputs pre-staged, untimed).  First a
+    closed-loop run gives the saturation rate, then Poisson arrivals at 0.8 of
+    it; the same arrivals are replayed through a plain FP64 FIFO (one
+    sbs_solve_batch per request, no coalescing) for comparison."""
+    import threading
+    count = args.serve_requests
+    lhss = W.serving_lhs_set()
+    hs = [sbs.SharedLhs(l.kind, l.bands) for l in lhss]
+    pool_elems = 1 << 28
+    g = torch.Generator(device="cuda:0")
+    g.manual_seed(4)
+    pool64 = torch.rand(pool_elems, dtype=torch.float64, device="cuda:0", generator=g) * 2 - 1
+    pool32 = pool64.to(torch.float32)
+    free, _ = torch.cuda.mem_get_info()
+    budget = int(min(200e9, free - 16e9))
+    srv = _Server(sbs, budget)
+    ids = [srv.register(h.handle) for h in hs]
+    trace = W.serving_trace(rate_hz=1.0, count=count)       # arrival shape; rescaled below
+    rng = np.random.default_rng(7)
+    offs = []
+    for r in trace:
+        nm = lhss[r.lhs].n * r.m
+        offs.append(int(rng.integers(0, pool_elems - nm + 1)) // 64 * 64)
+    ptr = [(pool32 if r.fp32 else pool64).data_ptr() + o * (4 if r.fp32 else 8) for r, o in zip(trace, offs)]
+    dt = [sbs.SBS_F32 if r.fp32 else sbs.SBS_F64 for r in trace]
+    unknowns = float(sum(lhss[r.lhs].n * r.m for r in trace))
+    torch.cuda.synchronize()
+
+    def run(arrivals):
+        tickets = [None] * count
+        lat = [0.0] * count
+        done = threading.Event()
+
+        def waiter():
+            for k in range(count):
+                while tickets[k] is None:
+                    time.sleep(0)
+                st, l = srv.wait_release(tickets[k])
+                lat[k] = l
+            done.set()
+
+        th = threading.Thread(target=waiter)
+        th.start()
+        t0 = time.perf_counter()
+        for k, r in enumerate(trace):
+            if arrivals is not None:
+                while time.perf_counter() - t0 < arrivals[k]:
+                    pass
+            tickets[k] = srv.submit(ids[r.lhs], ptr[k], r.m, dt[k])
+        done.wait()
+        th.join()
+        return time.perf_counter() - t0, np.array(lat)
+
+    run(None)                                   # warm-up pass
+    make, lat_closed = run(None)
+    lam_sat = count / make
+    base_gaps = np.array([r.t_arrival for r in trace])       # arrivals of a unit-rate Poisson process
+    arrivals = base_gaps / (0.8 * lam_sat)
+    span, lat = run(arrivals)
+    s = srv.stats(sbs)
+    srv.close()
+
+    # Plain FP64 FIFO on the same arrivals: one solve per request, in order.
+    stream = torch.cuda.current_stream()
+    lat_f = np.zeros(count)
+    t0 = time.perf_counter()
+    for k, r in enumerate(trace):
+        while time.perf_counter() - t0 < arrivals[k]:
+            pass
+        h = hs[r.lhs]
+        x = pool64[offs[k]:offs[k] + h.n * r.m].view(h.n, r.m)
+        sbs.sbs_solve_batch(h.handle, x)
+        stream.synchronize()
+        lat_f[k] = (time.perf_counter() - t0 - arrivals[k]) * 1e6
+    fifo_span = time.perf_counter() - t0
+    for h in hs:
+        h.close()
+    pct = lambda a, q: float(np.percentile(a, q))
+    return {"workload": f"serving_64lhs_{count}req_rho0.8", "requests": count, "unknowns": unknowns,
+            "saturation_req_per_s": lam_sat, "saturation_unknowns_per_s": unknowns / make,
+            "offered_req_per_s": 0.8 * lam_sat, "launches": int(s.launches),
+            "p50_us": pct(lat, 50), "p99_us": pct(lat, 99), "max_us": float(lat.max()),
+            "unknowns_per_s": unknowns / span,
+            "fifo_f64_p50_us": pct(lat_f, 50), "fifo_f64_p99_us": pct(lat_f, 99),
+            "fifo_f64_unknowns_per_s": unknowns / fifo_span,
+            "note": "latency = submit to completion incl. queueing; rhs device-resident; FIFO baseline solves "
+                    "every request in FP64 on one stream without coalescing"}
+
+
 def copy_probe(args):
     """Plain device copy of 1 GiB (torch's copy kernel): the practical HBM
     ceiling, and the calibration run for the FETCH_SIZE / WRITE_SIZE counters
@@ -173,6 +320,7 @@ def main():
     ap.add_argument("--variant", default="auto", choices=["auto", "resident", "chunked", "stream"])
     ap.add_argument("--only", default="", help="'headline' skips the other workloads")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--serve-requests", type=int, default=20000)
     ap.add_argument("--probe", default="", choices=["", "copy"], help="run a calibration probe instead")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -189,8 +337,12 @@ def main():
     log("headline: penta f64 n=1024 m=65536")
     h = bench_headline(args, torch, sbs, W)
     extra = {}
+    if args.only == "serving":
+        print(json.dumps(bench_serving(args, torch, sbs, W)), flush=True)
+        return
     if args.only != "headline":
-        for name, fn in (("tri_n256_m1024", bench_tri256), ("adi_2048", bench_adi), ("refined_n512_m1M", bench_refined)):
+        for name, fn in (("tri_n256_m1024", bench_tri256), ("adi_2048", bench_adi), ("refined_n512_m1M", bench_refined),
+                         ("serving", bench_serving)):
             log(f"workload {name}")
             try:
                 extra[name] = fn(args, torch, sbs, W)
