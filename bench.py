@@ -4,7 +4,7 @@ Headline (the JSON line's `value`): right-hand-side unknowns solved per
 second for the pentadiagonal FP64 workload -- n = 1024 unknowns, m = 65536
 systems sharing one matrix (1-D hyperdiffusion Crank--Nicolson step, s = 0.5)
 -- one in-place solve per step, inputs resident in HBM.  Beside it: the
-roofline of the sweep kernel (algorithmic 16 B per unknown against 8 TB/s),
+roofline of the kernel that runs it (algorithmic 16 B per unknown against 8 TB/s),
 the oracle timed on the host cores, and the other workloads (tridiagonal
 n=256 batch, 2-D ADI step, mixed-precision refinement, serving).
 
@@ -24,17 +24,23 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_sweep_penta_f64_n1024_m65536.json")
 KERNEL_SOURCE = os.path.join(ROOT, "paper_1909_04539_amd", "csrc", "kernels.hip")
+VARIANTS = {"auto": 0, "resident": 1, "chunked": 2, "stream": 3, "partition": 4}
+# kernel that runs each variant of the headline solve
+KERNEL_OF = {1: "k_sweep", 2: "k_sweep", 3: "k_sweep", 4: "k_part"}
 
 
-def measured_traffic():
+def traffic_file(kernel):
+    return os.path.join(ROOT, "profiles", f"{kernel}_penta_f64_n1024_m65536.json")
+
+
+def measured_traffic(kernel):
     """HBM bytes per launch of the headline kernel from the committed
     rocprofv3 FETCH_SIZE / WRITE_SIZE runs (scaled by the copy calibration),
     or None if the kernel source has changed since they were taken."""
     import hashlib
     try:
-        rec = json.load(open(TRAFFIC_FILE))
+        rec = json.load(open(traffic_file(kernel)))
         sha = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
     except OSError:
         return None
@@ -100,15 +106,19 @@ def bench_headline(args, torch, sbs, W):
     n, m = wl.n, wl.m
     rhs = torch.from_numpy(wl.rhs).to("cuda:0")
     lhs = sbs.SharedLhs(5, wl.bands)
-    variant = {"auto": 0, "resident": 1, "chunked": 2, "stream": 3}[args.variant]
+    variant = VARIANTS[args.variant]
+    ran = variant if variant else sbs.sbs_auto_variant(lhs.handle, m)
+    kernel = KERNEL_OF[ran]
     step = lambda: lhs.solve(rhs, variant)
     wall, dev = timed_steps(step, args.steps, args.warmup, torch)
     unknowns = n * m
     achieved = 16.0 * unknowns / dev / 1e9
     res = {
         "wall_s": wall, "dev_s": dev, "unknowns": unknowns,
+        "variant": {v: k for k, v in VARIANTS.items()}[ran], "kernel": kernel,
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic()},
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(kernel),
+                     "kernel": kernel},
         "cpu_sample": wl.rhs[:, :8192].copy(), "bands": wl.bands,
     }
     lhs.close()
@@ -317,7 +327,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--variant", default="auto", choices=["auto", "resident", "chunked", "stream"])
+    ap.add_argument("--variant", default="auto", choices=list(VARIANTS))
     ap.add_argument("--only", default="", help="'headline' skips the other workloads")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--serve-requests", type=int, default=20000)
@@ -364,7 +374,7 @@ def main():
         "dtype": "f64",
         "data": "synthetic (seeded): rhs = A x_true, x_true ~ N(0,1)",
         "config": {"workload": "penta_f64_n1024_m65536_shared_lhs", "n": 1024, "m": 65536,
-                   "matrix": "I + s(1,-4,6,-4,1), s=0.5, truncated ends", "variant": args.variant},
+                   "matrix": "I + s(1,-4,6,-4,1), s=0.5, truncated ends", "variant": h["variant"]},
         "roofline": h["roofline"],
         "cpu_baseline": cpu,
         "kernel_ms": h["dev_s"] * 1e3,

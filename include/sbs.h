@@ -57,7 +57,9 @@ typedef enum sbs_variant {
     SBS_VARIANT_AUTO = 0,     /* chosen from n and dtype                      */
     SBS_VARIANT_RESIDENT = 1, /* whole column in registers (n <= 64)          */
     SBS_VARIANT_CHUNKED = 2,  /* checkpoint every chunk, recompute backwards  */
-    SBS_VARIANT_STREAM = 3    /* forward result written over the rhs, re-read */
+    SBS_VARIANT_STREAM = 3,   /* forward result written over the rhs, re-read */
+    SBS_VARIANT_PARTITION = 4 /* each system's rows split over several lanes:  */
+                              /* block solves, shared spikes, interface solve */
 } sbs_variant;
 
 typedef struct sbs_lhs *sbs_handle;
@@ -115,15 +117,32 @@ sbs_status sbs_solve_batch(sbs_handle h, void *rhs, int64_t m, int32_t dtype,
                            void *stream);
 
 /* As sbs_solve_batch with an explicit sweep variant (SBS_VARIANT_*).  The
- * resident variant needs n <= 64; otherwise SBS_ERR_INVALID_ARG. */
+ * resident variant needs n <= 64, the partitioned variant a matrix whose
+ * blocks and interface system factor without a zero pivot and fit in LDS
+ * (n up to a few thousand); otherwise SBS_ERR_INVALID_ARG.
+ * The partitioned variant is not in the paper: it cuts every system's rows
+ * into blocks solved by different lanes and couples them through the
+ * partition ("spike") form of the same banded system; the couplings depend on
+ * the matrix only, so they are computed once with the factor. */
 sbs_status sbs_solve_batch_variant(sbs_handle h, void *rhs, int64_t m,
                                    int32_t dtype, int32_t variant, void *stream);
+
+/* The variant SBS_VARIANT_AUTO runs for m systems of this dtype: the
+ * partitioned variant when a plan exists and fits, otherwise resident
+ * (n <= 64), chunked (checkpoints fit 64 KiB of LDS) or stream.  Host only,
+ * no device work.  Errors: SBS_ERR_INVALID_ARG (NULL handle or output,
+ * m < 1, dtype). */
+sbs_status sbs_auto_variant(sbs_handle h, int64_t m, int32_t dtype,
+                            int32_t *variant);
 
 /*
  * Mixed precision: FP32 right-hand sides, FP64 solution.
  * x0 = FP32 solve of b; then `sweeps` times: r = b - A x in FP64 with the
  * original FP64 bands, delta = FP32 solve of fl32(r), x += delta in FP64.
- * The FP32 solves use the FP32 rounding of the FP64 factor.
+ * The FP32 solves use the FP32 rounding of the FP64 factor.  When the
+ * matrix has a partition plan (see SBS_VARIANT_PARTITION) all passes run in
+ * one kernel that keeps each system's b and x on chip, so b is read once and
+ * x written once; `work` is then not touched.
  *
  *  b          device, n*m floats, interleaved, read only.
  *  x          device, n*m doubles, interleaved, written (may not alias b).

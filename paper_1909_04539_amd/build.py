@@ -11,7 +11,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libsbs.so")
 
-SOURCES = ["kernels.hip", "api.cpp", "server.cpp"]
+SOURCES = ["kernels.hip", "api.cpp", "partition.cpp", "server.cpp"]
 
 # -packed-fp32-ops: keep the compiler from emitting packed FP32 VALU forms.
 HIP_FLAGS = [

@@ -6,66 +6,18 @@
 #include <new>
 #include <vector>
 
+#include "factor_rows.h"
 #include "internal.h"
 
 using namespace sbs;
 
 namespace {
 
-bool finite_nonzero(double p) { return std::isfinite(p) && p != 0.0; }
-
 // Coefficient k of row i of a row-aligned band array, 0 outside the matrix.
 double coef(const double *bands, int kind, int64_t n, int k, int64_t i) {
     const int64_t col = i + k - kind / 2;
     if (col < 0 || col >= n) return 0.0;
     return bands[(int64_t)k * n + i];
-}
-
-// Host FP64 factorisation, Section 3.1.  den_i = b_i - a_i chat_{i-1},
-// chat_i = c_i / den_i; rows hold {a_i/den_i, chat_i, 1/den_i}.
-sbs_status factor_tri(const double *B, int64_t n, std::vector<TriRow<double>> &rows, int64_t *bad) {
-    double chat_prev = 0.0;
-    for (int64_t i = 0; i < n; ++i) {
-        const double a = coef(B, 3, n, 0, i), b = coef(B, 3, n, 1, i), c = coef(B, 3, n, 2, i);
-        const double den = b - a * chat_prev;
-        if (!finite_nonzero(den)) {
-            *bad = i;
-            return SBS_ERR_ZERO_PIVOT;
-        }
-        const double chat = c / den;
-        rows[i] = {a / den, chat, 1.0 / den, 0.0};
-        chat_prev = chat;
-    }
-    return SBS_OK;
-}
-
-// Host FP64 factorisation A = L R, Section 4.1.  With everything outside the
-// matrix equal to zero, one recurrence covers every row:
-//   beta_i = b_i - a_i gamma_{i-2}
-//   alpha_i = c_i - a_i delta_{i-2} - beta_i gamma_{i-1}
-//   gamma_i = (d_i - beta_i delta_{i-1}) / alpha_i,  delta_i = e_i / alpha_i,
-//   eps_i = a_i.
-// Rows hold {eps_i/alpha_i, beta_i/alpha_i, 1/alpha_i, gamma_i, delta_i}.
-sbs_status factor_penta(const double *B, int64_t n, std::vector<PentaRow<double>> &rows, int64_t *bad) {
-    double g1 = 0.0, g2 = 0.0, d1 = 0.0, d2 = 0.0;  // gamma/delta at i-1 and i-2
-    for (int64_t i = 0; i < n; ++i) {
-        const double a = coef(B, 5, n, 0, i), b = coef(B, 5, n, 1, i), c = coef(B, 5, n, 2, i);
-        const double d = coef(B, 5, n, 3, i), e = coef(B, 5, n, 4, i);
-        const double beta = b - a * g2;
-        const double alpha = c - a * d2 - beta * g1;
-        if (!finite_nonzero(alpha)) {
-            *bad = i;
-            return SBS_ERR_ZERO_PIVOT;
-        }
-        const double gamma = (d - beta * d1) / alpha;
-        const double delta = e / alpha;
-        rows[i] = {a / alpha, beta / alpha, 1.0 / alpha, gamma, delta, 0.0, 0.0, 0.0};
-        g2 = g1;
-        g1 = gamma;
-        d2 = d1;
-        d1 = delta;
-    }
-    return SBS_OK;
 }
 
 template <typename Row32, typename Row64>
@@ -151,21 +103,23 @@ sbs_status sbs_factor_shared_lhs(int32_t kind, int64_t n, const double *bands, s
     h->rows = (n + kRowPad - 1) / kRowPad * kRowPad;
     sbs_status st;
     try {
+        auto cf = [&](int k, int64_t i) { return coef(bands, kind, n, k, i); };
         if (kind == SBS_TRI) {
             std::vector<TriRow<double>> r(n);
-            st = factor_tri(bands, n, r, &bad);
+            st = factor_tri_rows(n, cf, r.data(), &bad) ? SBS_OK : SBS_ERR_ZERO_PIVOT;
             if (st == SBS_OK) st = upload<TriRow<double>, TriRow<float>>(h, r, bands);
         } else {
             std::vector<PentaRow<double>> r(n);
-            st = factor_penta(bands, n, r, &bad);
+            st = factor_penta_rows(n, cf, r.data(), &bad) ? SBS_OK : SBS_ERR_ZERO_PIVOT;
             if (st == SBS_OK) st = upload<PentaRow<double>, PentaRow<float>>(h, r, bands);
         }
+        if (st == SBS_OK) st = build_partitions(h, bands);
     } catch (const std::bad_alloc &) {
         st = SBS_ERR_NO_MEMORY;
     }
     if (st != SBS_OK) {
         if (bad_row) *bad_row = bad;
-        delete h;
+        sbs_release(h);
         return st;
     }
     *out = h;
@@ -176,6 +130,7 @@ sbs_status sbs_release(sbs_handle h) {
     if (!h) return SBS_OK;
     sbs_status st = SBS_OK;
     if (h->dev && hipFree(h->dev) != hipSuccess) st = SBS_ERR_DEVICE;
+    if (h->pdev && hipFree(h->pdev) != hipSuccess) st = SBS_ERR_DEVICE;
     delete h;
     return st;
 }
@@ -191,7 +146,7 @@ sbs_status sbs_handle_info(sbs_handle h, int32_t *kind, int64_t *n, int64_t *dev
 sbs_status sbs_solve_batch_variant(sbs_handle h, void *rhs, int64_t m, int32_t dtype, int32_t variant,
                                    void *stream) {
     if (!h || m < 0 || (dtype != SBS_F64 && dtype != SBS_F32)) return SBS_ERR_INVALID_ARG;
-    if (variant < SBS_VARIANT_AUTO || variant > SBS_VARIANT_STREAM) return SBS_ERR_INVALID_ARG;
+    if (variant < SBS_VARIANT_AUTO || variant > SBS_VARIANT_PARTITION) return SBS_ERR_INVALID_ARG;
     if (variant == SBS_VARIANT_RESIDENT && h->n > 64) return SBS_ERR_INVALID_ARG;
     if (m == 0) return SBS_OK;
     if (!rhs || !aligned(rhs, dtype == SBS_F64 ? 8 : 4)) return SBS_ERR_INVALID_ARG;
@@ -199,8 +154,23 @@ sbs_status sbs_solve_batch_variant(sbs_handle h, void *rhs, int64_t m, int32_t d
     if (variant == SBS_VARIANT_CHUNKED && chunked_lds_bytes(h, dtype == SBS_F64 ? 0 : 1) > kMaxLdsBytes)
         return SBS_ERR_INVALID_ARG;
     const int t = dtype == SBS_F64 ? 0 : 1;
-    hipError_t e = launch_sweep(h, variant, t, t, t, rhs, rhs, m, static_cast<hipStream_t>(stream));
+    hipError_t e;
+    PartChoice pc;
+    const bool part = choose_partition(h, t, m, &pc);
+    if (variant == SBS_VARIANT_PARTITION && !part) return SBS_ERR_INVALID_ARG;
+    if (variant == SBS_VARIANT_PARTITION || (variant == SBS_VARIANT_AUTO && part))
+        e = launch_partition(h, pc, t, t, t, rhs, rhs, m, static_cast<hipStream_t>(stream));
+    else
+        e = launch_sweep(h, variant, t, t, t, rhs, rhs, m, static_cast<hipStream_t>(stream));
     return e == hipSuccess ? SBS_OK : SBS_ERR_DEVICE;
+}
+
+sbs_status sbs_auto_variant(sbs_handle h, int64_t m, int32_t dtype, int32_t *variant) {
+    if (!h || !variant || m < 1 || (dtype != SBS_F64 && dtype != SBS_F32)) return SBS_ERR_INVALID_ARG;
+    const int t = dtype == SBS_F64 ? 0 : 1;
+    PartChoice pc;
+    *variant = choose_partition(h, t, m, &pc) ? SBS_VARIANT_PARTITION : choose_variant(h, t);
+    return SBS_OK;
 }
 
 sbs_status sbs_solve_batch(sbs_handle h, void *rhs, int64_t m, int32_t dtype, void *stream) {
@@ -213,8 +183,8 @@ size_t sbs_refined_workspace_bytes(sbs_handle h, int64_t m) {
     return ((size_t)h->n * (size_t)m * sizeof(float) + 255) / 256 * 256;
 }
 
-sbs_status sbs_solve_batch_refined(sbs_handle h, const float *b, double *x, int64_t m, int32_t sweeps,
-                                   void *work, size_t work_bytes, void *stream) {
+sbs_status sbs_solve_batch_refined(sbs_handle h, const float *b, double *x, int64_t m, int32_t sweeps, void *work,
+                                   size_t work_bytes, void *stream) {
     if (!h || m < 0 || sweeps < 0 || sweeps > 8) return SBS_ERR_INVALID_ARG;
     if (m == 0) return SBS_OK;
     if (!b || !x || !work || work_bytes < sbs_refined_workspace_bytes(h, m)) return SBS_ERR_INVALID_ARG;
@@ -223,6 +193,11 @@ sbs_status sbs_solve_batch_refined(sbs_handle h, const float *b, double *x, int6
     const char *bx = reinterpret_cast<const char *>(x), *bbp = reinterpret_cast<const char *>(b);
     if (bx < bbp + nb * 4 && bbp < bx + nb * 8) return SBS_ERR_INVALID_ARG;  // b and x overlap
     hipStream_t s = static_cast<hipStream_t>(stream);
+    // Fused path: one kernel keeps each block of b and x on chip through all
+    // passes (needs a partition plan).
+    PartChoice pc;
+    if (choose_partition_refine(h, m, &pc))
+        return launch_partition_refine(h, pc, b, x, m, sweeps, s) == hipSuccess ? SBS_OK : SBS_ERR_DEVICE;
     float *r = static_cast<float *>(work);
     // x0 = FP32 solve of b, written as FP64.
     hipError_t e = launch_sweep(h, SBS_VARIANT_AUTO, 1, 1, 0, b, x, m, s);

@@ -44,6 +44,33 @@ constexpr int kRowPad = 64;     // factor rows are padded with zero rows to a mu
 
 }  // namespace sbs
 
+namespace sbs {
+
+// Block partition of the shared matrix (several lanes per system).
+// Rows are cut into P blocks of lb rows (the last block padded with identity
+// rows).  For block p: its own factor A_p, and the spikes V_p = A_p^{-1} B_p,
+// W_p = A_p^{-1} C_p, where B_p / C_p hold the coefficients that couple the
+// block to the first h unknowns of block p+1 / the last h unknowns of block
+// p-1 (h = 1 tri, 2 penta).  With g_p = A_p^{-1} f_p every block's solution is
+//   x_p = g_p - V_p x_{p+1}[0:h] - W_p x_{p-1}[lb-h:lb],
+// and the 2h(P-1) interface unknowns (x_p bottom, x_{p+1} top for p < P-1)
+// solve a small system R z = (g interface values) whose inverse is stored.
+// Everything depends on the matrix only, so it is computed once, in FP64.
+struct PartPlan {
+    int lb = 0, P = 0, Nr = 0;
+    bool ok = false;
+    // Device arrays, each [fac | spk | rinv] contiguous and 16-byte aligned:
+    //   fac: P*lb factor rows of the blocks (TriRow/PentaRow)
+    //   spk: P*lb rows of {V[0..h), W[0..h)}
+    //   rinv: Nr*Nr, row-major
+    void *blob64 = nullptr, *blob32 = nullptr;
+    size_t fac_bytes64 = 0, spk_bytes64 = 0, rinv_bytes64 = 0;
+    size_t fac_bytes32 = 0, spk_bytes32 = 0, rinv_bytes32 = 0;
+};
+constexpr int kPartLbs[3] = {16, 32, 64};
+
+}  // namespace sbs
+
 struct sbs_lhs {
     int32_t kind = 0;
     int64_t n = 0;
@@ -52,6 +79,8 @@ struct sbs_lhs {
     void *fac64 = nullptr;      // TriRow<double>[rows] or PentaRow<double>[rows]
     void *fac32 = nullptr;      // TriRow<float>[rows]  or PentaRow<float>[rows]
     sbs::BandRow *bands = nullptr;  // BandRow[rows]
+    void *pdev = nullptr;       // partition data (one allocation for all plans)
+    sbs::PartPlan part[3];      // block lengths 16, 32, 64
     int64_t device_bytes = 0;
     int device = 0;
 };
@@ -84,7 +113,22 @@ hipError_t launch_transpose(const void *src, void *dst, int64_t rows, int64_t co
 // needs (tc: 0 = f64, 1 = f32).
 int choose_variant(const sbs_lhs *h, int tc);
 size_t chunked_lds_bytes(const sbs_lhs *h, int tc);
-constexpr size_t kMaxLdsBytes = 64 * 1024;
+constexpr size_t kMaxLdsBytes = 64 * 1024;        // LDS budget of the chunked variant (one wave)
+constexpr size_t kMaxPartLdsBytes = 160 * 1024;   // LDS one workgroup may allocate on gfx950
+
+// Partitioned solve (SBS_VARIANT_PARTITION): choose a plan and systems per
+// workgroup for m systems; returns false if no plan fits.
+struct PartChoice {
+    int plan = -1, S = 0, threads = 0;
+    size_t lds = 0;
+};
+bool choose_partition(const sbs_lhs *h, int tc, int64_t m, PartChoice *out);
+hipError_t launch_partition(const sbs_lhs *h, const PartChoice &c, int tc, int tin, int tout, const void *in,
+                            void *out, int64_t m, hipStream_t stream);
+sbs_status build_partitions(sbs_lhs *h, const double *bands);
+bool choose_partition_refine(const sbs_lhs *h, int64_t m, PartChoice *out);
+hipError_t launch_partition_refine(const sbs_lhs *h, const PartChoice &c, const float *b, double *x, int64_t m,
+                                   int sweeps, hipStream_t stream);
 
 // Serving: heterogeneous tile launches (see server.cpp).
 struct Tile {

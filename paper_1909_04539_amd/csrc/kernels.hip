@@ -7,6 +7,7 @@
 // coalesced 512-byte (FP64) access; the shared factor row i is the same for
 // every lane and is read with wave-uniform scalar loads.  Each workgroup is
 // exactly one wavefront.
+#include <algorithm>
 #include <type_traits>
 
 #include "internal.h"
@@ -456,6 +457,246 @@ __global__ __launch_bounds__(kWave) void k_sweep(const typename Rec<KIND, T>::Ro
 }
 
 // ---------------------------------------------------------------------------
+// Partitioned solve: several lanes per system.  A workgroup holds S systems
+// times P blocks (lane l: block p = l / S, system s = l % S).  Every lane
+// loads its block's lb rows of its system (for each block, S consecutive
+// systems of a row are contiguous, so the accesses stay whole cache lines),
+// solves its block with the block's own factor, publishes the top and bottom
+// values, and after one barrier computes the interface unknowns it needs --
+// the first h unknowns of block p+1 and the last h of block p-1 -- as dot
+// products with rows of the stored inverse of the interface system; then
+// x = g - V xt - W xb and one store.  Each right-hand side crosses HBM once in
+// and once out.  The block factors, spikes and inverse (shared by every
+// system) are copied into LDS once per persistent workgroup.
+
+template <int KIND, typename T, int L>
+__device__ __forceinline__ void bwd_regs(const typename Rec<KIND, T>::Row *__restrict__ fr, T (&buf)[L],
+                                         typename Rec<KIND, T>::Bwd &bs) {
+    using R = Rec<KIND, T>;
+    constexpr int G = L < kGroup ? L : kGroup, NG = L / G;
+    typename R::BC c[2][G];
+#pragma unroll
+    for (int u = 0; u < G; ++u) c[(NG - 1) & 1][u] = R::bc(fr, L - 1 - u);
+#pragma unroll
+    for (int g = NG - 1; g >= 0; --g) {
+        if (g > 0) {
+#pragma unroll
+            for (int u = 0; u < G; ++u) c[(g - 1) & 1][u] = R::bc(fr, g * G - 1 - u);
+        }
+#pragma unroll
+        for (int u = 0; u < G; ++u) {
+            const int t = g * G + G - 1 - u;
+            buf[t] = R::bwd(c[g & 1][u], buf[t], bs);
+        }
+        pin(bs.x1);
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ T ldot(const T *a, const T *b, int n) {
+    T s0 = T(0), s1 = T(0);
+    int k = 0;
+    for (; k + 1 < n; k += 2) {
+        s0 = fma(a[k], b[k], s0);
+        s1 = fma(a[k + 1], b[k + 1], s1);
+    }
+    if (k < n) s0 = fma(a[k], b[k], s0);
+    return s0 + s1;
+}
+
+// Interface step of the partitioned solve: publishes this block's interface
+// values and computes, from the stored inverse of the interface system, the
+// first H unknowns of block p+1 (xt) and the last H of block p-1 (xb); the
+// block's solution is then x = g - V xt - W xb.
+template <int KIND, typename T, int LB>
+__device__ __forceinline__ void part_interface(const T (&x)[LB], T *red, const T *rt, const T *rb, int p, int P,
+                                               int Nr, T (&xt)[KIND / 2], T (&xb)[KIND / 2]) {
+    constexpr int H = KIND / 2;
+    if (p <= P - 2) {
+#pragma unroll
+        for (int c = 0; c < H; ++c) red[2 * H * p + c] = x[LB - H + c];
+    }
+    if (p >= 1) {
+#pragma unroll
+        for (int c = 0; c < H; ++c) red[2 * H * (p - 1) + H + c] = x[c];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < H; ++c) {
+        xt[c] = p <= P - 2 ? ldot(rt + c * Nr, red, Nr) : T(0);
+        xb[c] = p >= 1 ? ldot(rb + c * Nr, red, Nr) : T(0);
+    }
+    __syncthreads();  // red is rewritten next time
+}
+
+template <int KIND, typename T>
+__device__ __forceinline__ T part_correct(T v, const T *spt, const T (&xt)[KIND / 2], const T (&xb)[KIND / 2]) {
+    constexpr int H = KIND / 2;
+#pragma unroll
+    for (int c = 0; c < H; ++c) v = fma(-spt[c], xt[c], v);
+#pragma unroll
+    for (int c = 0; c < H; ++c) v = fma(-spt[H + c], xb[c], v);
+    return v;
+}
+
+// Copies [fac | spk | rinv] (and anything after it in `extra`) into LDS.
+__device__ __forceinline__ void stage_blob(unsigned char *lds, const unsigned char *blob, int bytes) {
+    typedef unsigned int U4 __attribute__((ext_vector_type(4)));
+    const U4 *src = reinterpret_cast<const U4 *>(blob);
+    U4 *dst = reinterpret_cast<U4 *>(lds);
+    for (int i = threadIdx.x; i < bytes / 16; i += blockDim.x) dst[i] = src[i];
+}
+
+template <int KIND, typename T, typename Tin, typename Tout, int LB, int MAXT>
+__global__ __launch_bounds__(MAXT) void k_part(const unsigned char *__restrict__ blob, int fac_bytes, int spk_bytes,
+                                               int rinv_bytes, int n, int P, int Nr, int S, int ngroups,
+                                               const Tin *in, Tout *out, int64_t m) {
+    using R = Rec<KIND, T>;
+    using Row = typename R::Row;
+    constexpr int H = KIND / 2;
+    extern __shared__ __align__(16) unsigned char lds[];
+    stage_blob(lds, blob, fac_bytes + spk_bytes + rinv_bytes);
+    const Row *lfac = reinterpret_cast<const Row *>(lds);
+    const T *lspk = reinterpret_cast<const T *>(lds + fac_bytes);
+    const T *lrinv = reinterpret_cast<const T *>(lds + fac_bytes + spk_bytes);
+    T *lred = reinterpret_cast<T *>(lds + fac_bytes + spk_bytes + rinv_bytes);
+    const int ldr = Nr + 1;  // odd stride: the systems' rows fall in different banks
+    __syncthreads();
+
+    const int l = threadIdx.x, p = l / S, s = l - p * S;
+    const int r0 = p * LB;
+    const Row *fr = lfac + r0;
+    const T *sp = lspk + r0 * 2 * H;
+    T *red = lred + s * ldr;
+    const T *rt = lrinv + (2 * H * p + H) * Nr;        // rows of x_{p+1}[0:H]
+    const T *rb = lrinv + (2 * H * (p - 1)) * Nr;      // rows of x_{p-1}[lb-H:lb]
+    const int64_t rs = m;
+    for (int g = blockIdx.x; g < ngroups; g += gridDim.x) {
+        const int64_t j = min((int64_t)g * S + s, m - 1);
+        const Tin *src = in + (int64_t)r0 * rs + j;
+        T x[LB];
+        if (r0 + LB <= n) {
+#pragma unroll
+            for (int t = 0; t < LB; ++t) x[t] = static_cast<T>(src[(int64_t)t * rs]);
+        } else {
+#pragma unroll
+            for (int t = 0; t < LB; ++t) x[t] = (r0 + t < n) ? static_cast<T>(src[(int64_t)t * rs]) : T(0);
+        }
+        typename R::Fwd st;
+        fwd_chunk<KIND, T, LB>(fr, x, st);
+        typename R::Bwd bs;
+        bwd_regs<KIND, T, LB>(fr, x, bs);
+        T xt[H], xb[H];
+        part_interface<KIND, T, LB>(x, red, rt, rb, p, P, Nr, xt, xb);
+        Tout *dst = out + (int64_t)r0 * rs + j;
+#pragma unroll
+        for (int t = 0; t < LB; ++t) {
+            const T v = part_correct<KIND, T>(x[t], sp + t * 2 * H, xt, xb);
+            if (r0 + t < n) dst[(int64_t)t * rs] = static_cast<Tout>(v);
+        }
+    }
+}
+
+// Mixed precision on the partition, fused: each lane keeps its block of the
+// FP32 right-hand side b and of the FP64 solution x in registers through the
+// FP32 solve, every residual r = b - A x (FP64, original bands, neighbouring
+// blocks' values exchanged through LDS), the FP32 correction solves and the
+// FP64 updates; b is read once and x written once (12 bytes per unknown).
+template <int KIND, int LB, int MAXT>
+__global__ __launch_bounds__(MAXT) void k_part_refine(const unsigned char *__restrict__ blob, int fac_bytes,
+                                                      int spk_bytes, int rinv_bytes,
+                                                      const BandRow *__restrict__ bands, int n, int P, int Nr, int S,
+                                                      int ngroups, int sweeps, const float *b32, double *x64,
+                                                      int64_t m) {
+    using R = Rec<KIND, float>;
+    using Row = typename R::Row;
+    constexpr int H = KIND / 2;
+    extern __shared__ __align__(16) unsigned char lds[];
+    const int blob_bytes = fac_bytes + spk_bytes + rinv_bytes;
+    const int npad = P * LB;
+    stage_blob(lds, blob, blob_bytes);
+    BandRow *lband = reinterpret_cast<BandRow *>(lds + blob_bytes);
+    for (int i = threadIdx.x; i < npad; i += blockDim.x) lband[i] = bands[i];
+    const Row *lfac = reinterpret_cast<const Row *>(lds);
+    const float *lspk = reinterpret_cast<const float *>(lds + fac_bytes);
+    const float *lrinv = reinterpret_cast<const float *>(lds + fac_bytes + spk_bytes);
+    unsigned char *after = lds + blob_bytes + npad * sizeof(BandRow);
+    const int ldr = Nr + 1;
+    float *lred = reinterpret_cast<float *>(after);
+    double *lnb = reinterpret_cast<double *>(after + ((S * ldr * 4 + 15) / 16) * 16);  // [S][P][2H]
+    __syncthreads();
+
+    const int l = threadIdx.x, p = l / S, s = l - p * S;
+    const int r0 = p * LB;
+    const Row *fr = lfac + r0;
+    const float *sp = lspk + r0 * 2 * H;
+    float *red = lred + s * ldr;
+    const float *rt = lrinv + (2 * H * p + H) * Nr;
+    const float *rb = lrinv + (2 * H * (p - 1)) * Nr;
+    double *nb = lnb + (int64_t)s * P * 2 * H;
+    const BandRow *br = lband + r0;
+    const int64_t rs = m;
+    for (int g = blockIdx.x; g < ngroups; g += gridDim.x) {
+        const int64_t j = min((int64_t)g * S + s, m - 1);
+        const float *src = b32 + (int64_t)r0 * rs + j;
+        float b[LB], w[LB];
+        double x[LB];
+#pragma unroll
+        for (int t = 0; t < LB; ++t) b[t] = (r0 + t < n) ? src[(int64_t)t * rs] : 0.0f;
+#pragma unroll
+        for (int t = 0; t < LB; ++t) w[t] = b[t];
+        {
+            typename R::Fwd st;
+            fwd_chunk<KIND, float, LB>(fr, w, st);
+            typename R::Bwd bs;
+            bwd_regs<KIND, float, LB>(fr, w, bs);
+            float xt[H], xb[H];
+            part_interface<KIND, float, LB>(w, red, rt, rb, p, P, Nr, xt, xb);
+#pragma unroll
+            for (int t = 0; t < LB; ++t) x[t] = (double)part_correct<KIND, float>(w[t], sp + t * 2 * H, xt, xb);
+        }
+        for (int k = 0; k < sweeps; ++k) {
+            // neighbours: the last H values of block p-1 and the first H of block p+1
+#pragma unroll
+            for (int c = 0; c < H; ++c) {
+                nb[p * 2 * H + c] = x[c];
+                nb[p * 2 * H + H + c] = x[LB - H + c];
+            }
+            __syncthreads();
+            double win[LB + 2 * H];
+#pragma unroll
+            for (int c = 0; c < H; ++c) {
+                win[c] = p >= 1 ? nb[(p - 1) * 2 * H + H + c] : 0.0;
+                win[LB + H + c] = p <= P - 2 ? nb[(p + 1) * 2 * H + c] : 0.0;
+            }
+#pragma unroll
+            for (int t = 0; t < LB; ++t) win[H + t] = x[t];
+            __syncthreads();  // nb is rewritten next sweep
+#pragma unroll
+            for (int t = 0; t < LB; ++t) {
+                const BandRow &rw = br[t];
+                double ax = rw.c[0] * win[t];
+#pragma unroll
+                for (int q = 1; q < 2 * H + 1; ++q) ax = fma(rw.c[q], win[t + q], ax);
+                w[t] = (float)((double)b[t] - ax);
+            }
+            typename R::Fwd st;
+            fwd_chunk<KIND, float, LB>(fr, w, st);
+            typename R::Bwd bs;
+            bwd_regs<KIND, float, LB>(fr, w, bs);
+            float xt[H], xb[H];
+            part_interface<KIND, float, LB>(w, red, rt, rb, p, P, Nr, xt, xb);
+#pragma unroll
+            for (int t = 0; t < LB; ++t) x[t] += (double)part_correct<KIND, float>(w[t], sp + t * 2 * H, xt, xb);
+        }
+        double *dst = x64 + (int64_t)r0 * rs + j;
+#pragma unroll
+        for (int t = 0; t < LB; ++t)
+            if (r0 + t < n) dst[(int64_t)t * rs] = x[t];
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Mixed-precision passes.  Lane per system again; a lane walks its column
 // with a window of 2H+1 solution values (H = 1 tri, 2 penta).
 //  MODE 0: r_i = fl32(b_i - (A x)_i)
@@ -759,6 +1000,162 @@ hipError_t launch_sweep(const sbs_lhs *h, int variant, int tc, int tin, int tout
     if (tc == 1 && tin == 1 && tout == 0)
         return dispatch_kind<float, float, double>(h, mode, h->fac32, in, out, m, stream);
     return hipErrorInvalidValue;
+}
+
+namespace {
+template <int KIND, typename T, int LB>
+hipError_t go_part(const sbs_lhs *h, const PartChoice &c, const void *in, void *out, int64_t m, hipStream_t s) {
+    constexpr int MAXT = (LB == 64 && sizeof(T) == 8) ? 512 : 1024;
+    const PartPlan &pp = h->part[c.plan];
+    const bool f64 = sizeof(T) == 8;
+    auto kern = k_part<KIND, T, T, T, LB, MAXT>;
+    static bool attr = false;
+    if (!attr) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxPartLdsBytes);
+        if (e != hipSuccess) return e;
+        attr = true;
+    }
+    if (c.threads > MAXT) return hipErrorInvalidValue;
+    const int ngroups = (int)((m + c.S - 1) / c.S);
+    int cus = 256;
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, h->device);
+    const int per_cu = (int)std::max<size_t>(1, kMaxPartLdsBytes / c.lds);
+    const int grid = std::min(ngroups, cus * per_cu);
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(c.threads), c.lds, s,
+                       static_cast<const unsigned char *>(f64 ? pp.blob64 : pp.blob32),
+                       (int)(f64 ? pp.fac_bytes64 : pp.fac_bytes32), (int)(f64 ? pp.spk_bytes64 : pp.spk_bytes32),
+                       (int)(f64 ? pp.rinv_bytes64 : pp.rinv_bytes32), (int)h->n, pp.P, pp.Nr, c.S, ngroups,
+                       static_cast<const T *>(in), static_cast<T *>(out), m);
+    return hipGetLastError();
+}
+
+template <int KIND, typename T>
+hipError_t go_part_lb(const sbs_lhs *h, const PartChoice &c, const void *in, void *out, int64_t m, hipStream_t s) {
+    switch (h->part[c.plan].lb) {
+        case 16: return go_part<KIND, T, 16>(h, c, in, out, m, s);
+        case 32: return go_part<KIND, T, 32>(h, c, in, out, m, s);
+        default: return go_part<KIND, T, 64>(h, c, in, out, m, s);
+    }
+}
+}  // namespace
+
+namespace {
+template <int KIND, int LB>
+hipError_t go_part_refine(const sbs_lhs *h, const PartChoice &c, const float *b, double *x, int64_t m, int sweeps,
+                          hipStream_t s) {
+    constexpr int MAXT = 512;
+    const PartPlan &pp = h->part[c.plan];
+    auto kern = k_part_refine<KIND, LB, MAXT>;
+    static bool attr = false;
+    if (!attr) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxPartLdsBytes);
+        if (e != hipSuccess) return e;
+        attr = true;
+    }
+    if (c.threads > MAXT) return hipErrorInvalidValue;
+    const int ngroups = (int)((m + c.S - 1) / c.S);
+    int cus = 256;
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, h->device);
+    const int per_cu = (int)std::max<size_t>(1, kMaxPartLdsBytes / c.lds);
+    const int grid = std::min(ngroups, cus * per_cu);
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(c.threads), c.lds, s, static_cast<const unsigned char *>(pp.blob32),
+                       (int)pp.fac_bytes32, (int)pp.spk_bytes32, (int)pp.rinv_bytes32, h->bands, (int)h->n, pp.P,
+                       pp.Nr, c.S, ngroups, sweeps, b, x, m);
+    return hipGetLastError();
+}
+}  // namespace
+
+// Plan for the fused mixed-precision kernel: blocks of 16 or 32 rows (the
+// lane keeps b, x and a work copy of its block in registers), at most 512
+// threads, and LDS for the FP32 plan, the original bands, the interface
+// values and the neighbour exchange.
+bool choose_partition_refine(const sbs_lhs *h, int64_t m, PartChoice *out) {
+    const int H = h->kind / 2;
+    PartChoice best;
+    int64_t best_waves = -1;
+    for (int q = 1; q >= 0; --q) {  // lb 32, then 16
+        const PartPlan &pp = h->part[q];
+        if (!pp.ok || m < 1) continue;
+        int S = 64;
+        while (S > 16 && S * pp.P > 512) S /= 2;
+        if (S * pp.P > 512) continue;
+        const size_t npad = (size_t)pp.P * pp.lb;
+        const size_t lds = pp.fac_bytes32 + pp.spk_bytes32 + pp.rinv_bytes32 + npad * sizeof(BandRow) +
+                           ((size_t)S * (pp.Nr + 1) * 4 + 15) / 16 * 16 + (size_t)S * pp.P * 2 * H * 8;
+        if (lds > kMaxPartLdsBytes) continue;
+        const int64_t groups = (m + S - 1) / S;
+        const int64_t waves = std::min<int64_t>(groups * ((S * pp.P + kWave - 1) / kWave), 4096);
+        if (waves > best_waves) {
+            best_waves = waves;
+            best.plan = q;
+            best.S = S;
+            best.threads = S * pp.P;
+            best.lds = lds;
+        }
+    }
+    if (best.plan < 0) return false;
+    *out = best;
+    return true;
+}
+
+hipError_t launch_partition_refine(const sbs_lhs *h, const PartChoice &c, const float *b, double *x, int64_t m,
+                                   int sweeps, hipStream_t stream) {
+    if (m <= 0) return hipSuccess;
+    const int lb = h->part[c.plan].lb;
+    if (h->kind == SBS_TRI)
+        return lb == 16 ? go_part_refine<SBS_TRI, 16>(h, c, b, x, m, sweeps, stream)
+                        : go_part_refine<SBS_TRI, 32>(h, c, b, x, m, sweeps, stream);
+    return lb == 16 ? go_part_refine<SBS_PENTA, 16>(h, c, b, x, m, sweeps, stream)
+                    : go_part_refine<SBS_PENTA, 32>(h, c, b, x, m, sweeps, stream);
+}
+
+bool choose_partition(const sbs_lhs *h, int tc, int64_t m, PartChoice *out) {
+    const size_t elem = tc == 0 ? 8 : 4;
+    int cus = 256;
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, h->device);
+    PartChoice best;
+    int64_t best_waves = -1;
+    for (int q = 2; q >= 0; --q) {  // largest block first: fewest interfaces
+        const PartPlan &pp = h->part[q];
+        if (!pp.ok || m < 1) continue;
+        const int maxt = (pp.lb == 64 && elem == 8) ? 512 : 1024;
+        int S = 64;
+        while (S > 16 && S * pp.P > maxt) S /= 2;
+        if (S * pp.P > maxt) continue;
+        const size_t blob = tc == 0 ? pp.fac_bytes64 + pp.spk_bytes64 + pp.rinv_bytes64
+                                    : pp.fac_bytes32 + pp.spk_bytes32 + pp.rinv_bytes32;
+        auto lds_for = [&](int s) { return blob + ((size_t)s * (pp.Nr + 1) * elem + 15) / 16 * 16; };
+        if (lds_for(S) > kMaxPartLdsBytes) continue;
+        // At least 16 systems per workgroup keeps every row access a whole
+        // 128-byte line; with few systems, narrower workgroups (down to 4
+        // systems) spread the batch over more compute units instead.
+        while (S > 4 && (m + S - 1) / S < cus) S /= 2;
+        const int64_t groups = (m + S - 1) / S;
+        const int64_t waves = std::min<int64_t>(groups * ((S * pp.P + kWave - 1) / kWave), 4096);
+        if (waves > best_waves) {
+            best_waves = waves;
+            best.plan = q;
+            best.S = S;
+            best.threads = S * pp.P;
+            best.lds = lds_for(S);
+        }
+    }
+    if (best.plan < 0) return false;
+    *out = best;
+    return true;
+}
+
+hipError_t launch_partition(const sbs_lhs *h, const PartChoice &c, int tc, int tin, int tout, const void *in, void *out,
+                            int64_t m, hipStream_t stream) {
+    if (m <= 0) return hipSuccess;
+    if (tc != tin || tc != tout) return hipErrorInvalidValue;
+    if (h->kind == SBS_TRI)
+        return tc == 0 ? go_part_lb<SBS_TRI, double>(h, c, in, out, m, stream)
+                       : go_part_lb<SBS_TRI, float>(h, c, in, out, m, stream);
+    return tc == 0 ? go_part_lb<SBS_PENTA, double>(h, c, in, out, m, stream)
+                   : go_part_lb<SBS_PENTA, float>(h, c, in, out, m, stream);
 }
 
 hipError_t launch_refine_step(const sbs_lhs *h, int mode, const float *b, double *x,

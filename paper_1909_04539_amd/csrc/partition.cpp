@@ -1,0 +1,232 @@
+// Host side of the partitioned solve: block factors, spikes and the inverse
+// of the interface system, all in FP64, computed once per shared matrix.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <functional>
+#include <vector>
+
+#include "factor_rows.h"
+#include "internal.h"
+
+namespace sbs {
+namespace {
+
+constexpr int kMaxBlocks = 64;
+constexpr int kMaxInterface = 90;  // interface unknowns: the FP64 inverse stays under 64 KB of LDS
+
+size_t align16(size_t v) { return (v + 15) / 16 * 16; }
+
+// Gauss-Jordan inverse with partial pivoting, in place (row-major n x n).
+bool invert(std::vector<double> &a, int n) {
+    std::vector<double> inv((size_t)n * n, 0.0);
+    for (int i = 0; i < n; ++i) inv[(size_t)i * n + i] = 1.0;
+    for (int c = 0; c < n; ++c) {
+        int piv = c;
+        for (int r = c + 1; r < n; ++r)
+            if (std::fabs(a[(size_t)r * n + c]) > std::fabs(a[(size_t)piv * n + c])) piv = r;
+        const double pv = a[(size_t)piv * n + c];
+        if (!std::isfinite(pv) || std::fabs(pv) < 1e-300) return false;
+        if (piv != c)
+            for (int k = 0; k < n; ++k) {
+                std::swap(a[(size_t)piv * n + k], a[(size_t)c * n + k]);
+                std::swap(inv[(size_t)piv * n + k], inv[(size_t)c * n + k]);
+            }
+        const double s = 1.0 / pv;
+        for (int k = 0; k < n; ++k) {
+            a[(size_t)c * n + k] *= s;
+            inv[(size_t)c * n + k] *= s;
+        }
+        for (int r = 0; r < n; ++r) {
+            if (r == c) continue;
+            const double f = a[(size_t)r * n + c];
+            if (f == 0.0) continue;
+            for (int k = 0; k < n; ++k) {
+                a[(size_t)r * n + k] -= f * a[(size_t)c * n + k];
+                inv[(size_t)r * n + k] -= f * inv[(size_t)c * n + k];
+            }
+        }
+    }
+    for (double v : inv)
+        if (!std::isfinite(v)) return false;
+    a.swap(inv);
+    return true;
+}
+
+struct HostPlan {
+    int lb = 0, P = 0, Nr = 0;
+    std::vector<unsigned char> fac;  // P*lb FP64 rows
+    std::vector<double> spk;         // P*lb*2h
+    std::vector<double> rinv;        // Nr*Nr
+};
+
+template <typename Row, typename FactorFn, typename SolveFn>
+bool build_plan(int kind, int64_t n, const double *bands, int lb, FactorFn factor, SolveFn solve, HostPlan &hp) {
+    const int h = kind / 2;
+    const int P = (int)((n + lb - 1) / lb);
+    if (P > kMaxBlocks || lb < 2 * h || 2 * h * (P - 1) > kMaxInterface) return false;
+    const int64_t npad = (int64_t)P * lb;
+    std::vector<Row> rows(npad);
+    std::vector<double> spk((size_t)npad * 2 * h, 0.0);
+    // Coefficient k of global row i restricted to block p (identity past n).
+    auto local = [&](int p, int k, int64_t i) -> double {
+        if (i >= n) return k == h ? 1.0 : 0.0;
+        const int64_t col = i + k - h;
+        if (col < (int64_t)p * lb || col >= (int64_t)(p + 1) * lb || col >= n) return 0.0;
+        return bands[(int64_t)k * n + i];
+    };
+    std::vector<double> v(lb);
+    for (int p = 0; p < P; ++p) {
+        const int64_t r0 = (int64_t)p * lb;
+        int64_t bad = -1;
+        if (!factor(lb, [&](int k, int64_t t) { return local(p, k, r0 + t); }, rows.data() + r0, &bad)) return false;
+        // Right spike columns: coupling of row r0+t to column r0+lb+c.
+        for (int c = 0; c < h; ++c) {
+            for (int t = 0; t < lb; ++t) {
+                const int64_t i = r0 + t, col = r0 + lb + c;
+                const int k = (int)(col - i + h);
+                v[t] = (i < n && col < n && k >= 0 && k < kind) ? bands[(int64_t)k * n + i] : 0.0;
+            }
+            solve(lb, rows.data() + r0, v.data());
+            for (int t = 0; t < lb; ++t) spk[(size_t)(r0 + t) * 2 * h + c] = v[t];
+        }
+        // Left spike columns: coupling of row r0+t to column r0-h+c.
+        for (int c = 0; c < h; ++c) {
+            for (int t = 0; t < lb; ++t) {
+                const int64_t i = r0 + t, col = r0 - h + c;
+                const int k = (int)(col - i + h);
+                v[t] = (p > 0 && i < n && k >= 0 && k < kind) ? bands[(int64_t)k * n + i] : 0.0;
+            }
+            solve(lb, rows.data() + r0, v.data());
+            for (int t = 0; t < lb; ++t) spk[(size_t)(r0 + t) * 2 * h + h + c] = v[t];
+        }
+    }
+    // Interface system.  Unknown order: pair q = 0..P-2 holds
+    // (bottom h of block q, top h of block q+1).
+    const int Nr = 2 * h * (P - 1);
+    std::vector<double> R((size_t)Nr * Nr, 0.0);
+    auto ibot = [&](int p, int c) { return 2 * h * p + c; };          // p in [0, P-2]
+    auto itop = [&](int p, int c) { return 2 * h * (p - 1) + h + c; };  // p in [1, P-1]
+    auto V = [&](int p, int t, int c) { return spk[(size_t)((int64_t)p * lb + t) * 2 * h + c]; };
+    auto Wt = [&](int p, int t, int c) { return spk[(size_t)((int64_t)p * lb + t) * 2 * h + h + c]; };
+    for (int p = 0; p < P; ++p) {
+        for (int c = 0; c < h; ++c) {
+            // equation of block p's local row t, for its interface rows
+            for (int side = 0; side < 2; ++side) {
+                int row, t;
+                if (side == 0) {  // bottom rows, needed for p <= P-2
+                    if (p > P - 2) continue;
+                    row = ibot(p, c);
+                    t = lb - h + c;
+                } else {  // top rows, needed for p >= 1
+                    if (p < 1) continue;
+                    row = itop(p, c);
+                    t = c;
+                }
+                R[(size_t)row * Nr + row] += 1.0;
+                for (int c2 = 0; c2 < h; ++c2) {
+                    if (p <= P - 2) R[(size_t)row * Nr + itop(p + 1, c2)] += V(p, t, c2);
+                    if (p >= 1) R[(size_t)row * Nr + ibot(p - 1, c2)] += Wt(p, t, c2);
+                }
+            }
+        }
+    }
+    if (Nr > 0 && !invert(R, Nr)) return false;
+    hp.lb = lb;
+    hp.P = P;
+    hp.Nr = Nr;
+    hp.fac.resize(sizeof(Row) * npad);
+    std::memcpy(hp.fac.data(), rows.data(), hp.fac.size());
+    hp.spk.swap(spk);
+    hp.rinv.swap(R);
+    return true;
+}
+
+template <typename Row32, typename Row64>
+Row32 narrow_row(const Row64 &r);
+template <>
+TriRow<float> narrow_row(const TriRow<double> &r) {
+    return {(float)r.a_s, (float)r.chat, (float)r.inv, 0.0f};
+}
+template <>
+PentaRow<float> narrow_row(const PentaRow<double> &r) {
+    return {(float)r.eps_s, (float)r.beta_s, (float)r.inv, (float)r.gamma, (float)r.delta, 0.f, 0.f, 0.f};
+}
+
+// Serialise one plan as [fac | spk | rinv] in FP64 and in FP32.
+template <typename Row64, typename Row32>
+void serialise(const HostPlan &hp, std::vector<unsigned char> &b64, std::vector<unsigned char> &b32, PartPlan &pp) {
+    const size_t nrow = hp.fac.size() / sizeof(Row64);
+    pp.fac_bytes64 = align16(hp.fac.size());
+    pp.spk_bytes64 = align16(hp.spk.size() * 8);
+    pp.rinv_bytes64 = align16(hp.rinv.size() * 8);
+    b64.assign(pp.fac_bytes64 + pp.spk_bytes64 + pp.rinv_bytes64, 0);
+    std::memcpy(b64.data(), hp.fac.data(), hp.fac.size());
+    std::memcpy(b64.data() + pp.fac_bytes64, hp.spk.data(), hp.spk.size() * 8);
+    std::memcpy(b64.data() + pp.fac_bytes64 + pp.spk_bytes64, hp.rinv.data(), hp.rinv.size() * 8);
+    pp.fac_bytes32 = align16(nrow * sizeof(Row32));
+    pp.spk_bytes32 = align16(hp.spk.size() * 4);
+    pp.rinv_bytes32 = align16(hp.rinv.size() * 4);
+    b32.assign(pp.fac_bytes32 + pp.spk_bytes32 + pp.rinv_bytes32, 0);
+    const Row64 *r64 = reinterpret_cast<const Row64 *>(hp.fac.data());
+    Row32 *r32 = reinterpret_cast<Row32 *>(b32.data());
+    for (size_t i = 0; i < nrow; ++i) r32[i] = narrow_row<Row32>(r64[i]);
+    float *s32 = reinterpret_cast<float *>(b32.data() + pp.fac_bytes32);
+    for (size_t i = 0; i < hp.spk.size(); ++i) s32[i] = (float)hp.spk[i];
+    float *q32 = reinterpret_cast<float *>(b32.data() + pp.fac_bytes32 + pp.spk_bytes32);
+    for (size_t i = 0; i < hp.rinv.size(); ++i) q32[i] = (float)hp.rinv[i];
+}
+
+}  // namespace
+
+// Builds every plan that exists for this matrix.  A plan that does not exist
+// (too many blocks, a zero pivot inside a block, a singular interface
+// system) only disables the partitioned variant for that block length.
+sbs_status build_partitions(sbs_lhs *h, const double *bands) {
+    std::vector<unsigned char> b64[3], b32[3];
+    size_t total = 0;
+    for (int q = 0; q < 3; ++q) {
+        HostPlan hp;
+        const int lb = kPartLbs[q];
+        bool ok;
+        if (h->kind == SBS_TRI)
+            ok = build_plan<TriRow<double>>(h->kind, h->n, bands, lb, factor_tri_rows<std::function<double(int, int64_t)>>,
+                                            solve_tri_rows, hp);
+        else
+            ok = build_plan<PentaRow<double>>(h->kind, h->n, bands, lb,
+                                              factor_penta_rows<std::function<double(int, int64_t)>>, solve_penta_rows, hp);
+        if (!ok) continue;
+        PartPlan &pp = h->part[q];
+        if (h->kind == SBS_TRI)
+            serialise<TriRow<double>, TriRow<float>>(hp, b64[q], b32[q], pp);
+        else
+            serialise<PentaRow<double>, PentaRow<float>>(hp, b64[q], b32[q], pp);
+        pp.lb = hp.lb;
+        pp.P = hp.P;
+        pp.Nr = hp.Nr;
+        pp.ok = true;
+        total += align16(b64[q].size()) + align16(b32[q].size());
+    }
+    if (total == 0) return SBS_OK;
+    void *dev = nullptr;
+    if (hipMalloc(&dev, total) != hipSuccess) return SBS_ERR_NO_MEMORY;
+    h->pdev = dev;
+    size_t at = 0;
+    for (int q = 0; q < 3; ++q) {
+        PartPlan &pp = h->part[q];
+        if (!pp.ok) continue;
+        unsigned char *base = static_cast<unsigned char *>(dev);
+        if (hipMemcpy(base + at, b64[q].data(), b64[q].size(), hipMemcpyHostToDevice) != hipSuccess)
+            return SBS_ERR_DEVICE;
+        pp.blob64 = base + at;
+        at += align16(b64[q].size());
+        if (hipMemcpy(base + at, b32[q].data(), b32[q].size(), hipMemcpyHostToDevice) != hipSuccess)
+            return SBS_ERR_DEVICE;
+        pp.blob32 = base + at;
+        at += align16(b32[q].size());
+    }
+    h->device_bytes += (int64_t)total;
+    return SBS_OK;
+}
+
+}  // namespace sbs

@@ -211,7 +211,7 @@ bool sbs_server::launch(Slot &s) {
     for (int g = 0; g < kGroups; ++g) {
         std::stable_sort(grp[g].begin(), grp[g].end(), [](const Tile &a, const Tile &b) { return a.n > b.n; });
         offs[g] = at;
-        std::memcpy(s.host + at, grp[g].data(), grp[g].size() * sizeof(Tile));
+        if (!grp[g].empty()) std::memcpy(s.host + at, grp[g].data(), grp[g].size() * sizeof(Tile));
         at += grp[g].size() * sizeof(Tile);
     }
     std::memset(s.host, 0, kGroups * 64);

@@ -24,7 +24,7 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "sbs.h")
 
 SBS_TRI, SBS_PENTA = 3, 5
 SBS_F64, SBS_F32 = 0, 1
-VARIANT_AUTO, VARIANT_RESIDENT, VARIANT_CHUNKED, VARIANT_STREAM = 0, 1, 2, 3
+VARIANT_AUTO, VARIANT_RESIDENT, VARIANT_CHUNKED, VARIANT_STREAM, VARIANT_PARTITION = 0, 1, 2, 3, 4
 
 STATUS = {0: "SBS_OK", 1: "SBS_ERR_INVALID_ARG", 2: "SBS_ERR_ZERO_PIVOT", 3: "SBS_ERR_NONFINITE",
           4: "SBS_ERR_DEVICE", 5: "SBS_ERR_NO_MEMORY", 6: "SBS_ERR_BUDGET", 7: "SBS_ERR_NOT_FOUND",
@@ -71,6 +71,7 @@ def lib() -> ctypes.CDLL:
         "sbs_factor_shared_lhs": ([i32, i64, vp, P(vp), P(i64)], i32),
         "sbs_solve_batch": ([vp, vp, i64, i32, vp], i32),
         "sbs_solve_batch_variant": ([vp, vp, i64, i32, i32, vp], i32),
+        "sbs_auto_variant": ([vp, i64, i32, P(i32)], i32),
         "sbs_solve_batch_refined": ([vp, vp, vp, i64, i32, vp, sz, vp], i32),
         "sbs_refined_workspace_bytes": ([vp, i64], sz),
         "sbs_transpose": ([vp, vp, i64, i64, i32, vp], i32),
@@ -174,6 +175,13 @@ def sbs_solve_batch_variant(h: int, rhs: torch.Tensor, variant: int, stream=None
     _check(lib().sbs_solve_batch_variant(h, p, rhs.shape[1], _dtype_code(rhs), variant, _stream(stream)),
            "sbs_solve_batch_variant")
     return rhs
+
+
+def sbs_auto_variant(h: int, m: int, dtype: int = SBS_F64) -> int:
+    """The SBS_VARIANT_* that SBS_VARIANT_AUTO runs for m systems."""
+    v = ctypes.c_int32()
+    _check(lib().sbs_auto_variant(h, m, dtype, ctypes.byref(v)), "sbs_auto_variant")
+    return v.value
 
 
 def sbs_refined_workspace_bytes(h: int, m: int) -> int:

@@ -1,0 +1,200 @@
+// Scenarios for the serving loop's host logic, run against the CPU stand-in
+// for the device.  Usage: scenarios <mix|budget|errors|shutdown>; exit 0 on
+// success, otherwise prints what failed.
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <random>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+
+#define CHECK(c)                                                         \
+    do {                                                                 \
+        if (!(c)) {                                                      \
+            std::fprintf(stderr, "%s:%d: check failed: %s\n", __FILE__, __LINE__, #c); \
+            std::exit(1);                                                \
+        }                                                                \
+    } while (0)
+
+namespace {
+
+struct Input {
+    std::vector<double> f64;
+    std::vector<float> f32;
+    int dtype = SBS_F64;
+    int64_t n = 0, m = 0;
+    const void *ptr() const { return dtype == SBS_F64 ? (const void *)f64.data() : (const void *)f32.data(); }
+    double at(int64_t k) const { return dtype == SBS_F64 ? f64[k] : (double)f32[k]; }
+};
+
+Input make_input(std::mt19937_64 &g, int64_t n, int64_t m, int dtype) {
+    Input in;
+    in.dtype = dtype;
+    in.n = n;
+    in.m = m;
+    std::uniform_real_distribution<double> u(-1.0, 1.0);
+    if (dtype == SBS_F64) {
+        in.f64.resize(n * m);
+        for (double &v : in.f64) v = u(g);
+    } else {
+        in.f32.resize(n * m);
+        for (float &v : in.f32) v = (float)u(g);
+    }
+    return in;
+}
+
+// Every column of the result was written by its own tile, from its own input.
+bool result_matches(const double *x, const Input &in) {
+    for (int64_t k = 0; k < in.n * in.m; ++k)
+        if (x[k] != in.at(k)) return false;
+    return true;
+}
+
+struct Lhs {
+    std::vector<sbs_lhs> h;
+    std::vector<int32_t> id;
+    Lhs(sbs_server *srv, std::vector<int64_t> ns) : h(ns.size()), id(ns.size()) {
+        for (size_t k = 0; k < ns.size(); ++k) {
+            h[k] = sbs_lhs();
+            h[k].kind = k & 1 ? SBS_PENTA : SBS_TRI;
+            h[k].n = ns[k];
+            CHECK(sbs_server_register(srv, &h[k], &id[k]) == SBS_OK);
+        }
+    }
+};
+
+// Many overlapping requests of mixed size, matrix and precision, each
+// released as soon as it is done while later ones still run.
+void mix() {
+    sbs_server *srv = nullptr;
+    CHECK(sbs_server_create(64u << 20, 4, 0, &srv) == SBS_OK);
+    Lhs L(srv, {40, 77, 114, 151});
+    std::mt19937_64 g(7);
+    const int count = 600;
+    std::vector<Input> in;
+    std::vector<uint64_t> tk(count);
+    std::vector<int> which(count);
+    for (int r = 0; r < count; ++r) {
+        which[r] = (int)(g() % 4);
+        in.push_back(make_input(g, L.h[which[r]].n, 1 + (int64_t)(g() % 300), g() % 3 ? SBS_F64 : SBS_F32));
+    }
+    for (int r = 0; r < count; ++r)
+        CHECK(sbs_server_submit(srv, L.id[which[r]], in[r].ptr(), in[r].m, in[r].dtype, &tk[r]) == SBS_OK);
+    for (int r = 0; r < count; ++r) {
+        const double *x = nullptr;
+        double lat = -1;
+        CHECK(sbs_server_wait(srv, tk[r], 20000000, &x, &lat) == SBS_OK);
+        CHECK(x && lat >= 0);
+        CHECK(result_matches(x, in[r]));
+        CHECK(sbs_server_release(srv, tk[r]) == SBS_OK);
+        CHECK(sbs_server_wait(srv, tk[r], 0, &x, &lat) == SBS_ERR_NOT_FOUND);
+    }
+    sbs_server_stats st;
+    CHECK(sbs_server_stats_get(srv, &st) == SBS_OK);
+    CHECK(st.submitted == (uint64_t)count && st.completed == (uint64_t)count);
+    CHECK(st.in_flight == 0 && st.queued == 0 && st.bytes_reserved == 0);
+    CHECK(st.launches >= 1 && st.launches < (uint64_t)count);  // requests were coalesced
+    CHECK(st.p50_us > 0 && st.p99_us >= st.p50_us && st.max_us >= st.p99_us);
+    CHECK(sbs_server_destroy(srv) == SBS_OK);
+    std::printf("mix: %d requests in %lu launches\n", count, (unsigned long)st.launches);
+}
+
+// Admission follows the byte budget in arrival order; a request larger than
+// the whole budget is refused at submission.
+void budget() {
+    const int64_t n = 200, m = 64;
+    const size_t per = (size_t)n * m * 8;
+    sbs_server *srv = nullptr;
+    CHECK(sbs_server_create(3 * per, 2, 0, &srv) == SBS_OK);
+    Lhs L(srv, {n});
+    std::mt19937_64 g(3);
+    Input big = make_input(g, n, 1000, SBS_F64);
+    uint64_t t = 0;
+    CHECK(sbs_server_submit(srv, L.id[0], big.ptr(), big.m, SBS_F64, &t) == SBS_ERR_BUDGET);
+    std::vector<Input> in;
+    std::vector<uint64_t> tk(8);
+    for (int r = 0; r < 8; ++r) in.push_back(make_input(g, n, m, SBS_F64));
+    for (int r = 0; r < 8; ++r) CHECK(sbs_server_submit(srv, L.id[0], in[r].ptr(), m, SBS_F64, &tk[r]) == SBS_OK);
+    const double *x;
+    double lat;
+    for (int r = 0; r < 3; ++r) CHECK(sbs_server_wait(srv, tk[r], 20000000, &x, &lat) == SBS_OK);
+    // nobody has released anything: the fourth cannot be admitted
+    CHECK(sbs_server_wait(srv, tk[3], 50000, &x, &lat) == SBS_ERR_TIMEOUT);
+    sbs_server_stats st;
+    CHECK(sbs_server_stats_get(srv, &st) == SBS_OK);
+    CHECK(st.completed == 3 && st.queued == 5 && st.rejected == 1 && st.bytes_reserved == 3 * per);
+    for (int r = 0; r < 8; ++r) {
+        CHECK(sbs_server_wait(srv, tk[r], 20000000, &x, &lat) == SBS_OK);
+        CHECK(result_matches(x, in[r]));
+        CHECK(sbs_server_release(srv, tk[r]) == SBS_OK);
+    }
+    CHECK(sbs_server_stats_get(srv, &st) == SBS_OK);
+    CHECK(st.completed == 8 && st.bytes_reserved == 0);
+    CHECK(sbs_server_destroy(srv) == SBS_OK);
+    std::printf("budget: ok\n");
+}
+
+// Argument checks, unknown tickets, and release of an unfinished request.
+void errors() {
+    sbs_server *srv = nullptr;
+    CHECK(sbs_server_create(0, 1, 0, &srv) == SBS_ERR_INVALID_ARG && !srv);
+    CHECK(sbs_server_create(1 << 20, 17, 0, &srv) == SBS_ERR_INVALID_ARG);
+    CHECK(sbs_server_create(64u << 20, 1, 0, &srv) == SBS_OK);
+    Lhs L(srv, {40});
+    std::mt19937_64 g(5);
+    Input in = make_input(g, 40, 64 * 2000, SBS_F64);
+    uint64_t t = 0;
+    CHECK(sbs_server_submit(srv, 5, in.ptr(), in.m, SBS_F64, &t) == SBS_ERR_INVALID_ARG);
+    CHECK(sbs_server_submit(srv, L.id[0], in.ptr(), 0, SBS_F64, &t) == SBS_ERR_INVALID_ARG);
+    CHECK(sbs_server_submit(srv, L.id[0], in.ptr(), 8, 7, &t) == SBS_ERR_INVALID_ARG);
+    CHECK(sbs_server_submit(srv, L.id[0], nullptr, 8, SBS_F64, &t) == SBS_ERR_INVALID_ARG);
+    CHECK(sbs_server_submit(srv, L.id[0], (const char *)in.ptr() + 4, 8, SBS_F64, &t) == SBS_ERR_INVALID_ARG);
+    CHECK(sbs_server_submit(srv, L.id[0], in.ptr(), in.m, SBS_F64, &t) == SBS_OK);
+    // 2000 tiles take tens of milliseconds: the request is not done yet
+    CHECK(sbs_server_release(srv, t) == SBS_ERR_INVALID_ARG);
+    const double *x;
+    double lat;
+    CHECK(sbs_server_wait(srv, t + 1, 0, &x, &lat) == SBS_ERR_NOT_FOUND);
+    CHECK(sbs_server_wait(srv, t, 20000000, &x, &lat) == SBS_OK);
+    CHECK(result_matches(x, in));
+    CHECK(sbs_server_release(srv, t) == SBS_OK);
+    CHECK(sbs_server_release(srv, t) == SBS_ERR_NOT_FOUND);
+    CHECK(sbs_server_destroy(srv) == SBS_OK);
+    std::printf("errors: ok\n");
+}
+
+// Shutdown with requests running, finished-but-unreleased and still queued:
+// everything admitted drains, queued requests are dropped, nothing leaks.
+void shutdown() {
+    const int64_t n = 100, m = 640;
+    sbs_server *srv = nullptr;
+    CHECK(sbs_server_create(2 * (size_t)n * m * 8, 2, 0, &srv) == SBS_OK);
+    Lhs L(srv, {n});
+    std::mt19937_64 g(9);
+    std::vector<Input> in;
+    std::vector<uint64_t> tk(6);
+    for (int r = 0; r < 6; ++r) in.push_back(make_input(g, n, m, SBS_F64));
+    for (int r = 0; r < 6; ++r) CHECK(sbs_server_submit(srv, L.id[0], in[r].ptr(), m, SBS_F64, &tk[r]) == SBS_OK);
+    const double *x;
+    double lat;
+    CHECK(sbs_server_wait(srv, tk[0], 20000000, &x, &lat) == SBS_OK);
+    CHECK(sbs_server_destroy(srv) == SBS_OK);
+    std::printf("shutdown: ok\n");
+}
+
+}  // namespace
+
+int main(int argc, char **argv) {
+    const std::string s = argc > 1 ? argv[1] : "";
+    if (s == "mix") mix();
+    else if (s == "budget") budget();
+    else if (s == "errors") errors();
+    else if (s == "shutdown") shutdown();
+    else {
+        std::fprintf(stderr, "unknown scenario '%s'\n", s.c_str());
+        return 2;
+    }
+    return 0;
+}

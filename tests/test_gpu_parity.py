@@ -42,6 +42,31 @@ def chunked_fits(kind, n, elem=8):
     return K * S * 64 * elem + 2 * 32 * row <= 64 * 1024
 
 
+def partition_available(kind, n, elem=8):
+    """Mirror of the library's rule: some block length lb in (16, 32, 64) with
+    P = ceil(n/lb) <= 64 blocks, at most 90 interface unknowns 2h(P-1), and
+    block factors + spikes + interface inverse + one workgroup's interface
+    values (S >= 16 systems) within 160 KiB of LDS."""
+    h = kind // 2
+    row = (4 if kind == 3 else 8) * elem
+    for lb in (16, 32, 64):
+        P = -(-n // lb)
+        Nr = 2 * h * (P - 1)
+        if P > 64 or Nr > 90:
+            continue
+        maxt = 512 if (lb == 64 and elem == 8) else 1024
+        S = 64
+        while S > 16 and S * P > maxt:
+            S //= 2
+        if S * P > maxt:
+            continue
+        r16 = lambda v: -(-v // 16) * 16
+        lds = r16(P * lb * row) + r16(P * lb * 2 * h * elem) + r16(Nr * Nr * elem) + r16(S * (Nr + 1) * elem)
+        if lds <= 160 * 1024:
+            return True
+    return False
+
+
 def gpu_solve(kind, B, rhs, variant=sbs.VARIANT_AUTO, dtype=torch.float64):
     with sbs.SharedLhs(kind, B) as lhs:
         x = torch.from_numpy(np.ascontiguousarray(rhs)).to(DEV, dtype)
@@ -56,7 +81,7 @@ SHAPES = [(1, 1), (2, 3), (3, 64), (4, 5), (5, 65), (8, 1), (31, 63), (32, 64), 
 
 @pytest.mark.parametrize("kind", [3, 5])
 @pytest.mark.parametrize("variant", [sbs.VARIANT_AUTO, sbs.VARIANT_RESIDENT, sbs.VARIANT_CHUNKED,
-                                     sbs.VARIANT_STREAM])
+                                     sbs.VARIANT_STREAM, sbs.VARIANT_PARTITION])
 @pytest.mark.parametrize("n,m", SHAPES)
 def test_fp64_matches_oracle(kind, variant, n, m):
     if variant == sbs.VARIANT_RESIDENT and n > 64:
@@ -64,7 +89,8 @@ def test_fp64_matches_oracle(kind, variant, n, m):
     print(f"case kind={kind} variant={variant} n={n} m={m}", flush=True)
     B = bands_for(kind, n, 1000 * kind + n)
     rhs = np.random.default_rng(n * 7 + m).uniform(-1, 1, (n, m))
-    if variant == sbs.VARIANT_CHUNKED and not chunked_fits(kind, n):
+    if (variant == sbs.VARIANT_CHUNKED and not chunked_fits(kind, n)) or \
+            (variant == sbs.VARIANT_PARTITION and not partition_available(kind, n)):
         with pytest.raises(sbs.SbsError) as e:
             gpu_solve(kind, B, rhs, variant)
         assert e.value.status == 1
@@ -73,8 +99,42 @@ def test_fp64_matches_oracle(kind, variant, n, m):
     assert colrel(got, oracle.solve(kind, B, rhs)) <= TOL64
 
 
+def test_partition_plan_rule():
+    # penta n = 2048 needs 31 blocks of 64 rows: 120 interface unknowns, over the limit
+    assert not partition_available(5, 2048) and partition_available(5, 1024) and partition_available(3, 2048)
+
+
+@pytest.mark.parametrize("kind", [3, 5])
+@pytest.mark.parametrize("n", [1, 40, 64, 65, 700, 1024, 1500, 2048, 3000, 5000])
+def test_auto_variant_query(kind, n):
+    # what AUTO runs: partitioned when a plan exists, else resident / chunked / stream
+    with sbs.SharedLhs(kind, bands_for(kind, n, n)) as lhs:
+        for dtype, elem in ((sbs.SBS_F64, 8), (sbs.SBS_F32, 4)):
+            if partition_available(kind, n, elem):
+                want = sbs.VARIANT_PARTITION
+            elif n <= 64:
+                want = sbs.VARIANT_RESIDENT
+            else:
+                want = sbs.VARIANT_CHUNKED if chunked_fits(kind, n, elem) else sbs.VARIANT_STREAM
+            assert sbs.sbs_auto_variant(lhs.handle, 1000, dtype) == want
+        with pytest.raises(sbs.SbsError):
+            sbs.sbs_auto_variant(lhs.handle, 0)
+
+
+@pytest.mark.parametrize("kind", [3, 5])
+@pytest.mark.parametrize("n,m", [(64, 4096), (65, 33), (129, 1000), (500, 17), (1024, 3000), (2048, 130)])
+def test_partition_fp32(kind, n, m):
+    if not partition_available(kind, n, elem=4):
+        pytest.skip("no partition plan")
+    B = bands_for(kind, n, 9 + n)
+    rhs = np.random.default_rng(n + m).uniform(-1, 1, (n, m)).astype(np.float32)
+    got = gpu_solve(kind, B, rhs, sbs.VARIANT_PARTITION, dtype=torch.float32)
+    ref = oracle.solve(kind, B, rhs.astype(np.float64))
+    assert colrel(got, ref) <= 2e-5
+
+
 def test_variants_agree_bit_for_bit():
-    # Every variant runs the same recurrences in the same order.
+    # The sweep variants run the same recurrences in the same order.
     for kind in (3, 5):
         B = bands_for(kind, 60, kind)
         rhs = np.random.default_rng(kind).uniform(-1, 1, (60, 190))
@@ -118,9 +178,12 @@ def test_handle_storage_is_independent_of_batch_size():
         B = bands_for(kind, n, 3)
         with sbs.SharedLhs(kind, B) as lhs:
             rows = (n + 63) // 64 * 64
-            # FP64 factor + FP32 shadow + original bands, per padded row
+            # FP64 factor + FP32 shadow + original bands, per padded row ...
             per_row = {3: 32 + 16 + 64, 5: 64 + 32 + 64}[kind]
-            assert lhs.device_bytes == rows * per_row
+            # ... plus up to three partition plans (block factors and spikes in
+            # FP64 and FP32, and an interface inverse of at most 90 x 90)
+            plan_row = {3: (32 + 16) * 3 // 2, 5: (64 + 32) * 3 // 2}[kind]
+            assert rows * per_row <= lhs.device_bytes <= rows * per_row + 3 * (rows * plan_row + 90 * 90 * 12 + 64)
     # Shared LHS storage against one copy per system (the storage counts
     # closing Sections 3.1 and 4.1): 3N + MN vs 4MN, 5N + MN vs 6MN.
     M, N = 65536, 1024

@@ -64,10 +64,14 @@ def make_lhs_set(count, n_lo, n_hi, seed=0):
     return lhss, [sbs.SharedLhs(l.kind, l.bands) for l in lhss]
 
 
-def alone(h, kind, rhs):
+def alone(h, kind, rhs, variant=sbs.VARIANT_STREAM):
+    """The request solved on its own through the plain entry points.  The
+    serving tiles run the per-system sweeps (chunked or stream, which give
+    identical bits), so that is the variant to compare bit for bit; AUTO may
+    pick the partitioned variant, whose rounding differs."""
     if rhs.dtype == torch.float64:
         x = rhs.clone()
-        sbs.sbs_solve_batch(h.handle, x)
+        sbs.sbs_solve_batch_variant(h.handle, x, variant)
         return x
     return h.solve_refined(rhs, sweeps=2)
 
@@ -91,8 +95,20 @@ def test_alone_vs_mix_bit_exact_with_overlapping_requests():
         got = srv.fetch(tk, lhss[r.lhs].n, r.m)
         ref = alone(hs[r.lhs], lhss[r.lhs].kind, t)
         torch.cuda.synchronize()
-        if not torch.equal(got, ref):
+        if t.dtype == torch.float64 and not torch.equal(got, ref):
             mismatches += 1
+        if t.dtype == torch.float32:
+            # the plain mixed-precision entry point may run the fused partitioned
+            # kernel, whose rounding differs from the tiles'
+            num = (got - ref).abs().amax(dim=0)
+            den = ref.abs().amax(dim=0).clamp_min(1e-300)
+            assert float((num / den).max()) <= 1e-12
+        if t.dtype == torch.float64:
+            auto = alone(hs[r.lhs], lhss[r.lhs].kind, t, sbs.VARIANT_AUTO)
+            torch.cuda.synchronize()
+            num = (got - auto).abs().amax(dim=0)
+            den = auto.abs().amax(dim=0).clamp_min(1e-300)
+            assert float((num / den).max()) <= 1e-12
         assert srv.release(tk) == 0
     s = srv.stats()
     print(f"served {s.completed} requests in {s.launches} launches; p50 {s.p50_us:.0f} us p99 {s.p99_us:.0f} us",
@@ -182,3 +198,34 @@ def test_arrivals_during_running_work_are_admitted_and_overlap():
     srv.close()
     hl.close()
     hs.close()
+
+
+@pytest.mark.skip(reason="per-request completion is switched off: in its tile kernel the compiler let lanes "
+                  "1-63 go round the persistent loop without lane 0 after the lane-0 completion step, so "
+                  "readfirstlane gave those lanes tile 0 again and the kernel never ended; requests complete "
+                  "when their launch does")
+def test_small_request_completes_before_its_launch_ends():
+    # One launch holding a large and a small request: with per-request
+    # completion the small one is reported done before the large one.
+    big_b = W.hyperdiffusion_bands(4096, 0.5)
+    hb = sbs.SharedLhs(5, big_b)
+    hsm = sbs.SharedLhs(3, W.diffusion_bands(64, 0.5))
+    srv = Server(budget=4 << 30, streams=1)
+    ib, ism = srv.register(hb.handle), srv.register(hsm.handle)
+    big = torch.rand((4096, 65536), dtype=torch.float64, device=DEV)
+    small = torch.rand((64, 64), dtype=torch.float64, device=DEV)
+    torch.cuda.synchronize()
+    st1, tb = srv.submit(ib, big)
+    st2, ts = srv.submit(ism, small)
+    assert st1 == 0 and st2 == 0
+    st, _, lat_s = srv.wait(ts, 60_000_000)
+    assert st == 0
+    st, _, lat_b = srv.wait(tb, 60_000_000)
+    assert st == 0
+    assert lat_s < lat_b
+    assert torch.equal(srv.fetch(ts, 64, 64), alone(hsm, 3, small))
+    srv.release(ts)
+    srv.release(tb)
+    srv.close()
+    hb.close()
+    hsm.close()
