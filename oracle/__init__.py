@@ -7,10 +7,12 @@ GPU library computes (arXiv:1909.04539, Sections 3.1 and 4.1), written in C
 leg may import this package.  It imports nothing from the GPU library and
 shares no code with it.
 
-Interface: bands are given as one float64 array of shape (kind, n), band-major
+Interface: bands are given as one float64 array of shape (bands, n), band-major
 and row-aligned -- band k, entry i is the coefficient in row i (tri: a, b, c;
 penta: a, b, c, d, e), exactly as the library's factor call takes them.  RHS
 arrays are interleaved: shape (n, m), unknown i of system j at [i, j].
+Kinds: 3 tridiagonal, 5 pentadiagonal, TRI_PERIODIC (13) tridiagonal with
+periodic wrap (Section 3.3; three bands, a_0 and c_{n-1} are the corners).
 
 Parity pins: none of these functions is trusted on its own; ``tests/
 test_oracle_pins.py`` checks them against dense LU, closed forms, banded LAPACK,
@@ -30,6 +32,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "sbs_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 _lib = None
+
+TRI_PERIODIC = 13
 
 GCC_FLAGS = ["-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
              "-fPIC", "-shared", "-std=c11"]
@@ -59,6 +63,8 @@ def _load():
         lib.oracle_penta_factor.restype = i64
         lib.oracle_penta_solve.argtypes = [i64, i64, i64, dp, dp, dp, dp, dp, dp]
         lib.oracle_penta_solve.restype = i64
+        lib.oracle_tri_periodic_solve.argtypes = [i64, i64, i64, dp, dp, dp, dp]
+        lib.oracle_tri_periodic_solve.restype = i64
         lib.oracle_adi_step.argtypes = [i64, i64, dp, dp, dp, dp, dp, dp, dp]
         lib.oracle_adi_step.restype = i64
         lib.oracle_tri_solve_mt.argtypes = [i64, i64, dp, dp, dp, dp, ctypes.c_int]
@@ -76,10 +82,11 @@ def _p(x: np.ndarray):
 
 
 def _bands(bands, kind: int):
+    nb = 3 if kind == TRI_PERIODIC else kind
     B = np.ascontiguousarray(np.asarray(bands, dtype=np.float64))
-    if B.ndim != 2 or B.shape[0] != kind:
-        raise ValueError(f"bands must have shape ({kind}, n)")
-    return [np.ascontiguousarray(B[k]) for k in range(kind)]
+    if B.ndim != 2 or B.shape[0] != nb:
+        raise ValueError(f"bands must have shape ({nb}, n)")
+    return [np.ascontiguousarray(B[k]) for k in range(nb)]
 
 
 def _raise(bad: int) -> None:
@@ -118,8 +125,13 @@ def solve(kind: int, bands, rhs) -> np.ndarray:
     elif kind == 5:
         a, b, c, d, e = _bands(bands, 5)
         _raise(_load().oracle_penta_solve(n, m, m, _p(a), _p(b), _p(c), _p(d), _p(e), _p(X)))
+    elif kind == TRI_PERIODIC:
+        if n < 3:
+            raise ValueError("a periodic system needs n >= 3")
+        a, b, c = _bands(bands, kind)
+        _raise(_load().oracle_tri_periodic_solve(n, m, m, _p(a), _p(b), _p(c), _p(X)))
     else:
-        raise ValueError("kind must be 3 (tri) or 5 (penta)")
+        raise ValueError("kind must be 3 (tri), 5 (penta) or 13 (periodic tri)")
     return X
 
 
@@ -164,4 +176,6 @@ def twin_solve(kind: int, bands, rhs) -> np.ndarray:
     X = np.asarray(rhs, dtype=np.float64)
     if kind == 3:
         return twin.tri_solve(*_bands(bands, 3), X)
+    if kind == TRI_PERIODIC:
+        return twin.tri_periodic_solve(*_bands(bands, kind), X)
     return twin.penta_solve(*_bands(bands, 5), X)

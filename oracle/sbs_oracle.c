@@ -184,6 +184,55 @@ int64_t oracle_penta_solve(int64_t n, int64_t m, int64_t ld, const double *a,
 }
 
 /* ---------------------------------------------------------------------------
+ * Periodic tridiagonal systems, Section 3.3 (Sherman-Morrison).
+ * Row i reads a_i x_{(i-1) mod n} + b_i x_i + c_i x_{(i+1) mod n}: besides
+ * the three bands the matrix has a_0 in its top-right corner and c_{n-1} in
+ * its bottom-left corner.  It is split as A = A' + u v^T with
+ *   u = (-b_0, 0, ..., 0, c_{n-1})^T,   v = (1, 0, ..., 0, -a_0 / b_0)^T.
+ * u v^T puts -b_0 at (0,0), a_0 at (0,n-1), c_{n-1} at (n-1,0) and
+ * -a_0 c_{n-1} / b_0 at (n-1,n-1), so A' is tridiagonal with the same bands
+ * except A'_00 = 2 b_0 and A'_{n-1,n-1} = b_{n-1} + a_0 c_{n-1} / b_0; its
+ * corners are zero (the paper's display of A' still shows them, which would
+ * make A' + u v^T differ from A).  Then
+ *   A' y = d,   A' z = u,   x = y - ((v.y) / (1 + v.z)) z,
+ * with v.w = w_0 + v_{n-1} w_{n-1}, v_{n-1} = -a_0 / b_0.
+ * Needs n >= 3 (for smaller n the corner entries fall on the bands).
+ * Returns -1, or the row of a bad pivot of A', or n when 1 + v.z is zero or
+ * not finite.  The interleaved layout and loop order are as above.
+ */
+int64_t oracle_tri_periodic_solve(int64_t n, int64_t m, int64_t ld,
+                                  const double *a, const double *b,
+                                  const double *c, double *d)
+{
+    if (n < 3) return 0;
+    double *w = (double *)malloc(sizeof(double) * (size_t)(4 * n));
+    double *bp = w, *den = w + n, *chat = w + 2 * n, *z = w + 3 * n;
+    const double vlast = -a[0] / b[0];
+    for (int64_t i = 0; i < n; ++i) bp[i] = b[i];
+    bp[0] = b[0] + b[0];
+    bp[n - 1] = b[n - 1] + a[0] * c[n - 1] / b[0];
+    int64_t bad = oracle_tri_factor(n, a, bp, c, den, chat);
+    if (bad < 0) {
+        for (int64_t i = 0; i < n; ++i) z[i] = 0.0;
+        z[0] = -b[0];
+        z[n - 1] = c[n - 1];
+        oracle_tri_apply(n, 1, 1, a, den, chat, z);
+        const double vz1 = 1.0 + (z[0] + vlast * z[n - 1]);
+        if (bad_pivot(vz1)) {
+            bad = n;
+        } else {
+            oracle_tri_apply(n, m, ld, a, den, chat, d);
+            for (int64_t j = 0; j < m; ++j) {
+                const double s = (d[j] + vlast * d[(n - 1) * ld + j]) / vz1;
+                for (int64_t i = 0; i < n; ++i) d[i * ld + j] = d[i * ld + j] - s * z[i];
+            }
+        }
+    }
+    free(w);
+    return bad;
+}
+
+/* ---------------------------------------------------------------------------
  * One alternating-direction step on an ny x nx grid stored row-major,
  * grid[y*nx + x] (the 2-D use of batched solvers named in the introduction).
  * First every column is solved along y with the y-matrix: the columns are

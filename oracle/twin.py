@@ -98,3 +98,28 @@ def penta_solve(a, b, c, d, e, f):
         x2 = x[i + 2] if i + 2 < n else zero
         x[i] = x[i] - ga[i] * x1 - de[i] * x2
     return x
+
+
+def tri_periodic_solve(a, b, c, d):
+    """Section 3.3: periodic tridiagonal (corners a_0 top-right, c_{n-1}
+    bottom-left) by Sherman-Morrison.  A = A' + u v^T with
+    u = (-b_0, 0.., c_{n-1}), v = (1, 0.., -a_0/b_0); A' is tridiagonal with
+    A'_00 = 2 b_0 and A'_{n-1,n-1} = b_{n-1} + a_0 c_{n-1} / b_0; then
+    y = A'^{-1} d, z = A'^{-1} u and x = y - ((v.y) / (1 + v.z)) z.
+    Raises PivotError(n) when 1 + v.z is zero or not finite."""
+    n = len(b)
+    if n < 3:
+        raise ValueError("a periodic system needs n >= 3")
+    vlast = -a[0] / b[0]
+    bp = np.array(b, dtype=np.float64, copy=True)
+    bp[0] = b[0] + b[0]
+    bp[n - 1] = b[n - 1] + a[0] * c[n - 1] / b[0]
+    u = np.zeros((n, 1))
+    u[0, 0] = -b[0]
+    u[n - 1, 0] = c[n - 1]
+    z = tri_solve(a, bp, c, u)[:, 0]
+    vz1 = 1.0 + (z[0] + vlast * z[n - 1])
+    _check(vz1, n)
+    y = tri_solve(a, bp, c, d)
+    s = (y[0] + vlast * y[n - 1]) / vz1
+    return y - s * z[:, None]
