@@ -65,6 +65,8 @@ def _load():
         lib.oracle_penta_solve.restype = i64
         lib.oracle_tri_periodic_solve.argtypes = [i64, i64, i64, dp, dp, dp, dp]
         lib.oracle_tri_periodic_solve.restype = i64
+        lib.oracle_cn_steps.argtypes = [ctypes.c_int, i64, i64, dp, dp, ctypes.c_int]
+        lib.oracle_cn_steps.restype = i64
         lib.oracle_adi_step.argtypes = [i64, i64, dp, dp, dp, dp, dp, dp, dp]
         lib.oracle_adi_step.restype = i64
         lib.oracle_tri_solve_mt.argtypes = [i64, i64, dp, dp, dp, dp, ctypes.c_int]
@@ -162,6 +164,22 @@ def adi_step(bands_y, bands_x, grid) -> np.ndarray:
         raise ValueError("band lengths must match the grid")
     _raise(_load().oracle_adi_step(ny, nx, _p(ay), _p(by), _p(cy), _p(ax), _p(bx), _p(cx), _p(G)))
     return G
+
+
+def cn_steps(kind: int, bands, C, steps: int = 1) -> np.ndarray:
+    """Crank-Nicolson steps A C^{n+1} = (2I - A) C^n (Sections 3.2, 4.2)."""
+    X = np.array(C, dtype=np.float64, order="C", copy=True)
+    n, m = X.shape
+    B = np.ascontiguousarray(np.stack(_bands(bands, kind)))
+    if kind == TRI_PERIODIC and n < 3:
+        raise ValueError("a periodic system needs n >= 3")
+    _raise(_load().oracle_cn_steps(kind, n, m, _p(B), _p(X), steps))
+    return X
+
+
+def twin_cn_steps(kind: int, bands, C, steps: int = 1) -> np.ndarray:
+    from . import twin
+    return twin.cn_steps(kind, np.stack(_bands(bands, kind)), C, steps)
 
 
 def refine_reference(kind: int, bands, b32: np.ndarray) -> np.ndarray:

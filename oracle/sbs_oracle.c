@@ -233,6 +233,49 @@ int64_t oracle_tri_periodic_solve(int64_t n, int64_t m, int64_t ld,
 }
 
 /* ---------------------------------------------------------------------------
+ * Crank-Nicolson time steps, Sections 3.2 and 4.2.  Both benchmark schemes
+ * have the form A C^{n+1} = f with the explicit half f = (2I - A) C^n: for
+ * diffusion A = (-s, 1 + 2s, -s) and f_i = s C_{i-1} + (1 - 2s) C_i
+ * + s C_{i+1}; for hyperdiffusion A = (s, -4s, 1 + 6s, -4s, s) and f_i =
+ * -s C_{i-2} + 4s C_{i-1} + (1 - 6s) C_i + 4s C_{i+1} - s C_{i+2}.  With
+ * per-row bands the same operator is written with the matrix's own entries:
+ *   f_i = 2 C_i - (A C)_i,
+ * (A C)_i summed over the bands left to right, a term outside the matrix
+ * being zero (or wrapping round for kind 13, the periodic tridiagonal).
+ * Each step forms f from C, then solves A C = f with the routines above.
+ * kind: 3, 5 or 13; bands as for the solves.  Returns -1, or the bad row.
+ */
+int64_t oracle_cn_steps(int kind, int64_t n, int64_t m, const double *bands,
+                        double *C, int steps)
+{
+    const int nb = (kind == 13) ? 3 : kind;
+    const int h = nb / 2;
+    const double *a = bands, *b = bands + n, *c = bands + 2 * n;
+    const double *d = bands + 3 * n, *e = bands + 4 * n;
+    double *f = (double *)malloc(sizeof(double) * (size_t)(n * m));
+    int64_t bad = -1;
+    for (int s = 0; s < steps && bad < 0; ++s) {
+        for (int64_t i = 0; i < n; ++i)
+            for (int64_t j = 0; j < m; ++j) {
+                double ac = 0.0;
+                for (int k = 0; k < nb; ++k) {
+                    int64_t col = i + k - h;
+                    if (kind == 13) col = (col + n) % n;
+                    else if (col < 0 || col >= n) continue;
+                    ac = ac + bands[k * n + i] * C[col * m + j];
+                }
+                f[i * m + j] = 2.0 * C[i * m + j] - ac;
+            }
+        for (int64_t t = 0; t < n * m; ++t) C[t] = f[t];
+        if (kind == 3) bad = oracle_tri_solve(n, m, m, a, b, c, C);
+        else if (kind == 5) bad = oracle_penta_solve(n, m, m, a, b, c, d, e, C);
+        else bad = oracle_tri_periodic_solve(n, m, m, a, b, c, C);
+    }
+    free(f);
+    return bad;
+}
+
+/* ---------------------------------------------------------------------------
  * One alternating-direction step on an ny x nx grid stored row-major,
  * grid[y*nx + x] (the 2-D use of batched solvers named in the introduction).
  * First every column is solved along y with the y-matrix: the columns are

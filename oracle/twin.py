@@ -123,3 +123,33 @@ def tri_periodic_solve(a, b, c, d):
     y = tri_solve(a, bp, c, d)
     s = (y[0] + vlast * y[n - 1]) / vz1
     return y - s * z[:, None]
+
+
+def cn_steps(kind, bands, C, steps=1):
+    """Sections 3.2 / 4.2: Crank-Nicolson steps A C^{n+1} = (2I - A) C^n with
+    f_i = 2 C_i - (A C)_i summed over the bands left to right (terms outside
+    the matrix zero; wrapped for kind 13), then the solve."""
+    B = np.asarray(bands, dtype=np.float64)
+    nb = B.shape[0]
+    h = nb // 2
+    X = np.array(C, dtype=np.float64, copy=True)
+    n = X.shape[0]
+    for _ in range(steps):
+        F = np.empty_like(X)
+        for i in range(n):
+            ac = np.zeros_like(X[0])
+            for k in range(nb):
+                col = i + k - h
+                if kind == 13:
+                    col %= n
+                elif col < 0 or col >= n:
+                    continue
+                ac = ac + B[k, i] * X[col]
+            F[i] = 2.0 * X[i] - ac
+        if kind == 3:
+            X = tri_solve(*B, F)
+        elif kind == 5:
+            X = penta_solve(*B, F)
+        else:
+            X = tri_periodic_solve(*B, F)
+    return X
