@@ -126,6 +126,26 @@ def bench_headline(args, torch, sbs, W):
     return res
 
 
+def bench_penta_general(args, torch, sbs, W):
+    """The headline's size with a general matrix: random diagonally dominant
+    bands, so no two partition blocks share a stored copy."""
+    n, m = 1024, 65536
+    rng = np.random.default_rng(11)
+    B = rng.uniform(-1, 1, (5, n))
+    B[2] = np.sum(np.abs(np.delete(B, 2, axis=0)), axis=0) + rng.uniform(1, 2, n)
+    B = W.zero_outside(B)
+    g = torch.Generator(device="cuda:0")
+    g.manual_seed(12)
+    rhs = torch.rand((n, m), dtype=torch.float64, device="cuda:0", generator=g)
+    lhs = sbs.SharedLhs(5, B)
+    ran = sbs.sbs_auto_variant(lhs.handle, m)
+    wall, dev = timed_steps(lambda: lhs.solve(rhs), 20, 3, torch)
+    lhs.close()
+    u = n * m
+    return {"workload": "penta_f64_n1024_m65536_random_bands", "variant": {v: k for k, v in VARIANTS.items()}[ran],
+            "unknowns_per_s": u / dev, "us_per_solve": dev * 1e6, "hbm_frac_16B": round(16 * u / dev / 1e9 / HBM_PEAK_GBS, 4)}
+
+
 def bench_tri256(args, torch, sbs, W):
     wl = W.config0()
     rhs = torch.from_numpy(wl.rhs).to("cuda:0")
@@ -351,8 +371,8 @@ def main():
         print(json.dumps(bench_serving(args, torch, sbs, W)), flush=True)
         return
     if args.only != "headline":
-        for name, fn in (("tri_n256_m1024", bench_tri256), ("adi_2048", bench_adi), ("refined_n512_m1M", bench_refined),
-                         ("serving", bench_serving)):
+        for name, fn in (("penta_general", bench_penta_general), ("tri_n256_m1024", bench_tri256),
+                         ("adi_2048", bench_adi), ("refined_n512_m1M", bench_refined), ("serving", bench_serving)):
             log(f"workload {name}")
             try:
                 extra[name] = fn(args, torch, sbs, W)

@@ -48,7 +48,11 @@ typedef enum sbs_status {
     SBS_ERR_SHUTDOWN = 9     /* server is shutting down                        */
 } sbs_status;
 
-typedef enum sbs_kind { SBS_TRI = 3, SBS_PENTA = 5 } sbs_kind;
+typedef enum sbs_kind {
+    SBS_TRI = 3,           /* tridiagonal                                   */
+    SBS_PENTA = 5,         /* pentadiagonal                                 */
+    SBS_TRI_PERIODIC = 13  /* tridiagonal with periodic wrap (three bands)  */
+} sbs_kind;
 typedef enum sbs_dtype { SBS_F64 = 0, SBS_F32 = 1 } sbs_dtype;
 
 /* Sweep variants (all compute the same recurrences; they differ only in how
@@ -76,8 +80,9 @@ const char *sbs_version(void);
  * b_i - a_i chat_{i-1}) and 4.1 (pentadiagonal A = L R: alpha, beta, gamma,
  * delta, epsilon).  The paper performs this step on the CPU (Section 2).
  *
- *  kind     SBS_TRI or SBS_PENTA.
- *  n        number of unknowns per system, n >= 1.
+ *  kind     SBS_TRI, SBS_PENTA or SBS_TRI_PERIODIC.
+ *  n        number of unknowns per system, n >= 1 (n >= 3 for
+ *           SBS_TRI_PERIODIC).
  *  bands    host, kind*n doubles, band-major and row-aligned: band k, entry i
  *           is the coefficient in row i.  Tridiagonal row i reads
  *           a_i x_{i-1} + b_i x_i + c_i x_{i+1}  (bands a, b, c);
@@ -86,14 +91,30 @@ const char *sbs_version(void);
  *           Entries outside the matrix (tri a_0, c_{n-1}; penta a_0, a_1, b_0,
  *           d_{n-1}, e_{n-2}, e_{n-1}) are ignored.  The array is copied; the
  *           caller keeps ownership.
+ *           SBS_TRI_PERIODIC (Section 3.3) takes the three tridiagonal bands
+ *           with the wrap: row i reads a_i x_{(i-1) mod n} + b_i x_i
+ *           + c_i x_{(i+1) mod n}, so a_0 and c_{n-1} are the corner
+ *           entries.  It is factored by Sherman-Morrison: A = A' + u v^T with
+ *           u = (-b_0, 0, .., 0, c_{n-1}), v = (1, 0, .., 0, -a_0/b_0) and A'
+ *           tridiagonal (A'_00 = 2 b_0, A'_{n-1,n-1} = b_{n-1}
+ *           + a_0 c_{n-1} / b_0, no corners).  z = A'^{-1} u and
+ *           w = A'^{-T} v / (1 + v.z) are computed here, so that each solve
+ *           is x = y - (w.d) z with y = A'^{-1} d, in the same two sweeps.
+ *           Periodic handles take the plain solves (resident, chunked and
+ *           stream variants, FP64 or FP32) and the ADI step; the refined
+ *           solve, the partitioned variant and the serving loop reject them
+ *           with SBS_ERR_INVALID_ARG.
  *  out      receives the new handle (owned by the caller; free with
  *           sbs_release).  Set to NULL on every error.
  *  bad_row  optional (may be NULL): on SBS_ERR_ZERO_PIVOT or
- *           SBS_ERR_NONFINITE the 0-based offending row, else -1.
+ *           SBS_ERR_NONFINITE the 0-based offending row, else -1.  For
+ *           SBS_TRI_PERIODIC, bad_row == n means 1 + v.z is zero or not
+ *           finite (the rank-one correction fails).
  * There is no pivoting (the paper has none): a zero or non-finite pivot is
  * reported as SBS_ERR_ZERO_PIVOT.  Diagonally dominant and symmetric
  * positive definite matrices never produce one.
- * Errors: SBS_ERR_INVALID_ARG (kind, n < 1, NULL bands/out),
+ * Errors: SBS_ERR_INVALID_ARG (kind, n < 1 or periodic n < 3, NULL
+ *         bands/out),
  *         SBS_ERR_NONFINITE, SBS_ERR_ZERO_PIVOT, SBS_ERR_NO_MEMORY,
  *         SBS_ERR_DEVICE.
  */
@@ -149,7 +170,8 @@ sbs_status sbs_auto_variant(sbs_handle h, int64_t m, int32_t dtype,
  *  sweeps     number of corrections, 0..8 (2 is the usual choice).
  *  work       device scratch of at least sbs_refined_workspace_bytes(h, m)
  *             bytes (caller-owned; contents on return are unspecified).
- * Errors: SBS_ERR_INVALID_ARG, SBS_ERR_DEVICE.
+ * Errors: SBS_ERR_INVALID_ARG (also for an SBS_TRI_PERIODIC handle),
+ *         SBS_ERR_DEVICE.
  */
 sbs_status sbs_solve_batch_refined(sbs_handle h, const float *b, double *x,
                                    int64_t m, int32_t sweeps, void *work,
@@ -172,7 +194,8 @@ sbs_status sbs_transpose(const void *src, void *dst, int64_t rows,
  * One alternating-direction step on a row-major FP64 grid g[y*nx + x]:
  * solve along y with hy (n == ny; the columns are already interleaved with
  * m = nx), transpose into `work`, solve along x with hx (n == nx, m = ny),
- * transpose back into g.  Both handles must be SBS_TRI or SBS_PENTA.
+ * transpose back into g.  Either handle may be of any kind (periodic
+ * handles give periodic directions).
  *  grid  device, ny*nx doubles, overwritten.
  *  work  device scratch, ny*nx doubles (caller-owned).
  */
@@ -222,7 +245,8 @@ sbs_status sbs_server_create(size_t budget_bytes, int32_t max_streams,
                              int32_t max_batch_requests, sbs_server **out);
 
 /* Register a factored matrix; the server keeps a reference, the caller still
- * owns the handle and must keep it alive until sbs_server_destroy. */
+ * owns the handle and must keep it alive until sbs_server_destroy.
+ * SBS_TRI and SBS_PENTA handles only (SBS_ERR_INVALID_ARG otherwise). */
 sbs_status sbs_server_register(sbs_server *srv, sbs_handle h, int32_t *lhs_id);
 
 /* Queue a request.  rhs: device, n*m elements of dtype (interleaved),

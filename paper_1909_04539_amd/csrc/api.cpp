@@ -30,6 +30,18 @@ template <>
 PentaRow<float> narrow(const PentaRow<double> &r) {
     return {(float)r.eps_s, (float)r.beta_s, (float)r.inv, (float)r.gamma, (float)r.delta, 0.f, 0.f, 0.f};
 }
+template <>
+PeriodicRow<float> narrow(const PeriodicRow<double> &r) {
+    return {(float)r.a_s, (float)r.chat, (float)r.inv, (float)r.wt, (float)r.z, 0.f, 0.f, 0.f};
+}
+
+int nbands(int kind) { return kind == SBS_TRI_PERIODIC ? 3 : kind; }
+
+// Band k of row i as the matrix uses it: 0 outside a banded matrix; every
+// entry (the corners a_0 and c_{n-1} included) for a periodic one.
+double entry(const double *bands, int kind, int64_t n, int k, int64_t i) {
+    return kind == SBS_TRI_PERIODIC ? bands[(int64_t)k * n + i] : coef(bands, kind, n, k, i);
+}
 
 template <typename Row64, typename Row32>
 sbs_status upload(sbs_lhs *h, const std::vector<Row64> &r64, const double *B) {
@@ -42,7 +54,7 @@ sbs_status upload(sbs_lhs *h, const std::vector<Row64> &r64, const double *B) {
     for (int64_t i = 0; i < h->n; ++i) p32[i] = narrow<Row32>(r64[i]);
     BandRow *pb = reinterpret_cast<BandRow *>(host.data() + b64 + b32);
     for (int64_t i = 0; i < h->n; ++i)
-        for (int k = 0; k < h->kind; ++k) pb[i].c[k] = coef(B, h->kind, h->n, k, i);
+        for (int k = 0; k < nbands(h->kind); ++k) pb[i].c[k] = entry(B, h->kind, h->n, k, i);
 
     if (hipGetDevice(&h->device) != hipSuccess) return SBS_ERR_DEVICE;
     void *dev = nullptr;
@@ -88,11 +100,12 @@ sbs_status sbs_factor_shared_lhs(int32_t kind, int64_t n, const double *bands, s
     int64_t bad = -1;
     if (bad_row) *bad_row = -1;
     if (out) *out = nullptr;
-    if (!out || !bands || n < 1 || (kind != SBS_TRI && kind != SBS_PENTA)) return SBS_ERR_INVALID_ARG;
-    if (n > (int64_t(1) << 40)) return SBS_ERR_INVALID_ARG;
+    if (!out || !bands || n < 1 || (kind != SBS_TRI && kind != SBS_PENTA && kind != SBS_TRI_PERIODIC))
+        return SBS_ERR_INVALID_ARG;
+    if (n > (int64_t(1) << 40) || (kind == SBS_TRI_PERIODIC && n < 3)) return SBS_ERR_INVALID_ARG;
     for (int64_t i = 0; i < n; ++i)
-        for (int k = 0; k < kind; ++k)
-            if (!std::isfinite(coef(bands, kind, n, k, i))) {
+        for (int k = 0; k < nbands(kind); ++k)
+            if (!std::isfinite(entry(bands, kind, n, k, i))) {
                 if (bad_row) *bad_row = i;
                 return SBS_ERR_NONFINITE;
             }
@@ -103,17 +116,22 @@ sbs_status sbs_factor_shared_lhs(int32_t kind, int64_t n, const double *bands, s
     h->rows = (n + kRowPad - 1) / kRowPad * kRowPad;
     sbs_status st;
     try {
-        auto cf = [&](int k, int64_t i) { return coef(bands, kind, n, k, i); };
+        auto cf = [&](int k, int64_t i) { return entry(bands, kind, n, k, i); };
         if (kind == SBS_TRI) {
             std::vector<TriRow<double>> r(n);
             st = factor_tri_rows(n, cf, r.data(), &bad) ? SBS_OK : SBS_ERR_ZERO_PIVOT;
             if (st == SBS_OK) st = upload<TriRow<double>, TriRow<float>>(h, r, bands);
-        } else {
+        } else if (kind == SBS_PENTA) {
             std::vector<PentaRow<double>> r(n);
             st = factor_penta_rows(n, cf, r.data(), &bad) ? SBS_OK : SBS_ERR_ZERO_PIVOT;
             if (st == SBS_OK) st = upload<PentaRow<double>, PentaRow<float>>(h, r, bands);
+        } else {
+            std::vector<PeriodicRow<double>> r(n);
+            st = factor_periodic_rows(n, cf, r.data(), &bad) ? SBS_OK : SBS_ERR_ZERO_PIVOT;
+            if (st == SBS_OK) st = upload<PeriodicRow<double>, PeriodicRow<float>>(h, r, bands);
         }
-        if (st == SBS_OK) st = build_partitions(h, bands);
+        // The partitioned variant covers the banded kinds.
+        if (st == SBS_OK && kind != SBS_TRI_PERIODIC) st = build_partitions(h, bands);
     } catch (const std::bad_alloc &) {
         st = SBS_ERR_NO_MEMORY;
     }
@@ -185,7 +203,7 @@ size_t sbs_refined_workspace_bytes(sbs_handle h, int64_t m) {
 
 sbs_status sbs_solve_batch_refined(sbs_handle h, const float *b, double *x, int64_t m, int32_t sweeps, void *work,
                                    size_t work_bytes, void *stream) {
-    if (!h || m < 0 || sweeps < 0 || sweeps > 8) return SBS_ERR_INVALID_ARG;
+    if (!h || m < 0 || sweeps < 0 || sweeps > 8 || h->kind == SBS_TRI_PERIODIC) return SBS_ERR_INVALID_ARG;
     if (m == 0) return SBS_OK;
     if (!b || !x || !work || work_bytes < sbs_refined_workspace_bytes(h, m)) return SBS_ERR_INVALID_ARG;
     if (!aligned(b, 8) || !aligned(x, 16) || !aligned(work, 8)) return SBS_ERR_INVALID_ARG;

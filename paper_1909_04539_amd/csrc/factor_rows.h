@@ -5,6 +5,7 @@
 
 #include <cmath>
 #include <cstdint>
+#include <vector>
 
 #include "internal.h"
 
@@ -58,6 +59,53 @@ bool factor_penta_rows(int64_t n, Coef coef, PentaRow<double> *rows, int64_t *ba
         d2 = d1;
         d1 = delta;
     }
+    return true;
+}
+
+// Section 3.3, periodic tridiagonal (a_0 and c_{n-1} are the corners): the
+// Sherman-Morrison splitting A = A' + u v^T, u = (-b_0, 0.., c_{n-1}),
+// v = (1, 0.., -a_0/b_0), leaves A' tridiagonal with A'_00 = 2 b_0 and
+// A'_{n-1,n-1} = b_{n-1} + a_0 c_{n-1} / b_0.  The rows carry A''s factor,
+// z = A'^{-1} u and wt = A'^{-T} v / (1 + v.z): then v.y = wt.d (1 + v.z)
+// for y = A'^{-1} d, so x = y - (wt.d) z needs no third pass.
+// Returns false with *bad = the row of a bad pivot, or n when 1 + v.z is zero
+// or not finite.  Needs n >= 3.
+inline void solve_tri_rows(int64_t n, const TriRow<double> *r, double *x);
+
+template <class Coef>
+bool factor_periodic_rows(int64_t n, Coef coef, PeriodicRow<double> *rows, int64_t *bad) {
+    const double a0 = coef(0, 0), b0 = coef(1, 0), cl = coef(2, n - 1);
+    const double vlast = -a0 / b0;
+    auto primed = [&](int k, int64_t i) -> double {  // bands of A' (no corners)
+        if (k == 0) return i == 0 ? 0.0 : coef(0, i);
+        if (k == 2) return i == n - 1 ? 0.0 : coef(2, i);
+        if (i == 0) return b0 + b0;
+        if (i == n - 1) return coef(1, n - 1) + a0 * cl / b0;
+        return coef(1, i);
+    };
+    // A'^T has sub-diagonal c_{i-1} and super-diagonal a_{i+1}.
+    auto transposed = [&](int k, int64_t i) -> double {
+        if (k == 0) return i == 0 ? 0.0 : primed(2, i - 1);
+        if (k == 2) return i == n - 1 ? 0.0 : primed(0, i + 1);
+        return primed(1, i);
+    };
+    std::vector<TriRow<double>> f(n), ft(n);
+    if (!factor_tri_rows(n, primed, f.data(), bad)) return false;
+    if (!factor_tri_rows(n, transposed, ft.data(), bad)) return false;
+    std::vector<double> z(n, 0.0), w(n, 0.0);
+    z[0] = -b0;
+    z[n - 1] = cl;
+    solve_tri_rows(n, f.data(), z.data());
+    w[0] = 1.0;
+    w[n - 1] = vlast;
+    solve_tri_rows(n, ft.data(), w.data());
+    const double den = 1.0 + (z[0] + vlast * z[n - 1]);
+    if (!finite_nonzero(den)) {
+        *bad = n;
+        return false;
+    }
+    for (int64_t i = 0; i < n; ++i)
+        rows[i] = {f[i].a_s, f[i].chat, f[i].inv, w[i] / den, z[i], 0.0, 0.0, 0.0};
     return true;
 }
 

@@ -31,6 +31,16 @@ struct alignas(8 * sizeof(T)) PentaRow {
     T eps_s, beta_s, inv, gamma, delta, p0, p1, p2;
 };
 
+// Periodic tridiagonal (Section 3.3), A = A' + u v^T with A' tridiagonal:
+//   forward   y_i = d_i / den_i - (a_i / den_i) y_{i-1},  acc += wt_i d_i
+//   backward  y_i = yhat_i - chat_i y_{i+1},  x_i = y_i - acc z_i
+// where den / chat factor A', z = A'^{-1} u and wt = A'^{-T} v / (1 + v.z),
+// so acc ends the forward sweep equal to (v.y) / (1 + v.z).
+template <typename T>
+struct alignas(8 * sizeof(T)) PeriodicRow {
+    T a_s, chat, inv, wt, z, p0, p1, p2;
+};
+
 // Original coefficients of row i, for the FP64 residual b - A x:
 // tri {a_i, b_i, c_i, 0}; penta {a_i, b_i, c_i, d_i, e_i, 0, 0, 0}.
 // Coefficients outside the matrix are stored as 0.
@@ -58,14 +68,21 @@ namespace sbs {
 // Everything depends on the matrix only, so it is computed once, in FP64.
 struct PartPlan {
     int lb = 0, P = 0, Nr = 0;
+    int D = 0;  // distinct blocks stored (bit-identical blocks share one copy)
     bool ok = false;
-    // Device arrays, each [fac | spk | rinv] contiguous and 16-byte aligned:
-    //   fac: P*lb factor rows of the blocks (TriRow/PentaRow)
-    //   spk: P*lb rows of {V[0..h), W[0..h)}
+    // Device arrays, each [fac | spk | rinv | map] contiguous and 16-byte aligned:
+    //   fac: D*lb factor rows of the distinct blocks (TriRow/PentaRow)
+    //   spk: D*lb rows of {V[0..h), W[0..h)}
     //   rinv: Nr*Nr, row-major
+    //   map: P ints, block p uses stored block map[p]
     void *blob64 = nullptr, *blob32 = nullptr;
     size_t fac_bytes64 = 0, spk_bytes64 = 0, rinv_bytes64 = 0;
     size_t fac_bytes32 = 0, spk_bytes32 = 0, rinv_bytes32 = 0;
+    size_t map_bytes = 0;
+    size_t blob_bytes(int tc) const {
+        return (tc == 0 ? fac_bytes64 + spk_bytes64 + rinv_bytes64 : fac_bytes32 + spk_bytes32 + rinv_bytes32) +
+               map_bytes;
+    }
 };
 constexpr int kPartLbs[3] = {16, 32, 64};
 
@@ -121,6 +138,7 @@ constexpr size_t kMaxPartLdsBytes = 160 * 1024;   // LDS one workgroup may alloc
 struct PartChoice {
     int plan = -1, S = 0, threads = 0;
     size_t lds = 0;
+    int wgs = 1;  // workgroups resident per CU at this size
 };
 bool choose_partition(const sbs_lhs *h, int tc, int64_t m, PartChoice *out);
 hipError_t launch_partition(const sbs_lhs *h, const PartChoice &c, int tc, int tin, int tout, const void *in,

@@ -57,6 +57,8 @@ struct Rec<SBS_TRI, T> {
     }
     static __device__ __forceinline__ void put(const Fwd &s, T *p) { p[0] = s.y1; }
     static __device__ __forceinline__ void get(Fwd &s, const T *p) { s.y1 = p[0]; }
+    // what the backward sweep takes over from the finished forward sweep
+    static __device__ __forceinline__ void link(const Fwd &, Bwd &) {}
 };
 
 template <typename T>
@@ -99,6 +101,50 @@ struct Rec<SBS_PENTA, T> {
         s.g2 = p[0];
         s.g1 = p[kWave];
     }
+    static __device__ __forceinline__ void link(const Fwd &, Bwd &) {}
+};
+
+// Periodic tridiagonal (Section 3.3) through A = A' + u v^T: the sweeps of
+// A' (same steps as Rec<SBS_TRI>) plus, in the forward sweep, the running dot
+// product acc = sum wt_i d_i, which at the end equals (v.y) / (1 + v.z) for
+// y = A'^{-1} d.  The backward sweep carries y and stores x_i = y_i - acc z_i.
+template <typename T>
+struct Rec<SBS_TRI_PERIODIC, T> {
+    using Row = PeriodicRow<T>;
+    static constexpr int S = 1;
+    struct Fwd {
+        T y1 = T(0), acc = T(0);
+    };
+    struct Bwd {
+        T x1 = T(0);  // carried y_{i+1} (of A'^{-1} d, before the correction)
+        T s = T(0);
+    };
+    struct FC {
+        T a_s, inv, wt;
+    };
+    struct BC {
+        T chat, z;
+    };
+    static __device__ __forceinline__ FC fc(const Row *f, int i) { return {f[i].a_s, f[i].inv, f[i].wt}; }
+    static __device__ __forceinline__ BC bc(const Row *f, int i) { return {f[i].chat, f[i].z}; }
+    static __device__ __forceinline__ T fwd(const FC &c, T d, Fwd &s) {
+        const T y = fma(-c.a_s, s.y1, d * c.inv);
+        s.acc = fma(c.wt, d, s.acc);
+        // Keep the dot product in row order: left free, the scheduler runs
+        // the y chain of a whole chunk first and holds every d of the chunk
+        // live for the deferred products (about 70 more registers).
+        asm volatile("" : "+v"(s.acc));
+        s.y1 = y;
+        return y;
+    }
+    static __device__ __forceinline__ T bwd(const BC &c, T yh, Bwd &s) {
+        const T y = fma(-c.chat, s.x1, yh);
+        s.x1 = y;
+        return fma(-c.z, s.s, y);
+    }
+    static __device__ __forceinline__ void put(const Fwd &s, T *p) { p[0] = s.y1; }
+    static __device__ __forceinline__ void get(Fwd &s, const T *p) { s.y1 = p[0]; }
+    static __device__ __forceinline__ void link(const Fwd &f, Bwd &b) { b.s = f.acc; }
 };
 
 // Addressing.  Row r of a wave's 64 columns starts at base + r * rs bytes
@@ -399,6 +445,7 @@ __device__ __forceinline__ void sweep_wave(const typename Rec<KIND, T>::Row *__r
     if constexpr (MODE == MODE_RESIDENT) {
         fwd_chunk<KIND, T, L>(frow(0), cur, st);
         typename R::Bwd bs;
+        R::link(st, bs);
         back_chunk<KIND, T, Tout, L, BIG>(frow(0), cur, bs, bout, lout, 0, n, rso);
         return;
     } else {
@@ -421,6 +468,7 @@ __device__ __forceinline__ void sweep_wave(const typename Rec<KIND, T>::Row *__r
         // Backward sweep; cur holds the forward values of the last chunk and
         // buffer (K-1)&1 its factor rows.
         typename R::Bwd bs;
+        R::link(st, bs);
         if (K >= 2) {
             fv.load(fac + (K - 2) * L, lane);
             if constexpr (MODE == MODE_CHUNKED)
@@ -539,7 +587,10 @@ __device__ __forceinline__ T part_correct(T v, const T *spt, const T (&xt)[KIND 
     return v;
 }
 
-// Copies [fac | spk | rinv] (and anything after it in `extra`) into LDS.
+// Bytes of a plan's block map (P ints, 16-byte aligned) at the end of its blob.
+__device__ __forceinline__ int map_bytes(int P) { return (P * 4 + 15) / 16 * 16; }
+
+// Copies a plan blob [fac | spk | rinv | map] into LDS.
 __device__ __forceinline__ void stage_blob(unsigned char *lds, const unsigned char *blob, int bytes) {
     typedef unsigned int U4 __attribute__((ext_vector_type(4)));
     const U4 *src = reinterpret_cast<const U4 *>(blob);
@@ -555,18 +606,21 @@ __global__ __launch_bounds__(MAXT) void k_part(const unsigned char *__restrict__
     using Row = typename R::Row;
     constexpr int H = KIND / 2;
     extern __shared__ __align__(16) unsigned char lds[];
-    stage_blob(lds, blob, fac_bytes + spk_bytes + rinv_bytes);
+    const int blob_bytes = fac_bytes + spk_bytes + rinv_bytes + map_bytes(P);
+    stage_blob(lds, blob, blob_bytes);
     const Row *lfac = reinterpret_cast<const Row *>(lds);
     const T *lspk = reinterpret_cast<const T *>(lds + fac_bytes);
     const T *lrinv = reinterpret_cast<const T *>(lds + fac_bytes + spk_bytes);
-    T *lred = reinterpret_cast<T *>(lds + fac_bytes + spk_bytes + rinv_bytes);
+    const int *lmap = reinterpret_cast<const int *>(lds + fac_bytes + spk_bytes + rinv_bytes);
+    T *lred = reinterpret_cast<T *>(lds + blob_bytes);
     const int ldr = Nr + 1;  // odd stride: the systems' rows fall in different banks
     __syncthreads();
 
     const int l = threadIdx.x, p = l / S, s = l - p * S;
     const int r0 = p * LB;
-    const Row *fr = lfac + r0;
-    const T *sp = lspk + r0 * 2 * H;
+    const int q = lmap[p];  // stored copy of this block's factor and spikes
+    const Row *fr = lfac + q * LB;
+    const T *sp = lspk + q * LB * 2 * H;
     T *red = lred + s * ldr;
     const T *rt = lrinv + (2 * H * p + H) * Nr;        // rows of x_{p+1}[0:H]
     const T *rb = lrinv + (2 * H * (p - 1)) * Nr;      // rows of x_{p-1}[lb-H:lb]
@@ -612,7 +666,7 @@ __global__ __launch_bounds__(MAXT) void k_part_refine(const unsigned char *__res
     using Row = typename R::Row;
     constexpr int H = KIND / 2;
     extern __shared__ __align__(16) unsigned char lds[];
-    const int blob_bytes = fac_bytes + spk_bytes + rinv_bytes;
+    const int blob_bytes = fac_bytes + spk_bytes + rinv_bytes + map_bytes(P);
     const int npad = P * LB;
     stage_blob(lds, blob, blob_bytes);
     BandRow *lband = reinterpret_cast<BandRow *>(lds + blob_bytes);
@@ -620,6 +674,7 @@ __global__ __launch_bounds__(MAXT) void k_part_refine(const unsigned char *__res
     const Row *lfac = reinterpret_cast<const Row *>(lds);
     const float *lspk = reinterpret_cast<const float *>(lds + fac_bytes);
     const float *lrinv = reinterpret_cast<const float *>(lds + fac_bytes + spk_bytes);
+    const int *lmap = reinterpret_cast<const int *>(lds + fac_bytes + spk_bytes + rinv_bytes);
     unsigned char *after = lds + blob_bytes + npad * sizeof(BandRow);
     const int ldr = Nr + 1;
     float *lred = reinterpret_cast<float *>(after);
@@ -628,8 +683,9 @@ __global__ __launch_bounds__(MAXT) void k_part_refine(const unsigned char *__res
 
     const int l = threadIdx.x, p = l / S, s = l - p * S;
     const int r0 = p * LB;
-    const Row *fr = lfac + r0;
-    const float *sp = lspk + r0 * 2 * H;
+    const int q = lmap[p];
+    const Row *fr = lfac + q * LB;
+    const float *sp = lspk + q * LB * 2 * H;
     float *red = lred + s * ldr;
     const float *rt = lrinv + (2 * H * p + H) * Nr;
     const float *rb = lrinv + (2 * H * (p - 1)) * Nr;
@@ -969,6 +1025,7 @@ template <typename T, typename Tin, typename Tout>
 hipError_t dispatch_kind(const sbs_lhs *h, int mode, const void *fac, const void *in, void *out,
                          int64_t m, hipStream_t s) {
     if (h->kind == SBS_TRI) return dispatch_mode<SBS_TRI, T, Tin, Tout>(h, mode, fac, in, out, m, s);
+    if (h->kind == SBS_TRI_PERIODIC) return dispatch_mode<SBS_TRI_PERIODIC, T, Tin, Tout>(h, mode, fac, in, out, m, s);
     return dispatch_mode<SBS_PENTA, T, Tin, Tout>(h, mode, fac, in, out, m, s);
 }
 
@@ -979,6 +1036,9 @@ size_t chunked_lds_bytes(const sbs_lhs *h, int tc) {
     if (h->kind == SBS_TRI)
         return tc == 0 ? wave_lds_bytes<SBS_TRI, double, 32, MODE_CHUNKED>(K)
                        : wave_lds_bytes<SBS_TRI, float, 32, MODE_CHUNKED>(K);
+    if (h->kind == SBS_TRI_PERIODIC)
+        return tc == 0 ? wave_lds_bytes<SBS_TRI_PERIODIC, double, 32, MODE_CHUNKED>(K)
+                       : wave_lds_bytes<SBS_TRI_PERIODIC, float, 32, MODE_CHUNKED>(K);
     return tc == 0 ? wave_lds_bytes<SBS_PENTA, double, 32, MODE_CHUNKED>(K)
                    : wave_lds_bytes<SBS_PENTA, float, 32, MODE_CHUNKED>(K);
 }
@@ -1004,11 +1064,14 @@ hipError_t launch_sweep(const sbs_lhs *h, int variant, int tc, int tin, int tout
 
 namespace {
 template <int KIND, typename T, int LB>
-hipError_t go_part(const sbs_lhs *h, const PartChoice &c, const void *in, void *out, int64_t m, hipStream_t s) {
-    constexpr int MAXT = (LB == 64 && sizeof(T) == 8) ? 512 : 1024;
-    const PartPlan &pp = h->part[c.plan];
-    const bool f64 = sizeof(T) == 8;
-    auto kern = k_part<KIND, T, T, T, LB, MAXT>;
+constexpr int part_maxt() {
+    return (LB == 64 && sizeof(T) == 8) ? 512 : 1024;
+}
+
+// The partitioned kernel of (KIND, T, LB), allowed the whole LDS of a CU.
+template <int KIND, typename T, int LB>
+hipError_t part_kernel(const void **fn) {
+    auto kern = k_part<KIND, T, T, T, LB, part_maxt<KIND, T, LB>()>;
     static bool attr = false;
     if (!attr) {
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
@@ -1016,12 +1079,44 @@ hipError_t go_part(const sbs_lhs *h, const PartChoice &c, const void *in, void *
         if (e != hipSuccess) return e;
         attr = true;
     }
+    *fn = reinterpret_cast<const void *>(kern);
+    return hipSuccess;
+}
+
+template <int KIND, typename T>
+int part_wgs_lb(int lb, int threads, size_t lds) {
+    const void *fn = nullptr;
+    hipError_t e = lb == 16 ? part_kernel<KIND, T, 16>(&fn) : lb == 32 ? part_kernel<KIND, T, 32>(&fn)
+                                                                       : part_kernel<KIND, T, 64>(&fn);
+    int wgs = 0;
+    if (e != hipSuccess || hipOccupancyMaxActiveBlocksPerMultiprocessor(&wgs, fn, threads, lds) != hipSuccess)
+        return 0;
+    return wgs;
+}
+
+// Workgroups of the partitioned kernel that one CU holds at once (registers,
+// waves and LDS together).
+int part_wgs_per_cu(int kind, int tc, int lb, int threads, size_t lds) {
+    if (kind == SBS_TRI)
+        return tc == 0 ? part_wgs_lb<SBS_TRI, double>(lb, threads, lds) : part_wgs_lb<SBS_TRI, float>(lb, threads, lds);
+    return tc == 0 ? part_wgs_lb<SBS_PENTA, double>(lb, threads, lds)
+                   : part_wgs_lb<SBS_PENTA, float>(lb, threads, lds);
+}
+
+template <int KIND, typename T, int LB>
+hipError_t go_part(const sbs_lhs *h, const PartChoice &c, const void *in, void *out, int64_t m, hipStream_t s) {
+    constexpr int MAXT = part_maxt<KIND, T, LB>();
+    const PartPlan &pp = h->part[c.plan];
+    const bool f64 = sizeof(T) == 8;
+    auto kern = k_part<KIND, T, T, T, LB, MAXT>;
+    const void *fn = nullptr;
+    if (hipError_t e = part_kernel<KIND, T, LB>(&fn); e != hipSuccess) return e;
     if (c.threads > MAXT) return hipErrorInvalidValue;
     const int ngroups = (int)((m + c.S - 1) / c.S);
     int cus = 256;
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, h->device);
-    const int per_cu = (int)std::max<size_t>(1, kMaxPartLdsBytes / c.lds);
-    const int grid = std::min(ngroups, cus * per_cu);
+    const int per_cu = std::max(1, c.wgs);
+    const int grid = (int)std::min<int64_t>(ngroups, (int64_t)cus * per_cu);
     hipLaunchKernelGGL(kern, dim3(grid), dim3(c.threads), c.lds, s,
                        static_cast<const unsigned char *>(f64 ? pp.blob64 : pp.blob32),
                        (int)(f64 ? pp.fac_bytes64 : pp.fac_bytes32), (int)(f64 ? pp.spk_bytes64 : pp.spk_bytes32),
@@ -1082,7 +1177,7 @@ bool choose_partition_refine(const sbs_lhs *h, int64_t m, PartChoice *out) {
         while (S > 16 && S * pp.P > 512) S /= 2;
         if (S * pp.P > 512) continue;
         const size_t npad = (size_t)pp.P * pp.lb;
-        const size_t lds = pp.fac_bytes32 + pp.spk_bytes32 + pp.rinv_bytes32 + npad * sizeof(BandRow) +
+        const size_t lds = pp.blob_bytes(1) + npad * sizeof(BandRow) +
                            ((size_t)S * (pp.Nr + 1) * 4 + 15) / 16 * 16 + (size_t)S * pp.P * 2 * H * 8;
         if (lds > kMaxPartLdsBytes) continue;
         const int64_t groups = (m + S - 1) / S;
@@ -1111,35 +1206,44 @@ hipError_t launch_partition_refine(const sbs_lhs *h, const PartChoice &c, const 
                     : go_part_refine<SBS_PENTA, 32>(h, c, b, x, m, sweeps, stream);
 }
 
+// Block length and systems per workgroup S for the partitioned solve.  The
+// score is the number of waves that run at once over the whole batch; ties go
+// to more workgroups per CU (each has its own barrier, so one can load while
+// another computes), then to longer blocks (fewer interfaces), then to larger
+// S.  S >= 16 keeps every row access a whole 128-byte line (FP64); narrower
+// workgroups (down to 4 systems) are only tried when the batch is too small
+// to give every CU a group.
 bool choose_partition(const sbs_lhs *h, int tc, int64_t m, PartChoice *out) {
     const size_t elem = tc == 0 ? 8 : 4;
     int cus = 256;
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, h->device);
     PartChoice best;
     int64_t best_waves = -1;
+    int best_wgs = 0;
     for (int q = 2; q >= 0; --q) {  // largest block first: fewest interfaces
         const PartPlan &pp = h->part[q];
         if (!pp.ok || m < 1) continue;
         const int maxt = (pp.lb == 64 && elem == 8) ? 512 : 1024;
-        int S = 64;
-        while (S > 16 && S * pp.P > maxt) S /= 2;
-        if (S * pp.P > maxt) continue;
-        const size_t blob = tc == 0 ? pp.fac_bytes64 + pp.spk_bytes64 + pp.rinv_bytes64
-                                    : pp.fac_bytes32 + pp.spk_bytes32 + pp.rinv_bytes32;
-        auto lds_for = [&](int s) { return blob + ((size_t)s * (pp.Nr + 1) * elem + 15) / 16 * 16; };
-        if (lds_for(S) > kMaxPartLdsBytes) continue;
-        // At least 16 systems per workgroup keeps every row access a whole
-        // 128-byte line; with few systems, narrower workgroups (down to 4
-        // systems) spread the batch over more compute units instead.
-        while (S > 4 && (m + S - 1) / S < cus) S /= 2;
-        const int64_t groups = (m + S - 1) / S;
-        const int64_t waves = std::min<int64_t>(groups * ((S * pp.P + kWave - 1) / kWave), 4096);
-        if (waves > best_waves) {
-            best_waves = waves;
-            best.plan = q;
-            best.S = S;
-            best.threads = S * pp.P;
-            best.lds = lds_for(S);
+        const size_t blob = pp.blob_bytes(tc);
+        for (int S = 64; S >= 4; S /= 2) {
+            if (S < 16 && (m + 2 * S - 1) / (2 * S) >= cus) break;  // the wider S already fills the CUs
+            const int threads = S * pp.P;
+            if (threads > maxt) continue;
+            const size_t lds = blob + ((size_t)S * (pp.Nr + 1) * elem + 15) / 16 * 16;
+            if (lds > kMaxPartLdsBytes) continue;
+            const int wgs = part_wgs_per_cu(h->kind, tc, pp.lb, threads, lds);
+            if (wgs < 1) continue;
+            const int64_t groups = (m + S - 1) / S;
+            const int64_t waves = std::min<int64_t>(groups, (int64_t)cus * wgs) * ((threads + kWave - 1) / kWave);
+            if (waves > best_waves || (waves == best_waves && wgs > best_wgs)) {
+                best_waves = waves;
+                best_wgs = wgs;
+                best.plan = q;
+                best.S = S;
+                best.threads = threads;
+                best.lds = lds;
+                best.wgs = wgs;
+            }
         }
     }
     if (best.plan < 0) return false;

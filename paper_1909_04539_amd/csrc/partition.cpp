@@ -16,6 +16,7 @@ constexpr int kMaxBlocks = 64;
 constexpr int kMaxInterface = 90;  // interface unknowns: the FP64 inverse stays under 64 KB of LDS
 
 size_t align16(size_t v) { return (v + 15) / 16 * 16; }
+size_t align256(size_t v) { return (v + 255) / 256 * 256; }  // each blob starts as a device allocation would
 
 // Gauss-Jordan inverse with partial pivoting, in place (row-major n x n).
 bool invert(std::vector<double> &a, int n) {
@@ -54,10 +55,11 @@ bool invert(std::vector<double> &a, int n) {
 }
 
 struct HostPlan {
-    int lb = 0, P = 0, Nr = 0;
-    std::vector<unsigned char> fac;  // P*lb FP64 rows
-    std::vector<double> spk;         // P*lb*2h
+    int lb = 0, P = 0, Nr = 0, D = 0;
+    std::vector<unsigned char> fac;  // D*lb FP64 rows (distinct blocks only)
+    std::vector<double> spk;         // D*lb*2h
     std::vector<double> rinv;        // Nr*Nr
+    std::vector<int> map;            // block p -> stored block map[p]
 };
 
 template <typename Row, typename FactorFn, typename SolveFn>
@@ -135,9 +137,24 @@ bool build_plan(int kind, int64_t n, const double *bands, int lb, FactorFn facto
     hp.lb = lb;
     hp.P = P;
     hp.Nr = Nr;
-    hp.fac.resize(sizeof(Row) * npad);
-    std::memcpy(hp.fac.data(), rows.data(), hp.fac.size());
-    hp.spk.swap(spk);
+    // Blocks whose factor rows and spikes are bit-identical (every interior
+    // block of a matrix with constant bands) are stored once.
+    const size_t rb = sizeof(Row) * lb, sb = sizeof(double) * lb * 2 * h;
+    hp.map.assign(P, -1);
+    hp.fac.clear();
+    hp.spk.clear();
+    for (int p = 0; p < P; ++p) {
+        const unsigned char *rp = reinterpret_cast<const unsigned char *>(rows.data() + (int64_t)p * lb);
+        const double *sp = spk.data() + (size_t)p * lb * 2 * h;
+        for (int q = 0; q < hp.D && hp.map[p] < 0; ++q)
+            if (!std::memcmp(hp.fac.data() + q * rb, rp, rb) && !std::memcmp(hp.spk.data() + q * lb * 2 * h, sp, sb))
+                hp.map[p] = q;
+        if (hp.map[p] < 0) {
+            hp.map[p] = hp.D++;
+            hp.fac.insert(hp.fac.end(), rp, rp + rb);
+            hp.spk.insert(hp.spk.end(), sp, sp + (size_t)lb * 2 * h);
+        }
+    }
     hp.rinv.swap(R);
     return true;
 }
@@ -153,21 +170,29 @@ PentaRow<float> narrow_row(const PentaRow<double> &r) {
     return {(float)r.eps_s, (float)r.beta_s, (float)r.inv, (float)r.gamma, (float)r.delta, 0.f, 0.f, 0.f};
 }
 
-// Serialise one plan as [fac | spk | rinv] in FP64 and in FP32.
+// memcpy that accepts an empty source (an empty vector's data() may be null).
+void copy_bytes(void *dst, const void *src, size_t bytes) {
+    if (bytes) std::memcpy(dst, src, bytes);
+}
+
+// Serialise one plan as [fac | spk | rinv | map] in FP64 and in FP32.
 template <typename Row64, typename Row32>
 void serialise(const HostPlan &hp, std::vector<unsigned char> &b64, std::vector<unsigned char> &b32, PartPlan &pp) {
     const size_t nrow = hp.fac.size() / sizeof(Row64);
+    const size_t map_bytes = align16(hp.map.size() * sizeof(int));
     pp.fac_bytes64 = align16(hp.fac.size());
     pp.spk_bytes64 = align16(hp.spk.size() * 8);
     pp.rinv_bytes64 = align16(hp.rinv.size() * 8);
-    b64.assign(pp.fac_bytes64 + pp.spk_bytes64 + pp.rinv_bytes64, 0);
-    std::memcpy(b64.data(), hp.fac.data(), hp.fac.size());
-    std::memcpy(b64.data() + pp.fac_bytes64, hp.spk.data(), hp.spk.size() * 8);
-    std::memcpy(b64.data() + pp.fac_bytes64 + pp.spk_bytes64, hp.rinv.data(), hp.rinv.size() * 8);
+    b64.assign(pp.fac_bytes64 + pp.spk_bytes64 + pp.rinv_bytes64 + map_bytes, 0);
+    copy_bytes(b64.data(), hp.fac.data(), hp.fac.size());
+    copy_bytes(b64.data() + pp.fac_bytes64, hp.spk.data(), hp.spk.size() * 8);
+    copy_bytes(b64.data() + pp.fac_bytes64 + pp.spk_bytes64, hp.rinv.data(), hp.rinv.size() * 8);
+    copy_bytes(b64.data() + pp.fac_bytes64 + pp.spk_bytes64 + pp.rinv_bytes64, hp.map.data(),
+                hp.map.size() * sizeof(int));
     pp.fac_bytes32 = align16(nrow * sizeof(Row32));
     pp.spk_bytes32 = align16(hp.spk.size() * 4);
     pp.rinv_bytes32 = align16(hp.rinv.size() * 4);
-    b32.assign(pp.fac_bytes32 + pp.spk_bytes32 + pp.rinv_bytes32, 0);
+    b32.assign(pp.fac_bytes32 + pp.spk_bytes32 + pp.rinv_bytes32 + map_bytes, 0);
     const Row64 *r64 = reinterpret_cast<const Row64 *>(hp.fac.data());
     Row32 *r32 = reinterpret_cast<Row32 *>(b32.data());
     for (size_t i = 0; i < nrow; ++i) r32[i] = narrow_row<Row32>(r64[i]);
@@ -175,6 +200,10 @@ void serialise(const HostPlan &hp, std::vector<unsigned char> &b64, std::vector<
     for (size_t i = 0; i < hp.spk.size(); ++i) s32[i] = (float)hp.spk[i];
     float *q32 = reinterpret_cast<float *>(b32.data() + pp.fac_bytes32 + pp.spk_bytes32);
     for (size_t i = 0; i < hp.rinv.size(); ++i) q32[i] = (float)hp.rinv[i];
+    copy_bytes(b32.data() + pp.fac_bytes32 + pp.spk_bytes32 + pp.rinv_bytes32, hp.map.data(),
+                hp.map.size() * sizeof(int));
+    pp.map_bytes = map_bytes;
+    pp.D = hp.D;
 }
 
 }  // namespace
@@ -205,7 +234,7 @@ sbs_status build_partitions(sbs_lhs *h, const double *bands) {
         pp.P = hp.P;
         pp.Nr = hp.Nr;
         pp.ok = true;
-        total += align16(b64[q].size()) + align16(b32[q].size());
+        total += align256(b64[q].size()) + align256(b32[q].size());
     }
     if (total == 0) return SBS_OK;
     void *dev = nullptr;
@@ -219,11 +248,11 @@ sbs_status build_partitions(sbs_lhs *h, const double *bands) {
         if (hipMemcpy(base + at, b64[q].data(), b64[q].size(), hipMemcpyHostToDevice) != hipSuccess)
             return SBS_ERR_DEVICE;
         pp.blob64 = base + at;
-        at += align16(b64[q].size());
+        at += align256(b64[q].size());
         if (hipMemcpy(base + at, b32[q].data(), b32[q].size(), hipMemcpyHostToDevice) != hipSuccess)
             return SBS_ERR_DEVICE;
         pp.blob32 = base + at;
-        at += align16(b32[q].size());
+        at += align256(b32[q].size());
     }
     h->device_bytes += (int64_t)total;
     return SBS_OK;

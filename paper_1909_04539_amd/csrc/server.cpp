@@ -311,6 +311,7 @@ sbs_status sbs_server_create(size_t budget_bytes, int32_t max_streams, int32_t m
 
 sbs_status sbs_server_register(sbs_server *srv, sbs_handle h, int32_t *lhs_id) {
     if (!srv || !h || !lhs_id) return SBS_ERR_INVALID_ARG;
+    if (h->kind != SBS_TRI && h->kind != SBS_PENTA) return SBS_ERR_INVALID_ARG;  // tiles cover the banded kinds
     std::lock_guard<std::mutex> lk(srv->mu);
     *lhs_id = (int32_t)srv->lhs.size();
     srv->lhs.push_back(h);

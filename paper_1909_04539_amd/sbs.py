@@ -22,7 +22,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libsbs.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "sbs.h")
 
-SBS_TRI, SBS_PENTA = 3, 5
+SBS_TRI, SBS_PENTA, SBS_TRI_PERIODIC = 3, 5, 13
 SBS_F64, SBS_F32 = 0, 1
 VARIANT_AUTO, VARIANT_RESIDENT, VARIANT_CHUNKED, VARIANT_STREAM, VARIANT_PARTITION = 0, 1, 2, 3, 4
 
@@ -142,8 +142,9 @@ def sbs_version() -> str:
 def sbs_factor_shared_lhs(kind: int, bands) -> int:
     """Factor once (host, FP64) and upload; returns the handle (an int)."""
     B = np.ascontiguousarray(np.asarray(bands, dtype=np.float64))
-    if B.ndim != 2 or B.shape[0] != kind:
-        raise ValueError(f"bands must have shape ({kind}, n)")
+    nb = 3 if kind == SBS_TRI_PERIODIC else kind
+    if B.ndim != 2 or B.shape[0] != nb:
+        raise ValueError(f"bands must have shape ({nb}, n)")
     h = ctypes.c_void_p()
     bad = ctypes.c_int64(-1)
     st = lib().sbs_factor_shared_lhs(kind, B.shape[1], B.ctypes.data, ctypes.byref(h), ctypes.byref(bad))

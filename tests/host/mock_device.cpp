@@ -64,7 +64,9 @@ hipError_t hipGetDevice(int *d) {
     return hipSuccess;
 }
 hipError_t hipMalloc(void **p, size_t n) {
-    *p = calloc(1, n ? n : 1);
+    const size_t bytes = (n + 255) / 256 * 256;  // device allocations are 256-byte aligned
+    *p = aligned_alloc(256, bytes ? bytes : 256);
+    if (*p) memset(*p, 0, bytes ? bytes : 256);
     return *p ? hipSuccess : hipErrorOutOfMemory;
 }
 hipError_t hipFree(void *p) {
@@ -105,6 +107,10 @@ hipError_t hipEventRecord(hipEvent_t e, hipStream_t s) {
     return hipSuccess;
 }
 hipError_t hipEventQuery(hipEvent_t e) { return e->pending.load() ? hipErrorNotReady : hipSuccess; }
+hipError_t hipMemcpy(void *dst, const void *src, size_t n, hipMemcpyKind) {
+    memcpy(dst, src, n);
+    return hipSuccess;
+}
 hipError_t hipMemcpyAsync(void *dst, const void *src, size_t n, hipMemcpyKind, hipStream_t s) {
     if (!s) {
         memcpy(dst, src, n);

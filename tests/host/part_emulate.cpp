@@ -1,0 +1,89 @@
+// Runs the partitioned solve on the host from the FP64 plan that
+// build_partitions serialises (the CPU stand-in for the device keeps the
+// uploaded blob in host memory), step for step as the kernel does: per block
+// p the factor and spikes of stored block map[p], the block solve, the
+// interface unknowns from rows of the stored inverse, the correction.
+//   part_emulate in.bin out.bin
+// in:  int32 kind, int64 n, int64 m, bands (kind x n doubles), rhs (n x m)
+// out: per block length 16, 32, 64: int32 lb (0 if no plan), P, D, Nr, then
+//      the n x m solution (only when the plan exists)
+#include <cstdio>
+#include <cstdlib>
+#include <vector>
+
+#include "factor_rows.h"
+#include "internal.h"
+
+using namespace sbs;
+
+template <typename Row, typename Solve>
+void emulate(const sbs_lhs &h, const PartPlan &pp, const double *rhs, int64_t m, double *x, Solve solve) {
+    const int H = h.kind / 2, lb = pp.lb, P = pp.P, Nr = pp.Nr;
+    const unsigned char *blob = static_cast<const unsigned char *>(pp.blob64);
+    const Row *fac = reinterpret_cast<const Row *>(blob);
+    const double *spk = reinterpret_cast<const double *>(blob + pp.fac_bytes64);
+    const double *rinv = reinterpret_cast<const double *>(blob + pp.fac_bytes64 + pp.spk_bytes64);
+    const int *map = reinterpret_cast<const int *>(blob + pp.fac_bytes64 + pp.spk_bytes64 + pp.rinv_bytes64);
+    const int64_t n = h.n;
+    std::vector<double> g((size_t)P * lb), red(Nr > 0 ? Nr : 1);
+    for (int64_t j = 0; j < m; ++j) {
+        for (int64_t i = 0; i < (int64_t)P * lb; ++i) g[i] = i < n ? rhs[i * m + j] : 0.0;
+        for (int p = 0; p < P; ++p) solve(lb, fac + (int64_t)map[p] * lb, g.data() + (int64_t)p * lb);
+        for (int p = 0; p < P; ++p) {
+            if (p <= P - 2)
+                for (int c = 0; c < H; ++c) red[2 * H * p + c] = g[(int64_t)p * lb + lb - H + c];
+            if (p >= 1)
+                for (int c = 0; c < H; ++c) red[2 * H * (p - 1) + H + c] = g[(int64_t)p * lb + c];
+        }
+        for (int p = 0; p < P; ++p) {
+            double xt[2] = {0, 0}, xb[2] = {0, 0};
+            for (int c = 0; c < H; ++c)
+                for (int k = 0; k < Nr; ++k) {
+                    if (p <= P - 2) xt[c] += rinv[(size_t)(2 * H * p + H + c) * Nr + k] * red[k];
+                    if (p >= 1) xb[c] += rinv[(size_t)(2 * H * (p - 1) + c) * Nr + k] * red[k];
+                }
+            const double *sp = spk + (size_t)map[p] * lb * 2 * H;
+            for (int t = 0; t < lb; ++t) {
+                const int64_t i = (int64_t)p * lb + t;
+                if (i >= n) continue;
+                double v = g[i];
+                for (int c = 0; c < H; ++c) v -= sp[t * 2 * H + c] * xt[c];
+                for (int c = 0; c < H; ++c) v -= sp[t * 2 * H + H + c] * xb[c];
+                x[i * m + j] = v;
+            }
+        }
+    }
+}
+
+int main(int argc, char **argv) {
+    if (argc != 3) return 2;
+    FILE *f = std::fopen(argv[1], "rb");
+    if (!f) return 2;
+    int32_t kind;
+    int64_t n, m;
+    if (std::fread(&kind, 4, 1, f) != 1 || std::fread(&n, 8, 1, f) != 1 || std::fread(&m, 8, 1, f) != 1) return 2;
+    std::vector<double> bands((size_t)kind * n), rhs((size_t)n * m), x((size_t)n * m);
+    if (std::fread(bands.data(), 8, bands.size(), f) != bands.size()) return 2;
+    if (std::fread(rhs.data(), 8, rhs.size(), f) != rhs.size()) return 2;
+    std::fclose(f);
+    sbs_lhs h;
+    h.kind = kind;
+    h.n = n;
+    if (build_partitions(&h, bands.data()) != SBS_OK) return 3;
+    FILE *o = std::fopen(argv[2], "wb");
+    if (!o) return 2;
+    for (int q = 0; q < 3; ++q) {
+        const PartPlan &pp = h.part[q];
+        int32_t hdr[4] = {pp.ok ? pp.lb : 0, pp.P, pp.D, pp.Nr};
+        std::fwrite(hdr, 4, 4, o);
+        if (!pp.ok) continue;
+        if (kind == SBS_TRI)
+            emulate<TriRow<double>>(h, pp, rhs.data(), m, x.data(), solve_tri_rows);
+        else
+            emulate<PentaRow<double>>(h, pp, rhs.data(), m, x.data(), solve_penta_rows);
+        std::fwrite(x.data(), 8, x.size(), o);
+    }
+    std::fclose(o);
+    if (h.pdev) std::free(h.pdev);
+    return 0;
+}

@@ -111,3 +111,21 @@ def test_server_argument_checks(L):
     assert L.sbs_server_wait(None, 1, 0, None, None) == 1
     assert L.sbs_server_release(None, 1) == 1
     assert L.sbs_server_destroy(None) == 0
+
+
+def test_periodic_factor_errors_without_device(L):
+    # Periodic tridiagonal handles (Section 3.3): n >= 3, corners must be
+    # finite, b_0 = 0 breaks the splitting at row 0, and the singular periodic
+    # Laplacian (rows sum to zero) makes 1 + v.z vanish: reported as row n.
+    ring = lambda n, b: np.stack([np.full(n, -1.0), np.full(n, b), np.full(n, -1.0)])
+    assert _factor(L, 13, 2, ring(2, 4.0))[0] == 1
+    B = ring(6, 4.0)
+    B[0, 0] = np.nan                                   # corner a_0
+    assert _factor(L, 13, 6, B)[0] == 3 and _factor(L, 13, 6, B)[2] == 0
+    B = ring(6, 4.0)
+    B[1, 0] = 0.0
+    st, h, bad = _factor(L, 13, 6, B)
+    assert st == 2 and h is None and bad == 0
+    for n in (3, 4, 5, 8, 64):
+        st, h, bad = _factor(L, 13, n, ring(n, 2.0))
+        assert st == 2 and h is None and bad == n

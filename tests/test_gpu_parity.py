@@ -42,13 +42,16 @@ def chunked_fits(kind, n, elem=8):
     return K * S * 64 * elem + 2 * 32 * row <= 64 * 1024
 
 
-def partition_available(kind, n, elem=8):
-    """Mirror of the library's rule: some block length lb in (16, 32, 64) with
-    P = ceil(n/lb) <= 64 blocks, at most 90 interface unknowns 2h(P-1), and
-    block factors + spikes + interface inverse + one workgroup's interface
-    values (S >= 16 systems) within 160 KiB of LDS."""
+def partition_available(kind, n, elem=8, m=1 << 20, cus=256):
+    """Mirror of the library's rule (for matrices whose blocks all differ):
+    some block length lb in (16, 32, 64) with P = ceil(n/lb) <= 64 blocks, at
+    most 90 interface unknowns 2h(P-1), and for some S systems per workgroup
+    (64, 32, 16; 8 and 4 only while a batch of m leaves CUs idle) at most
+    512 (lb 64, FP64) or 1024 threads and block factors + spikes + interface
+    inverse + block map + interface values within 160 KiB of LDS."""
     h = kind // 2
     row = (4 if kind == 3 else 8) * elem
+    r16 = lambda v: -(-v // 16) * 16
     for lb in (16, 32, 64):
         P = -(-n // lb)
         Nr = 2 * h * (P - 1)
@@ -56,14 +59,15 @@ def partition_available(kind, n, elem=8):
             continue
         maxt = 512 if (lb == 64 and elem == 8) else 1024
         S = 64
-        while S > 16 and S * P > maxt:
+        while S >= 4:
+            if S < 16 and -(-m // (2 * S)) >= cus:
+                break
+            if S * P <= maxt:
+                lds = (r16(P * lb * row) + r16(P * lb * 2 * h * elem) + r16(Nr * Nr * elem) + r16(P * 4)
+                       + r16(S * (Nr + 1) * elem))
+                if lds <= 160 * 1024:
+                    return True
             S //= 2
-        if S * P > maxt:
-            continue
-        r16 = lambda v: -(-v // 16) * 16
-        lds = r16(P * lb * row) + r16(P * lb * 2 * h * elem) + r16(Nr * Nr * elem) + r16(S * (Nr + 1) * elem)
-        if lds <= 160 * 1024:
-            return True
     return False
 
 
@@ -90,7 +94,7 @@ def test_fp64_matches_oracle(kind, variant, n, m):
     B = bands_for(kind, n, 1000 * kind + n)
     rhs = np.random.default_rng(n * 7 + m).uniform(-1, 1, (n, m))
     if (variant == sbs.VARIANT_CHUNKED and not chunked_fits(kind, n)) or \
-            (variant == sbs.VARIANT_PARTITION and not partition_available(kind, n)):
+            (variant == sbs.VARIANT_PARTITION and not partition_available(kind, n, m=m)):
         with pytest.raises(sbs.SbsError) as e:
             gpu_solve(kind, B, rhs, variant)
         assert e.value.status == 1
@@ -110,7 +114,7 @@ def test_auto_variant_query(kind, n):
     # what AUTO runs: partitioned when a plan exists, else resident / chunked / stream
     with sbs.SharedLhs(kind, bands_for(kind, n, n)) as lhs:
         for dtype, elem in ((sbs.SBS_F64, 8), (sbs.SBS_F32, 4)):
-            if partition_available(kind, n, elem):
+            if partition_available(kind, n, elem, m=1000):
                 want = sbs.VARIANT_PARTITION
             elif n <= 64:
                 want = sbs.VARIANT_RESIDENT
@@ -124,7 +128,7 @@ def test_auto_variant_query(kind, n):
 @pytest.mark.parametrize("kind", [3, 5])
 @pytest.mark.parametrize("n,m", [(64, 4096), (65, 33), (129, 1000), (500, 17), (1024, 3000), (2048, 130)])
 def test_partition_fp32(kind, n, m):
-    if not partition_available(kind, n, elem=4):
+    if not partition_available(kind, n, elem=4, m=m):
         pytest.skip("no partition plan")
     B = bands_for(kind, n, 9 + n)
     rhs = np.random.default_rng(n + m).uniform(-1, 1, (n, m)).astype(np.float32)
@@ -181,9 +185,10 @@ def test_handle_storage_is_independent_of_batch_size():
             # FP64 factor + FP32 shadow + original bands, per padded row ...
             per_row = {3: 32 + 16 + 64, 5: 64 + 32 + 64}[kind]
             # ... plus up to three partition plans (block factors and spikes in
-            # FP64 and FP32, and an interface inverse of at most 90 x 90)
+            # FP64 and FP32, an interface inverse of at most 90 x 90, a block
+            # map of at most 64 ints, each blob 256-byte aligned)
             plan_row = {3: (32 + 16) * 3 // 2, 5: (64 + 32) * 3 // 2}[kind]
-            assert rows * per_row <= lhs.device_bytes <= rows * per_row + 3 * (rows * plan_row + 90 * 90 * 12 + 64)
+            assert rows * per_row <= lhs.device_bytes <= rows * per_row + 3 * (rows * plan_row + 90 * 90 * 12 + 2048)
     # Shared LHS storage against one copy per system (the storage counts
     # closing Sections 3.1 and 4.1): 3N + MN vs 4MN, 5N + MN vs 6MN.
     M, N = 65536, 1024

@@ -1,0 +1,103 @@
+"""Host side of the partitioned solve, on the CPU: the plan that
+build_partitions serialises (block factors, spikes, inverse of the interface
+system, and the map that lets bit-identical blocks share one stored copy) is
+run step for step by tests/host/part_emulate.cpp, built with g++ and
+AddressSanitizer against the CPU stand-in for the device calls, and compared
+with the oracle."""
+import os
+import shutil
+import struct
+import subprocess
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1909_04539_amd import workloads as W
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+CSRC = os.path.join(ROOT, "paper_1909_04539_amd", "csrc")
+
+
+@pytest.fixture(scope="module")
+def exe(tmp_path_factory):
+    if not shutil.which("g++") or not os.path.isdir("/opt/rocm/include/hip"):
+        pytest.skip("needs g++ and the HIP headers")
+    out = str(tmp_path_factory.mktemp("part") / "part_emulate")
+    cmd = ["g++", "-std=c++17", "-O1", "-g", "-fsanitize=address,undefined", "-fno-omit-frame-pointer", "-pthread",
+           "-D__HIP_PLATFORM_AMD__", "-I/opt/rocm/include", "-I", os.path.join(ROOT, "include"), "-I", CSRC,
+           os.path.join(CSRC, "partition.cpp"), os.path.join(HERE, "host", "mock_device.cpp"),
+           os.path.join(HERE, "host", "part_emulate.cpp"), "-o", out]
+    subprocess.run(cmd, check=True)
+    return out
+
+
+def run(exe, tmp_path, kind, B, rhs):
+    n, m = rhs.shape
+    src, dst = str(tmp_path / "in.bin"), str(tmp_path / "out.bin")
+    with open(src, "wb") as f:
+        f.write(struct.pack("<iqq", kind, n, m))
+        f.write(np.ascontiguousarray(B, dtype=np.float64).tobytes())
+        f.write(np.ascontiguousarray(rhs, dtype=np.float64).tobytes())
+    r = subprocess.run([exe, src, dst], capture_output=True, text=True, timeout=120,
+                       env=dict(os.environ, ASAN_OPTIONS="detect_leaks=1", UBSAN_OPTIONS="halt_on_error=1"))
+    assert r.returncode == 0, r.stderr
+    plans = []
+    with open(dst, "rb") as f:
+        for _ in range(3):
+            lb, P, D, Nr = struct.unpack("<4i", f.read(16))
+            x = np.frombuffer(f.read(8 * n * m), dtype=np.float64).reshape(n, m) if lb else None
+            plans.append((lb, P, D, Nr, x))
+    return plans
+
+
+def colrel(x, ref):
+    num = np.max(np.abs(x - ref), axis=0)
+    den = np.maximum(np.max(np.abs(ref), axis=0), np.finfo(float).tiny)
+    return float(np.max(num / den))
+
+
+def dominant(kind, n, seed):
+    rng = np.random.default_rng(seed)
+    if kind == 3:
+        return W.tri_dominant_bands(rng, n)
+    B = rng.uniform(-1, 1, (5, n))
+    B[2] = np.sum(np.abs(np.delete(B, 2, axis=0)), axis=0) + rng.uniform(1, 2, n)
+    return W.zero_outside(B)
+
+
+@pytest.mark.parametrize("kind", [3, 5])
+@pytest.mark.parametrize("n", [1, 2, 3, 5, 16, 17, 31, 64, 100, 256, 1000, 1024, 2048])
+def test_plan_solves_like_the_oracle(exe, tmp_path, kind, n):
+    B = dominant(kind, n, 50 + n)
+    rhs = np.random.default_rng(n).uniform(-1, 1, (n, 3))
+    ref = oracle.solve(kind, B, rhs)
+    found = 0
+    for lb, P, D, Nr, x in run(exe, tmp_path, kind, B, rhs):
+        if not lb:
+            continue
+        found += 1
+        assert P == -(-n // lb) and Nr == (kind // 2) * 2 * (P - 1)
+        assert 1 <= D <= P
+        assert colrel(x, ref) <= 1e-13, (lb, P, D)
+    assert found >= 1 or kind == 5 and n > 1400
+
+
+@pytest.mark.parametrize("kind,n,lb", [(5, 1024, 64), (3, 512, 64), (3, 1000, 32), (5, 200, 16)])
+def test_constant_bands_store_three_blocks(exe, tmp_path, kind, n, lb):
+    # Constant bands with truncated ends: every interior block has the same
+    # factor and spikes.  The first block shares that factor but has no left
+    # spike, and the last has no right spike (and is padded when lb does not
+    # divide n): three blocks are stored whatever P is.
+    if kind == 5:
+        B = W.hyperdiffusion_bands(n, 0.5)
+    else:
+        B = W.diffusion_bands(n, 0.5)
+    rhs = np.random.default_rng(7).uniform(-1, 1, (n, 4))
+    ref = oracle.solve(kind, B, rhs)
+    plan = {p[0]: p for p in run(exe, tmp_path, kind, B, rhs) if p[0]}
+    assert lb in plan
+    _, P, got_d, _, x = plan[lb]
+    assert P > 3 and got_d == 3, (P, got_d)
+    assert colrel(x, ref) <= 1e-13

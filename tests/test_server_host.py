@@ -21,8 +21,8 @@ def exe(tmp_path_factory):
     out = str(tmp_path_factory.mktemp("sched") / "scenarios")
     cmd = ["g++", "-std=c++17", "-g", "-O1", "-fsanitize=address,undefined", "-fno-omit-frame-pointer",
            "-pthread", "-D__HIP_PLATFORM_AMD__", "-I/opt/rocm/include", "-I", os.path.join(ROOT, "include"),
-           "-I", CSRC, os.path.join(CSRC, "server.cpp"), os.path.join(HERE, "host_sched", "mock_device.cpp"),
-           os.path.join(HERE, "host_sched", "scenarios.cpp"), "-o", out]
+           "-I", CSRC, os.path.join(CSRC, "server.cpp"), os.path.join(HERE, "host", "mock_device.cpp"),
+           os.path.join(HERE, "host", "scenarios.cpp"), "-o", out]
     subprocess.run(cmd, check=True)
     return out
 
