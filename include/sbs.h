@@ -182,6 +182,22 @@ sbs_status sbs_solve_batch_refined(sbs_handle h, const float *b, double *x,
 size_t sbs_refined_workspace_bytes(sbs_handle h, int64_t m);
 
 /*
+ * Crank-Nicolson time steps in place (Sections 3.2 and 4.2): `steps` times
+ *   A c' = (2I - A) c,
+ * the scheme of both benchmark problems (the explicit half of diffusion,
+ * s C_{i-1} + (1 - 2s) C_i + s C_{i+1}, and of hyperdiffusion, is 2I - A for
+ * their matrices A), with the explicit half taken from the handle's own rows,
+ * periodic rows wrapping round.  The explicit half is fused into the solve:
+ * each step reads and writes every unknown as one solve does.
+ *  c      device, interleaved (n, m), dtype SBS_F64 or SBS_F32; overwritten.
+ *  steps  >= 0 (0 and m == 0 do nothing).
+ * Any kind of handle.  Asynchronous on `stream`.
+ * Errors: SBS_ERR_INVALID_ARG, SBS_ERR_DEVICE.
+ */
+sbs_status sbs_cn_step(sbs_handle h, void *c, int64_t m, int32_t dtype,
+                       int32_t steps, void *stream);
+
+/*
  * Out-of-place transpose: dst[c*rows + r] = src[r*cols + c].  Bit-exact
  * copy of 8-byte (SBS_F64) or 4-byte (SBS_F32) elements.  Converts a
  * row-major grid into the interleaved layout of its other direction.

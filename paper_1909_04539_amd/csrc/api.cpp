@@ -228,6 +228,17 @@ sbs_status sbs_solve_batch_refined(sbs_handle h, const float *b, double *x, int6
     return e == hipSuccess ? SBS_OK : SBS_ERR_DEVICE;
 }
 
+sbs_status sbs_cn_step(sbs_handle h, void *c, int64_t m, int32_t dtype, int32_t steps, void *stream) {
+    if (!h || m < 0 || steps < 0 || (dtype != SBS_F64 && dtype != SBS_F32)) return SBS_ERR_INVALID_ARG;
+    if (m == 0 || steps == 0) return SBS_OK;
+    if (!c || !aligned(c, dtype == SBS_F64 ? 8 : 4)) return SBS_ERR_INVALID_ARG;
+    if (m > (int64_t)0x7fffffff * kWave) return SBS_ERR_INVALID_ARG;
+    const int t = dtype == SBS_F64 ? 0 : 1;
+    for (int k = 0; k < steps; ++k)
+        if (launch_cn(h, t, c, m, static_cast<hipStream_t>(stream)) != hipSuccess) return SBS_ERR_DEVICE;
+    return SBS_OK;
+}
+
 sbs_status sbs_transpose(const void *src, void *dst, int64_t rows, int64_t cols, int32_t dtype, void *stream) {
     if (rows < 0 || cols < 0 || (dtype != SBS_F64 && dtype != SBS_F32)) return SBS_ERR_INVALID_ARG;
     if (rows == 0 || cols == 0) return SBS_OK;

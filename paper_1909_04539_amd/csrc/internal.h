@@ -126,6 +126,9 @@ hipError_t launch_refine_step(const sbs_lhs *h, int mode, const float *b, double
 hipError_t launch_transpose(const void *src, void *dst, int64_t rows, int64_t cols,
                             int elem_bytes, hipStream_t stream);
 
+// One Crank-Nicolson step in place: c <- A^{-1} (2I - A) c (tc: 0 f64, 1 f32).
+hipError_t launch_cn(const sbs_lhs *h, int tc, void *c, int64_t m, hipStream_t stream);
+
 // Which variant AUTO picks, and the LDS bytes per wave the chunked variant
 // needs (tc: 0 = f64, 1 = f32).
 int choose_variant(const sbs_lhs *h, int tc);

@@ -49,6 +49,8 @@ struct Rec<SBS_TRI, T> {
         s.y1 = y;
         return y;
     }
+    // the same step when a chunk is recomputed from its checkpoint
+    static __device__ __forceinline__ T refwd(const FC &c, T d, Fwd &s) { return fwd(c, d, s); }
     // x_i = y_i - chat_i x_{i+1}                          (Section 3.1, backward)
     static __device__ __forceinline__ T bwd(const BC &c, T y, Bwd &s) {
         const T x = fma(-c.chat, s.x1, y);
@@ -86,6 +88,7 @@ struct Rec<SBS_PENTA, T> {
         s.g1 = g;
         return g;
     }
+    static __device__ __forceinline__ T refwd(const FC &c, T v, Fwd &s) { return fwd(c, v, s); }
     // x_i = g_i - gamma_i x_{i+1} - delta_i x_{i+2}            (Section 4.1, R x = g)
     static __device__ __forceinline__ T bwd(const BC &c, T g, Bwd &s) {
         const T x = fma(-c.gamma, s.x1, fma(-c.delta, s.x2, g));
@@ -137,6 +140,12 @@ struct Rec<SBS_TRI_PERIODIC, T> {
         s.y1 = y;
         return y;
     }
+    // recomputing a chunk from its checkpoint: the dot product is complete
+    static __device__ __forceinline__ T refwd(const FC &c, T d, Fwd &s) {
+        const T y = fma(-c.a_s, s.y1, d * c.inv);
+        s.y1 = y;
+        return y;
+    }
     static __device__ __forceinline__ T bwd(const BC &c, T yh, Bwd &s) {
         const T y = fma(-c.chat, s.x1, yh);
         s.x1 = y;
@@ -182,12 +191,18 @@ __device__ __forceinline__ E bld(Rsrc r, uint32_t vo, uint32_t so) {
     else
         return __builtin_bit_cast(E, __builtin_amdgcn_raw_buffer_load_b32(r, vo, so, 0));
 }
-template <typename E>
+// Results are written with the non-temporal policy (they are not read again
+// by the kernel; on the 1024-row pentadiagonal batch the partitioned solve
+// went from 272 to 247 us).  Values that are read back soon, such as the
+// stream variant's forward results, use the default policy.
+constexpr int kStoreNT = 2;  // cache-policy bits of a buffer store: nt
+
+template <typename E, int POLICY = 0>
 __device__ __forceinline__ void bst(E v, Rsrc r, uint32_t vo, uint32_t so) {
     if constexpr (sizeof(E) == 8)
-        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0, 0, 0)), v), r, vo, so, 0);
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0, 0, 0)), v), r, vo, so, POLICY);
     else
-        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, vo, so, 0);
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, vo, so, POLICY);
 }
 
 // Wave-uniform copies of values that may arrive in vector registers (the
@@ -303,9 +318,9 @@ __device__ __forceinline__ void back_chunk(const typename Rec<KIND, T>::Row *__r
             const T x = R::bwd(c[g & 1][u], buf[t], bs);
             if (full || r0 + t < n) {
                 if constexpr (BIG)
-                    bst<Tout>(static_cast<Tout>(x), rsrc_at(p + t * rs), lo, 0);
+                    bst<Tout, kStoreNT>(static_cast<Tout>(x), rsrc_at(p + t * rs), lo, 0);
                 else
-                    bst<Tout>(static_cast<Tout>(x), r, lo, so);
+                    bst<Tout, kStoreNT>(static_cast<Tout>(x), r, lo, so);
             }
             so = step_off(so, (uint32_t)(-rs));
         }
@@ -315,7 +330,7 @@ __device__ __forceinline__ void back_chunk(const typename Rec<KIND, T>::Row *__r
 
 template <int KIND, typename T, int L>
 __device__ __forceinline__ void fwd_chunk(const typename Rec<KIND, T>::Row *__restrict__ fr,
-                                          T (&buf)[L], typename Rec<KIND, T>::Fwd &st) {
+                                          T (&buf)[L], typename Rec<KIND, T>::Fwd &st, bool again = false) {
     using R = Rec<KIND, T>;
     constexpr int G = L < kGroup ? L : kGroup, NG = L / G;
     typename R::FC c[2][G];
@@ -328,8 +343,37 @@ __device__ __forceinline__ void fwd_chunk(const typename Rec<KIND, T>::Row *__re
             for (int u = 0; u < G; ++u) c[(g + 1) & 1][u] = R::fc(fr, (g + 1) * G + u);
         }
 #pragma unroll
-        for (int u = 0; u < G; ++u) buf[g * G + u] = R::fwd(c[g & 1][u], buf[g * G + u], st);
+        for (int u = 0; u < G; ++u)
+            buf[g * G + u] = again ? R::refwd(c[g & 1][u], buf[g * G + u], st) : R::fwd(c[g & 1][u], buf[g * G + u], st);
         pin(buf[g * G + G - 1]);
+    }
+}
+
+// Backward sweep over one chunk held in registers, leaving the solution in
+// `buf` (for passes that still need the chunk's values).
+template <int KIND, typename T, int L>
+__device__ __forceinline__ void bwd_regs(const typename Rec<KIND, T>::Row *__restrict__ fr, T (&buf)[L],
+                                         typename Rec<KIND, T>::Bwd &bs) {
+    using R = Rec<KIND, T>;
+    constexpr int G = L < kGroup ? L : kGroup, NG = L / G;
+    typename R::BC c[2][G];
+#pragma unroll
+    for (int u = 0; u < G; ++u) c[(NG - 1) & 1][u] = R::bc(fr, L - 1 - u);
+#pragma unroll
+    for (int g = NG - 1; g >= 0; --g) {
+        if (g > 0) {
+#pragma unroll
+            for (int u = 0; u < G; ++u) c[(g - 1) & 1][u] = R::bc(fr, g * G - 1 - u);
+        }
+#pragma unroll
+        for (int u = 0; u < G; ++u) {
+            const int t = g * G + G - 1 - u;
+            buf[t] = R::bwd(c[g & 1][u], buf[t], bs);
+            // in row order: a solution value off the carried chain (periodic:
+            // y - s z) would otherwise be deferred with every z kept live
+            asm volatile("" : "+v"(buf[t]));
+        }
+        pin(bs.x1);
     }
 }
 
@@ -386,9 +430,82 @@ template <int KIND, typename T, int L, int MODE>
 __host__ __device__ constexpr size_t ck_bytes(int K) {
     return MODE == 2 ? ((size_t)K * Rec<KIND, T>::S * kWave * sizeof(T) + 15) / 16 * 16 : 0;
 }
-template <int KIND, typename T, int L, int MODE>
+template <int KIND, typename T, int L, int MODE, bool CN = false>
 __host__ __device__ constexpr size_t wave_lds_bytes(int K) {
-    return ck_bytes<KIND, T, L, MODE>(K) + 2 * L * sizeof(typename Rec<KIND, T>::Row);
+    return ck_bytes<KIND, T, L, MODE>(K) + 2 * L * sizeof(typename Rec<KIND, T>::Row) +
+           (CN ? 2 * L * sizeof(BandRow) : 0);
+}
+
+// ---------------------------------------------------------------------------
+// Crank-Nicolson steps (Sections 3.2 and 4.2).  Both schemes solve
+// A C' = (2I - A) C; since A^{-1} and 2I - A commute, C' = (2I - A) u with
+// u = A^{-1} C, so the explicit half is applied to the solution as the
+// backward sweep produces it, from the last row to the first, with the
+// matrix's own rows: x_q = 2 u_q - sum_k A[q][q+k-H] u_{q+k-H}.  Output row q
+// needs u down to row q - H, so a chunk's pass forms rows r0 + H .. r0 + L + H - 1
+// (the last H of them belong to the chunk above) and the first H rows of the
+// matrix are formed after the last chunk.  No extra HBM traffic.
+template <typename T>
+struct CnWrap {  // periodic tridiagonal: the corner terms, finished at the end
+    T xlast = T(0), ulast = T(0), cl = T(0);
+};
+
+template <int H, typename T, typename Tout, int L, bool BIG, bool PERIODIC>
+__device__ __forceinline__ void cn_pass(const BandRow *bhere, const BandRow *babove, const T (&u)[L], T (&up)[2 * H],
+                                        char *base, uint32_t lo, int r0, int n, int64_t rs, CnWrap<T> &wrap) {
+    char *p = base + r0 * rs;
+    const Rsrc r = rsrc_at(p);
+    uint32_t so = (uint32_t)(H * rs);
+#pragma unroll
+    for (int t = 0; t < L; ++t) {
+        const int lq = H + t;  // output row r0 + lq
+        const BandRow &b = lq < L ? bhere[lq] : babove[lq - L];
+        auto uat = [&](int li) -> T { return li < L ? u[li] : up[li - L]; };
+        T ax = T(b.c[0]) * uat(t);
+#pragma unroll
+        for (int k = 1; k <= 2 * H; ++k) ax = fma(T(b.c[k]), uat(t + k), ax);
+        const T x = T(2) * uat(lq) - ax;
+        const int q = r0 + lq;
+        if (PERIODIC && q == n - 1) {  // its wrap term needs u_0: finished at the end
+            wrap.xlast = x;
+            wrap.cl = T(b.c[2]);
+        } else if (q < n) {
+            if constexpr (BIG)
+                bst<Tout, kStoreNT>(static_cast<Tout>(x), rsrc_at(p + lq * rs), lo, 0);
+            else
+                bst<Tout, kStoreNT>(static_cast<Tout>(x), r, lo, so);
+        }
+        so = step_off(so, (uint32_t)rs);
+        if (t % kGroup == kGroup - 1) pin(ax);
+    }
+    if (PERIODIC && r0 + L >= n && r0 < n) {
+        // u_{n-1} (the wrap term of row 0) lies in this, the top, chunk
+#pragma unroll
+        for (int t = 0; t < L; ++t)
+            if (r0 + t == n - 1) wrap.ulast = u[t];
+    }
+#pragma unroll
+    for (int i = 0; i < 2 * H; ++i) up[i] = u[i];
+}
+
+// Rows 0 .. H-1 once the whole column is solved (`up` holds u_0 .. u_{2H-1},
+// `b0` the band rows of the first chunk); for the periodic matrix also the
+// corner terms of rows 0 and n-1.
+template <int H, typename T, typename Tout, bool PERIODIC>
+__device__ __forceinline__ void cn_finish(const BandRow *b0, const T (&up)[2 * H], char *base, uint32_t lo, int n,
+                                          int64_t rs, const CnWrap<T> &wrap) {
+#pragma unroll
+    for (int q = 0; q < H; ++q) {
+        if (q >= n) break;
+        const BandRow &b = b0[q];
+        auto uat = [&](int i) -> T { return i < 0 ? (PERIODIC ? wrap.ulast : T(0)) : up[i]; };
+        T ax = T(b.c[0]) * uat(q - H);
+#pragma unroll
+        for (int k = 1; k <= 2 * H; ++k) ax = fma(T(b.c[k]), uat(q + k - H), ax);
+        const T x = T(2) * up[q] - ax;
+        st<Tout>(base + q * rs, lo, static_cast<Tout>(x));
+    }
+    if (PERIODIC) st<Tout>(base + (int64_t)(n - 1) * rs, lo, static_cast<Tout>(fma(-wrap.cl, up[0], wrap.xlast)));
 }
 
 // ---------------------------------------------------------------------------
@@ -412,13 +529,20 @@ __host__ __device__ constexpr size_t wave_lds_bytes(int K) {
 // loads outstanding, close to the hardware limit of 63 per wave.
 // The body works on the wave's systems j0 .. j0+63 of an (n, m) array; `lds`
 // is the wave's private LDS area of wave_lds_bytes(K) bytes.
-template <int KIND, typename T, typename Tin, typename Tout, int L, int MODE, bool BIG = false>
+//
+// CN: a Crank-Nicolson step instead of a solve (in == out): the backward
+// sweep leaves each chunk's solution in registers and cn_pass forms the
+// output rows from it with the band rows (`bands`), staged like the factor.
+template <int KIND, typename T, typename Tin, typename Tout, int L, int MODE, bool BIG = false, bool CN = false>
 __device__ __forceinline__ void sweep_wave(const typename Rec<KIND, T>::Row *__restrict__ fac, int n,
                                            const Tin *in, Tout *out, int64_t m, int64_t j0,
-                                           unsigned char *lds) {
+                                           unsigned char *lds, const BandRow *__restrict__ bands = nullptr) {
     using R = Rec<KIND, T>;
     using Row = typename R::Row;
     constexpr int CB = L * (int)sizeof(Row);
+    constexpr int H = KIND == SBS_PENTA ? 2 : 1;
+    constexpr bool PER = KIND == SBS_TRI_PERIODIC;
+    constexpr int CBB = L * (int)sizeof(BandRow);
     const int lane = threadIdx.x;
     in = uni(in);
     out = uni(out);
@@ -435,6 +559,13 @@ __device__ __forceinline__ void sweep_wave(const typename Rec<KIND, T>::Row *__r
     unsigned char *fb = lds + ck_bytes<KIND, T, L, MODE>(K);
     auto frow = [&](int k) { return reinterpret_cast<const Row *>(fb + (k & 1) * CB); };
     FacRegs<CB> fv;
+    // CN only: band rows of the chunks, double-buffered after the factor's
+    unsigned char *bb = fb + 2 * CB;
+    auto brow = [&](int k) { return reinterpret_cast<const BandRow *>(bb + (k & 1) * CBB); };
+    FacRegs<CBB> bv;
+    T up[2 * H] = {};
+    CnWrap<T> wrap;
+    if constexpr (CN) bands = uni(bands);
 
     T cur[L];
     typename R::Fwd st;
@@ -443,10 +574,18 @@ __device__ __forceinline__ void sweep_wave(const typename Rec<KIND, T>::Row *__r
     fv.stage(fb, lane);
 
     if constexpr (MODE == MODE_RESIDENT) {
+        if constexpr (CN) bv.load(bands, lane);
         fwd_chunk<KIND, T, L>(frow(0), cur, st);
         typename R::Bwd bs;
         R::link(st, bs);
-        back_chunk<KIND, T, Tout, L, BIG>(frow(0), cur, bs, bout, lout, 0, n, rso);
+        if constexpr (CN) {
+            bv.stage(bb, lane);
+            bwd_regs<KIND, T, L>(frow(0), cur, bs);
+            cn_pass<H, T, Tout, L, BIG, PER>(brow(0), brow(0), cur, up, bout, lout, 0, n, rso, wrap);
+            cn_finish<H, T, Tout, PER>(brow(0), up, bout, lout, n, rso, wrap);
+        } else {
+            back_chunk<KIND, T, Tout, L, BIG>(frow(0), cur, bs, bout, lout, 0, n, rso);
+        }
         return;
     } else {
         T nxt[L];
@@ -469,20 +608,33 @@ __device__ __forceinline__ void sweep_wave(const typename Rec<KIND, T>::Row *__r
         // buffer (K-1)&1 its factor rows.
         typename R::Bwd bs;
         R::link(st, bs);
+        if constexpr (CN) {
+            bv.load(bands + (K - 1) * L, lane);
+            bv.stage(bb + ((K - 1) & 1) * CBB, lane);
+        }
         if (K >= 2) {
             fv.load(fac + (K - 2) * L, lane);
+            if constexpr (CN) bv.load(bands + (K - 2) * L, lane);
             if constexpr (MODE == MODE_CHUNKED)
                 load_rows<T, Tin, L, BIG>(nxt, bin, lin, (K - 2) * L, n, rsi);
             else
                 load_rows<T, Tout, L, BIG>(nxt, bout, lout, (K - 2) * L, n, rso);
         }
-        back_chunk<KIND, T, Tout, L, BIG>(frow(K - 1), cur, bs, bout, lout, (K - 1) * L, n, rso);
+        if constexpr (CN) {
+            bwd_regs<KIND, T, L>(frow(K - 1), cur, bs);
+            // nothing lies above the top chunk: its rows past n are not stored
+            cn_pass<H, T, Tout, L, BIG, PER>(brow(K - 1), brow(K - 1), cur, up, bout, lout, (K - 1) * L, n, rso, wrap);
+        } else {
+            back_chunk<KIND, T, Tout, L, BIG>(frow(K - 1), cur, bs, bout, lout, (K - 1) * L, n, rso);
+        }
         for (int k = K - 2; k >= 0; --k) {
             fv.stage(fb + (k & 1) * CB, lane);
+            if constexpr (CN) bv.stage(bb + (k & 1) * CBB, lane);  // chunk k+2's rows are no longer needed
 #pragma unroll
             for (int t = 0; t < L; ++t) cur[t] = nxt[t];
             if (k >= 1) {
                 fv.load(fac + (k - 1) * L, lane);
+                if constexpr (CN) bv.load(bands + (k - 1) * L, lane);
                 if constexpr (MODE == MODE_CHUNKED)
                     load_rows<T, Tin, L, BIG>(nxt, bin, lin, (k - 1) * L, n, rsi);
                 else
@@ -490,11 +642,24 @@ __device__ __forceinline__ void sweep_wave(const typename Rec<KIND, T>::Row *__r
             }
             if constexpr (MODE == MODE_CHUNKED) {
                 R::get(st, ckp + k * (R::S * kWave));
-                fwd_chunk<KIND, T, L>(frow(k), cur, st);
+                fwd_chunk<KIND, T, L>(frow(k), cur, st, true);  // recompute from the checkpoint
             }
-            back_chunk<KIND, T, Tout, L, BIG>(frow(k), cur, bs, bout, lout, k * L, n, rso);
+            if constexpr (CN) {
+                bwd_regs<KIND, T, L>(frow(k), cur, bs);
+                cn_pass<H, T, Tout, L, BIG, PER>(brow(k), brow(k + 1), cur, up, bout, lout, k * L, n, rso, wrap);
+            } else {
+                back_chunk<KIND, T, Tout, L, BIG>(frow(k), cur, bs, bout, lout, k * L, n, rso);
+            }
         }
+        if constexpr (CN) cn_finish<H, T, Tout, PER>(brow(0), up, bout, lout, n, rso, wrap);
     }
+}
+
+template <int KIND, typename T, int L, int MODE, bool BIG>
+__global__ __launch_bounds__(kWave) void k_cn(const typename Rec<KIND, T>::Row *__restrict__ fac,
+                                              const BandRow *__restrict__ bands, int n, T *c, int64_t m) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    sweep_wave<KIND, T, T, T, L, MODE, BIG, true>(fac, n, c, c, m, (int64_t)blockIdx.x * kWave, smem, bands);
 }
 
 template <int KIND, typename T, typename Tin, typename Tout, int L, int MODE, bool BIG>
@@ -517,41 +682,6 @@ __global__ __launch_bounds__(kWave) void k_sweep(const typename Rec<KIND, T>::Ro
 // and once out.  The block factors, spikes and inverse (shared by every
 // system) are copied into LDS once per persistent workgroup.
 
-template <int KIND, typename T, int L>
-__device__ __forceinline__ void bwd_regs(const typename Rec<KIND, T>::Row *__restrict__ fr, T (&buf)[L],
-                                         typename Rec<KIND, T>::Bwd &bs) {
-    using R = Rec<KIND, T>;
-    constexpr int G = L < kGroup ? L : kGroup, NG = L / G;
-    typename R::BC c[2][G];
-#pragma unroll
-    for (int u = 0; u < G; ++u) c[(NG - 1) & 1][u] = R::bc(fr, L - 1 - u);
-#pragma unroll
-    for (int g = NG - 1; g >= 0; --g) {
-        if (g > 0) {
-#pragma unroll
-            for (int u = 0; u < G; ++u) c[(g - 1) & 1][u] = R::bc(fr, g * G - 1 - u);
-        }
-#pragma unroll
-        for (int u = 0; u < G; ++u) {
-            const int t = g * G + G - 1 - u;
-            buf[t] = R::bwd(c[g & 1][u], buf[t], bs);
-        }
-        pin(bs.x1);
-    }
-}
-
-template <typename T>
-__device__ __forceinline__ T ldot(const T *a, const T *b, int n) {
-    T s0 = T(0), s1 = T(0);
-    int k = 0;
-    for (; k + 1 < n; k += 2) {
-        s0 = fma(a[k], b[k], s0);
-        s1 = fma(a[k + 1], b[k + 1], s1);
-    }
-    if (k < n) s0 = fma(a[k], b[k], s0);
-    return s0 + s1;
-}
-
 // Interface step of the partitioned solve: publishes this block's interface
 // values and computes, from the stored inverse of the interface system, the
 // first H unknowns of block p+1 (xt) and the last H of block p-1 (xb); the
@@ -569,10 +699,26 @@ __device__ __forceinline__ void part_interface(const T (&x)[LB], T *red, const T
         for (int c = 0; c < H; ++c) red[2 * H * (p - 1) + H + c] = x[c];
     }
     __syncthreads();
+    // All 2H dot products in one pass over the system's interface values, so
+    // each is read from LDS once (the rows of the inverse are shared by the
+    // block's systems and broadcast).  Blocks at the ends use a row of the
+    // other side in place of the missing one and discard it.
+    const T *ra = p <= P - 2 ? rt : rb, *rz = p >= 1 ? rb : rt;
+    T at[H], az[H];
+#pragma unroll
+    for (int c = 0; c < H; ++c) at[c] = az[c] = T(0);
+    for (int k = 0; k < Nr; ++k) {
+        const T v = red[k];
+#pragma unroll
+        for (int c = 0; c < H; ++c) {
+            at[c] = fma(ra[c * Nr + k], v, at[c]);
+            az[c] = fma(rz[c * Nr + k], v, az[c]);
+        }
+    }
 #pragma unroll
     for (int c = 0; c < H; ++c) {
-        xt[c] = p <= P - 2 ? ldot(rt + c * Nr, red, Nr) : T(0);
-        xb[c] = p >= 1 ? ldot(rb + c * Nr, red, Nr) : T(0);
+        xt[c] = p <= P - 2 ? at[c] : T(0);
+        xb[c] = p >= 1 ? az[c] : T(0);
     }
     __syncthreads();  // red is rewritten next time
 }
@@ -646,7 +792,7 @@ __global__ __launch_bounds__(MAXT) void k_part(const unsigned char *__restrict__
 #pragma unroll
         for (int t = 0; t < LB; ++t) {
             const T v = part_correct<KIND, T>(x[t], sp + t * 2 * H, xt, xb);
-            if (r0 + t < n) dst[(int64_t)t * rs] = static_cast<Tout>(v);
+            if (r0 + t < n) __builtin_nontemporal_store(static_cast<Tout>(v), &dst[(int64_t)t * rs]);
         }
     }
 }
@@ -748,7 +894,7 @@ __global__ __launch_bounds__(MAXT) void k_part_refine(const unsigned char *__res
         double *dst = x64 + (int64_t)r0 * rs + j;
 #pragma unroll
         for (int t = 0; t < LB; ++t)
-            if (r0 + t < n) dst[(int64_t)t * rs] = x[t];
+            if (r0 + t < n) __builtin_nontemporal_store(x[t], &dst[(int64_t)t * rs]);
     }
 }
 
@@ -1021,6 +1167,45 @@ hipError_t dispatch_mode(const sbs_lhs *h, int mode, const void *fac, const void
     return go<KIND, T, Tin, Tout, 32, MODE_STREAM>(h, fac, in, out, m, s);
 }
 
+// Crank-Nicolson step launches: the sweep variants with the output pass.
+template <int KIND, typename T, int L, int MODE>
+hipError_t go_cn(const sbs_lhs *h, const void *fac, void *c, int64_t m, hipStream_t s) {
+    using R = Rec<KIND, T>;
+    const int64_t blocks = (m + kWave - 1) / kWave;
+    const size_t lds = wave_lds_bytes<KIND, T, L, MODE, true>((int)((h->n + L - 1) / L));
+    if (lds > kMaxLdsBytes) return hipErrorInvalidValue;
+    // the output pass stores up to two rows past the chunk
+    const int64_t span = (int64_t)(L + 2) * m * (int64_t)sizeof(T);
+    const auto *f = reinterpret_cast<const typename R::Row *>(fac);
+    auto *pc = reinterpret_cast<T *>(c);
+    if (span < (int64_t(1) << 31) - 4096)
+        hipLaunchKernelGGL((k_cn<KIND, T, L, MODE, false>), dim3((unsigned)blocks), dim3(kWave), lds, s, f, h->bands,
+                           (int)h->n, pc, m);
+    else
+        hipLaunchKernelGGL((k_cn<KIND, T, L, MODE, true>), dim3((unsigned)blocks), dim3(kWave), lds, s, f, h->bands,
+                           (int)h->n, pc, m);
+    return hipGetLastError();
+}
+
+template <int KIND, typename T>
+hipError_t cn_mode(const sbs_lhs *h, const void *fac, void *c, int64_t m, hipStream_t s) {
+    const int64_t n = h->n;
+    if (n <= 8) return go_cn<KIND, T, 8, MODE_RESIDENT>(h, fac, c, m, s);
+    if (n <= 16) return go_cn<KIND, T, 16, MODE_RESIDENT>(h, fac, c, m, s);
+    if (n <= 32) return go_cn<KIND, T, 32, MODE_RESIDENT>(h, fac, c, m, s);
+    if (n <= 64) return go_cn<KIND, T, 64, MODE_RESIDENT>(h, fac, c, m, s);
+    if (wave_lds_bytes<KIND, T, 32, MODE_CHUNKED, true>((int)((n + 31) / 32)) <= kMaxLdsBytes)
+        return go_cn<KIND, T, 32, MODE_CHUNKED>(h, fac, c, m, s);
+    return go_cn<KIND, T, 32, MODE_STREAM>(h, fac, c, m, s);
+}
+
+template <typename T>
+hipError_t cn_kind(const sbs_lhs *h, const void *fac, void *c, int64_t m, hipStream_t s) {
+    if (h->kind == SBS_TRI) return cn_mode<SBS_TRI, T>(h, fac, c, m, s);
+    if (h->kind == SBS_TRI_PERIODIC) return cn_mode<SBS_TRI_PERIODIC, T>(h, fac, c, m, s);
+    return cn_mode<SBS_PENTA, T>(h, fac, c, m, s);
+}
+
 template <typename T, typename Tin, typename Tout>
 hipError_t dispatch_kind(const sbs_lhs *h, int mode, const void *fac, const void *in, void *out,
                          int64_t m, hipStream_t s) {
@@ -1041,6 +1226,11 @@ size_t chunked_lds_bytes(const sbs_lhs *h, int tc) {
                        : wave_lds_bytes<SBS_TRI_PERIODIC, float, 32, MODE_CHUNKED>(K);
     return tc == 0 ? wave_lds_bytes<SBS_PENTA, double, 32, MODE_CHUNKED>(K)
                    : wave_lds_bytes<SBS_PENTA, float, 32, MODE_CHUNKED>(K);
+}
+
+hipError_t launch_cn(const sbs_lhs *h, int tc, void *c, int64_t m, hipStream_t stream) {
+    if (m <= 0) return hipSuccess;
+    return tc == 0 ? cn_kind<double>(h, h->fac64, c, m, stream) : cn_kind<float>(h, h->fac32, c, m, stream);
 }
 
 int choose_variant(const sbs_lhs *h, int tc) {
@@ -1207,19 +1397,22 @@ hipError_t launch_partition_refine(const sbs_lhs *h, const PartChoice &c, const 
 }
 
 // Block length and systems per workgroup S for the partitioned solve.  The
-// score is the number of waves that run at once over the whole batch; ties go
-// to more workgroups per CU (each has its own barrier, so one can load while
-// another computes), then to longer blocks (fewer interfaces), then to larger
-// S.  S >= 16 keeps every row access a whole 128-byte line (FP64); narrower
-// workgroups (down to 4 systems) are only tried when the batch is too small
-// to give every CU a group.
+// score is the number of waves that run at once over the whole batch, counted
+// up to 8 per CU (enough to keep HBM busy: more buys nothing once the batch
+// fills the chip, and a 1M-system tridiagonal batch ran 13% slower on the
+// 32-row blocks that allow 16); ties go to longer blocks (fewer interfaces),
+// then to larger S: each row access of a
+// block covers S consecutive systems, and wider runs stream better (measured
+// on the 1024-row pentadiagonal batch: S = 32 274 us, S = 16 299 us, both with
+// 8 waves per CU).  S >= 16 keeps every row access a whole 128-byte line
+// (FP64); narrower workgroups (down to 4 systems) are only tried when the
+// batch is too small to give every CU a group.
 bool choose_partition(const sbs_lhs *h, int tc, int64_t m, PartChoice *out) {
     const size_t elem = tc == 0 ? 8 : 4;
     int cus = 256;
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, h->device);
     PartChoice best;
     int64_t best_waves = -1;
-    int best_wgs = 0;
     for (int q = 2; q >= 0; --q) {  // largest block first: fewest interfaces
         const PartPlan &pp = h->part[q];
         if (!pp.ok || m < 1) continue;
@@ -1234,10 +1427,10 @@ bool choose_partition(const sbs_lhs *h, int tc, int64_t m, PartChoice *out) {
             const int wgs = part_wgs_per_cu(h->kind, tc, pp.lb, threads, lds);
             if (wgs < 1) continue;
             const int64_t groups = (m + S - 1) / S;
-            const int64_t waves = std::min<int64_t>(groups, (int64_t)cus * wgs) * ((threads + kWave - 1) / kWave);
-            if (waves > best_waves || (waves == best_waves && wgs > best_wgs)) {
+            const int64_t waves = std::min<int64_t>(
+                std::min<int64_t>(groups, (int64_t)cus * wgs) * ((threads + kWave - 1) / kWave), (int64_t)cus * 8);
+            if (waves > best_waves) {
                 best_waves = waves;
-                best_wgs = wgs;
                 best.plan = q;
                 best.S = S;
                 best.threads = threads;

@@ -74,6 +74,7 @@ def lib() -> ctypes.CDLL:
         "sbs_auto_variant": ([vp, i64, i32, P(i32)], i32),
         "sbs_solve_batch_refined": ([vp, vp, vp, i64, i32, vp, sz, vp], i32),
         "sbs_refined_workspace_bytes": ([vp, i64], sz),
+        "sbs_cn_step": ([vp, vp, i64, i32, i32, vp], i32),
         "sbs_transpose": ([vp, vp, i64, i64, i32, vp], i32),
         "sbs_adi_step": ([vp, vp, vp, vp, i64, i64, vp], i32),
         "sbs_release": ([vp], i32),
@@ -210,6 +211,14 @@ def sbs_solve_batch_refined(h: int, b: torch.Tensor, x: torch.Tensor | None = No
     return x
 
 
+def sbs_cn_step(h: int, c: torch.Tensor, steps: int = 1, stream=None) -> torch.Tensor:
+    """Crank-Nicolson steps in place: c <- A^{-1} (2I - A) c, `steps` times."""
+    _, n, _ = sbs_handle_info(h)
+    p = _rhs(c, n)
+    _check(lib().sbs_cn_step(h, p, c.shape[1], _dtype_code(c), steps, _stream(stream)), "sbs_cn_step")
+    return c
+
+
 def sbs_transpose(src: torch.Tensor, dst: torch.Tensor | None = None, stream=None) -> torch.Tensor:
     if src.dim() != 2 or not (src.is_cuda and src.is_contiguous()):
         raise ValueError("src must be a contiguous 2-D CUDA tensor")
@@ -243,6 +252,9 @@ class SharedLhs:
 
     def solve(self, rhs: torch.Tensor, variant: int = VARIANT_AUTO, stream=None) -> torch.Tensor:
         return sbs_solve_batch_variant(self.handle, rhs, variant, stream)
+
+    def cn_step(self, c: torch.Tensor, steps: int = 1, stream=None) -> torch.Tensor:
+        return sbs_cn_step(self.handle, c, steps, stream)
 
     def solve_refined(self, b: torch.Tensor, sweeps: int = 2, **kw) -> torch.Tensor:
         return sbs_solve_batch_refined(self.handle, b, sweeps=sweeps, **kw)

@@ -1,0 +1,88 @@
+"""GPU parity of Crank-Nicolson steps (Sections 3.2 and 4.2): the explicit
+half (2I - A) C fused into the solve, against the oracle's steps (which form
+the explicit half first and then solve), FP64 within 1e-12 per column, for
+tridiagonal, pentadiagonal and periodic tridiagonal handles at sizes that run
+the resident, chunked and stream sweeps."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1909_04539_amd import sbs, workloads as W
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def colrel(x, ref):
+    num = np.max(np.abs(x - ref), axis=0)
+    den = np.maximum(np.max(np.abs(ref), axis=0), np.finfo(float).tiny)
+    return float(np.max(num / den))
+
+
+def bands(kind, n, seed):
+    rng = np.random.default_rng(seed)
+    nb = 5 if kind == 5 else 3
+    B = rng.uniform(-1, 1, (nb, n))
+    B[nb // 2] = np.sum(np.abs(np.delete(B, nb // 2, axis=0)), axis=0) + rng.uniform(1, 2, n)
+    return B if kind == 13 else W.zero_outside(B)
+
+
+def gpu_cn(kind, B, C, steps, dtype=torch.float64):
+    with sbs.SharedLhs(kind, B) as lhs:
+        x = torch.from_numpy(np.ascontiguousarray(C)).to(DEV, dtype)
+        lhs.cn_step(x, steps)
+        torch.cuda.synchronize()
+        return x.cpu().numpy().astype(np.float64)
+
+
+SIZES = [(3, 5), (5, 64), (8, 1), (16, 65), (33, 100), (64, 128), (65, 300), (100, 64), (1000, 257), (3000, 130),
+         (20000, 70)]
+
+
+@pytest.mark.parametrize("kind", [3, 5, 13])
+@pytest.mark.parametrize("n,m", SIZES)
+@pytest.mark.parametrize("steps", [1, 3])
+def test_cn_steps_match_oracle(kind, n, m, steps):
+    if kind == 13 and n < 3:
+        pytest.skip("periodic needs n >= 3")
+    print(f"case kind={kind} n={n} m={m} steps={steps}", flush=True)
+    B = bands(kind, n, n + 7 * kind)
+    C = np.random.default_rng(n * m + steps).uniform(-1, 1, (n, m))
+    got = gpu_cn(kind, B, C, steps)
+    assert colrel(got, oracle.cn_steps(kind, B, C, steps)) <= 1e-12
+
+
+def test_paper_benchmark_schemes_ten_steps():
+    # periodic diffusion (Section 3.2) and hyperdiffusion (Section 4.2) bands
+    n, m = 512, 1024
+    s = 0.3
+    Bd = np.stack([np.full(n, -s), np.full(n, 1 + 2 * s), np.full(n, -s)])
+    Bh = W.hyperdiffusion_bands(n, s)
+    C = np.random.default_rng(3).uniform(-1, 1, (n, m))
+    assert colrel(gpu_cn(13, Bd, C, 10), oracle.cn_steps(13, Bd, C, 10)) <= 1e-12
+    assert colrel(gpu_cn(5, Bh, C, 10), oracle.cn_steps(5, Bh, C, 10)) <= 1e-12
+
+
+@pytest.mark.parametrize("kind", [3, 5, 13])
+def test_cn_fp32(kind):
+    n, m = 700, 300
+    B = bands(kind, n, 1)
+    C = np.random.default_rng(2).uniform(-1, 1, (n, m)).astype(np.float32)
+    got = gpu_cn(kind, B, C, 2, torch.float32)
+    assert colrel(got, oracle.cn_steps(kind, B, C.astype(np.float64), 2)) <= 1e-5
+
+
+def test_cn_noop_and_errors():
+    B = bands(3, 50, 4)
+    with sbs.SharedLhs(3, B) as lhs:
+        x = torch.rand((50, 20), dtype=torch.float64, device=DEV)
+        y = x.clone()
+        lhs.cn_step(x, 0)
+        torch.cuda.synchronize()
+        assert torch.equal(x, y)
+        L = sbs.lib()
+        assert L.sbs_cn_step(lhs.handle, x.data_ptr(), 20, 0, -1, None) == 1
+        assert L.sbs_cn_step(lhs.handle, x.data_ptr(), 20, 7, 1, None) == 1
+        assert L.sbs_cn_step(lhs.handle, None, 20, 0, 1, None) == 1
+        assert L.sbs_cn_step(lhs.handle, x.data_ptr(), 0, 0, 1, None) == 0
