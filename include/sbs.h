@@ -122,6 +122,19 @@ sbs_status sbs_factor_shared_lhs(int32_t kind, int64_t n, const double *bands,
                                  sbs_handle *out, int64_t *bad_row);
 
 /*
+ * As sbs_factor_shared_lhs for a matrix with constant bands (the uniform
+ * variant of Section 4.2): coeffs holds one value per band, in band order
+ * (tri a, b, c; penta a, b, c, d, e).  The ends are truncated as for banded
+ * kinds; SBS_TRI_PERIODIC wraps round.  The result is the handle the general
+ * call gives for the expanded bands (same solutions bit for bit); with
+ * constant bands every interior block of the partitioned variant is the
+ * same, so its plan keeps three blocks whatever n is.
+ * Errors: as sbs_factor_shared_lhs (NULL coeffs is SBS_ERR_INVALID_ARG).
+ */
+sbs_status sbs_factor_uniform(int32_t kind, int64_t n, const double *coeffs,
+                              sbs_handle *out, int64_t *bad_row);
+
+/*
  * Solve m systems in place: forward sweep then backward sweep per system
  * (Section 3.1 for SBS_TRI, Section 4.1 for SBS_PENTA), one GPU lane per
  * system, the shared factor read by all lanes (Section 2).

@@ -144,6 +144,23 @@ sbs_status sbs_factor_shared_lhs(int32_t kind, int64_t n, const double *bands, s
     return SBS_OK;
 }
 
+sbs_status sbs_factor_uniform(int32_t kind, int64_t n, const double *coeffs, sbs_handle *out, int64_t *bad_row) {
+    if (bad_row) *bad_row = -1;
+    if (out) *out = nullptr;
+    if (!out || !coeffs || n < 1 || n > (int64_t(1) << 40)) return SBS_ERR_INVALID_ARG;
+    if (kind != SBS_TRI && kind != SBS_PENTA && kind != SBS_TRI_PERIODIC) return SBS_ERR_INVALID_ARG;
+    const int nb = nbands(kind);
+    std::vector<double> bands;
+    try {
+        bands.resize((size_t)nb * n);
+    } catch (const std::bad_alloc &) {
+        return SBS_ERR_NO_MEMORY;
+    }
+    for (int k = 0; k < nb; ++k)
+        for (int64_t i = 0; i < n; ++i) bands[(size_t)k * n + i] = coeffs[k];
+    return sbs_factor_shared_lhs(kind, n, bands.data(), out, bad_row);
+}
+
 sbs_status sbs_release(sbs_handle h) {
     if (!h) return SBS_OK;
     sbs_status st = SBS_OK;

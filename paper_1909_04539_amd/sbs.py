@@ -69,6 +69,7 @@ def lib() -> ctypes.CDLL:
         "sbs_status_str": ([i32], ctypes.c_char_p),
         "sbs_version": ([], ctypes.c_char_p),
         "sbs_factor_shared_lhs": ([i32, i64, vp, P(vp), P(i64)], i32),
+        "sbs_factor_uniform": ([i32, i64, vp, P(vp), P(i64)], i32),
         "sbs_solve_batch": ([vp, vp, i64, i32, vp], i32),
         "sbs_solve_batch_variant": ([vp, vp, i64, i32, i32, vp], i32),
         "sbs_auto_variant": ([vp, i64, i32, P(i32)], i32),
@@ -150,6 +151,19 @@ def sbs_factor_shared_lhs(kind: int, bands) -> int:
     bad = ctypes.c_int64(-1)
     st = lib().sbs_factor_shared_lhs(kind, B.shape[1], B.ctypes.data, ctypes.byref(h), ctypes.byref(bad))
     _check(st, "sbs_factor_shared_lhs", bad.value)
+    return h.value
+
+
+def sbs_factor_uniform(kind: int, n: int, coeffs) -> int:
+    """Factor a matrix with constant bands (one coefficient per band)."""
+    c = np.ascontiguousarray(np.asarray(coeffs, dtype=np.float64))
+    nb = 3 if kind == SBS_TRI_PERIODIC else kind
+    if c.shape != (nb,):
+        raise ValueError(f"coeffs must have {nb} entries")
+    h = ctypes.c_void_p()
+    bad = ctypes.c_int64(-1)
+    _check(lib().sbs_factor_uniform(kind, n, c.ctypes.data, ctypes.byref(h), ctypes.byref(bad)),
+           "sbs_factor_uniform", bad.value)
     return h.value
 
 

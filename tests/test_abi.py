@@ -129,3 +129,21 @@ def test_periodic_factor_errors_without_device(L):
     for n in (3, 4, 5, 8, 64):
         st, h, bad = _factor(L, 13, n, ring(n, 2.0))
         assert st == 2 and h is None and bad == n
+
+
+def test_uniform_factor_errors_without_device(L):
+    def fac(kind, n, coeffs):
+        h = ctypes.c_void_p(5)
+        bad = ctypes.c_int64(7)
+        c = None if coeffs is None else np.ascontiguousarray(coeffs, dtype=np.float64)
+        st = L.sbs_factor_uniform(kind, n, None if c is None else c.ctypes.data, ctypes.byref(h), ctypes.byref(bad))
+        return st, h.value, bad.value
+    assert fac(3, 10, None)[0] == 1
+    assert fac(4, 10, [1.0, 2.0, 3.0, 4.0])[0] == 1
+    assert fac(3, 0, [1.0, 2.0, 3.0])[0] == 1
+    assert fac(13, 2, [-1.0, 4.0, -1.0])[0] == 1
+    assert fac(3, 10, [1.0, np.inf, 1.0])[0:3:2] == (3, 0)
+    st, h, bad = fac(3, 10, [1.0, 0.0, 1.0])             # b_0 = 0
+    assert st == 2 and h is None and bad == 0
+    st, h, bad = fac(13, 16, [-1.0, 2.0, -1.0])          # periodic Laplacian: singular
+    assert st == 2 and h is None and bad == 16

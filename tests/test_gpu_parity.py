@@ -293,3 +293,45 @@ def test_adi_step_matches_oracle(ny, nx):
     hx.close()
     assert colrel(got, ref) <= TOL64          # per column
     assert colrel(got.T, ref.T) <= TOL64      # per row
+
+
+@pytest.mark.parametrize("kind,coeffs", [(3, [-0.5, 2.0, -0.5]), (5, [0.5, -2.0, 4.0, -2.0, 0.5]),
+                                         (13, [-0.3, 1.6, -0.3])])
+@pytest.mark.parametrize("n", [5, 64, 1024, 3000])
+def test_uniform_factor_equals_general_factor(kind, coeffs, n):
+    # the uniform entry point is the general one on the expanded bands
+    B = np.stack([np.full(n, c) for c in coeffs])
+    if kind != 13:
+        B = W.zero_outside(B)
+    rhs = np.random.default_rng(n).uniform(-1, 1, (n, 130))
+    hu = sbs.sbs_factor_uniform(kind, n, coeffs)
+    try:
+        outs = []
+        for h in (hu, None):
+            with (sbs.SharedLhs(kind, B) if h is None else _Borrowed(h)) as lhs:
+                x = torch.from_numpy(rhs).to(DEV)
+                lhs.solve(x)
+                torch.cuda.synchronize()
+                outs.append(x.cpu().numpy())
+                assert sbs.sbs_handle_info(lhs.handle)[1] == n
+        assert np.array_equal(outs[0], outs[1])
+        ref_kind = oracle.TRI_PERIODIC if kind == 13 else kind
+        assert colrel(outs[0], oracle.solve(ref_kind, B, rhs)) <= TOL64
+    finally:
+        sbs.sbs_release(hu)
+
+
+class _Borrowed:
+    """A handle used like SharedLhs without being released on exit."""
+
+    def __init__(self, h):
+        self.handle = h
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        return False
+
+    def solve(self, rhs, variant=sbs.VARIANT_AUTO):
+        return sbs.sbs_solve_batch_variant(self.handle, rhs, variant)
