@@ -146,6 +146,35 @@ def bench_penta_general(args, torch, sbs, W):
             "unknowns_per_s": u / dev, "us_per_solve": dev * 1e6, "hbm_frac_16B": round(16 * u / dev / 1e9 / HBM_PEAK_GBS, 4)}
 
 
+def bench_periodic_and_cn(args, torch, sbs, W):
+    """Periodic tridiagonal solves (Section 3.3) and Crank-Nicolson steps of
+    the paper's two benchmark schemes (Sections 3.2, 4.2) at the headline's
+    size: diffusion on a periodic grid, a = c = -s, b = 1 + 2s, and
+    hyperdiffusion with truncated ends, s = 0.5.  One step is one solve or
+    one Crank-Nicolson step (explicit half fused) of all m systems."""
+    n, m = 1024, 65536
+    s = 0.5
+    g = torch.Generator(device="cuda:0")
+    g.manual_seed(13)
+    c = torch.rand((n, m), dtype=torch.float64, device="cuda:0", generator=g)
+    ring = np.stack([np.full(n, -s), np.full(n, 1 + 2 * s), np.full(n, -s)])
+    out = {}
+    hp = sbs.SharedLhs(sbs.SBS_TRI_PERIODIC, ring)
+    hh = sbs.SharedLhs(5, W.hyperdiffusion_bands(n, s))
+    u = n * m
+    for name, fn in (("tri_periodic_solve", lambda: hp.solve(c)),
+                     ("cn_step_periodic_diffusion", lambda: hp.cn_step(c)),
+                     ("cn_step_hyperdiffusion", lambda: hh.cn_step(c))):
+        wall, dev = timed_steps(fn, 20, 3, torch)
+        out[name] = {"us_per_step": round(dev * 1e6, 1), "unknowns_per_s": u / dev,
+                     "hbm_frac_16B": round(16 * u / dev / 1e9 / HBM_PEAK_GBS, 4)}
+    out["workload"] = "n1024_m65536_f64"
+    out["variant"] = {v: k for k, v in VARIANTS.items()}[sbs.sbs_auto_variant(hp.handle, m)]
+    hp.close()
+    hh.close()
+    return out
+
+
 def bench_tri256(args, torch, sbs, W):
     wl = W.config0()
     rhs = torch.from_numpy(wl.rhs).to("cuda:0")
@@ -371,7 +400,8 @@ def main():
         print(json.dumps(bench_serving(args, torch, sbs, W)), flush=True)
         return
     if args.only != "headline":
-        for name, fn in (("penta_general", bench_penta_general), ("tri_n256_m1024", bench_tri256),
+        for name, fn in (("penta_general", bench_penta_general), ("periodic_and_cn", bench_periodic_and_cn),
+                         ("tri_n256_m1024", bench_tri256),
                          ("adi_2048", bench_adi), ("refined_n512_m1M", bench_refined), ("serving", bench_serving)):
             log(f"workload {name}")
             try:

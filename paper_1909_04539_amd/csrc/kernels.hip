@@ -1399,7 +1399,7 @@ hipError_t launch_partition_refine(const sbs_lhs *h, const PartChoice &c, const 
 // Block length and systems per workgroup S for the partitioned solve.  The
 // score is the number of waves that run at once over the whole batch, counted
 // up to 8 per CU (enough to keep HBM busy: more buys nothing once the batch
-// fills the chip, and a 1M-system tridiagonal batch ran 13% slower on the
+// fills the chip, and a 1M-system tridiagonal batch ran 16% slower on the
 // 32-row blocks that allow 16); ties go to longer blocks (fewer interfaces),
 // then to larger S: each row access of a
 // block covers S consecutive systems, and wider runs stream better (measured
