@@ -130,8 +130,7 @@ sbs_status sbs_factor_shared_lhs(int32_t kind, int64_t n, const double *bands, s
             st = factor_periodic_rows(n, cf, r.data(), &bad) ? SBS_OK : SBS_ERR_ZERO_PIVOT;
             if (st == SBS_OK) st = upload<PeriodicRow<double>, PeriodicRow<float>>(h, r, bands);
         }
-        // The partitioned variant covers the banded kinds.
-        if (st == SBS_OK && kind != SBS_TRI_PERIODIC) st = build_partitions(h, bands);
+        if (st == SBS_OK) st = build_partitions(h, bands);
     } catch (const std::bad_alloc &) {
         st = SBS_ERR_NO_MEMORY;
     }
@@ -251,8 +250,13 @@ sbs_status sbs_cn_step(sbs_handle h, void *c, int64_t m, int32_t dtype, int32_t 
     if (!c || !aligned(c, dtype == SBS_F64 ? 8 : 4)) return SBS_ERR_INVALID_ARG;
     if (m > (int64_t)0x7fffffff * kWave) return SBS_ERR_INVALID_ARG;
     const int t = dtype == SBS_F64 ? 0 : 1;
-    for (int k = 0; k < steps; ++k)
-        if (launch_cn(h, t, c, m, static_cast<hipStream_t>(stream)) != hipSuccess) return SBS_ERR_DEVICE;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    PartChoice pc;
+    const bool part = choose_partition(h, t, m, &pc, true);
+    for (int k = 0; k < steps; ++k) {
+        const hipError_t e = part ? launch_partition(h, pc, t, t, t, c, c, m, s, true) : launch_cn(h, t, c, m, s);
+        if (e != hipSuccess) return SBS_ERR_DEVICE;
+    }
     return SBS_OK;
 }
 

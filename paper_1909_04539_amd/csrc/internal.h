@@ -70,6 +70,7 @@ struct PartPlan {
     int lb = 0, P = 0, Nr = 0;
     int D = 0;  // distinct blocks stored (bit-identical blocks share one copy)
     bool ok = false;
+    bool periodic = false;  // blocks wrap round: P interface pairs, not P-1
     // Device arrays, each [fac | spk | rinv | map] contiguous and 16-byte aligned:
     //   fac: D*lb factor rows of the distinct blocks (TriRow/PentaRow)
     //   spk: D*lb rows of {V[0..h), W[0..h)}
@@ -143,9 +144,10 @@ struct PartChoice {
     size_t lds = 0;
     int wgs = 1;  // workgroups resident per CU at this size
 };
-bool choose_partition(const sbs_lhs *h, int tc, int64_t m, PartChoice *out);
+// cn: a Crank-Nicolson step c <- A^{-1} (2I - A) c instead of a solve (in == out).
+bool choose_partition(const sbs_lhs *h, int tc, int64_t m, PartChoice *out, bool cn = false);
 hipError_t launch_partition(const sbs_lhs *h, const PartChoice &c, int tc, int tin, int tout, const void *in,
-                            void *out, int64_t m, hipStream_t stream);
+                            void *out, int64_t m, hipStream_t stream, bool cn = false);
 sbs_status build_partitions(sbs_lhs *h, const double *bands);
 bool choose_partition_refine(const sbs_lhs *h, int64_t m, PartChoice *out);
 hipError_t launch_partition_refine(const sbs_lhs *h, const PartChoice &c, const float *b, double *x, int64_t m,

@@ -687,23 +687,27 @@ __global__ __launch_bounds__(kWave) void k_sweep(const typename Rec<KIND, T>::Ro
 // first H unknowns of block p+1 (xt) and the last H of block p-1 (xb); the
 // block's solution is then x = g - V xt - W xb.
 template <int KIND, typename T, int LB>
-__device__ __forceinline__ void part_interface(const T (&x)[LB], T *red, const T *rt, const T *rb, int p, int P,
-                                               int Nr, T (&xt)[KIND / 2], T (&xb)[KIND / 2]) {
+__device__ __forceinline__ void part_interface(const T (&x)[LB], T *red, const T *rt, const T *rb, int p, int pp,
+                                               bool has_next, bool has_prev, int Nr, T (&xt)[KIND / 2],
+                                               T (&xb)[KIND / 2]) {
+    // Pair q of the interface holds (bottom H of block q, top H of the next
+    // block); block p's bottom is in pair p, its top in pair pp (the previous
+    // block's pair: p - 1, or P - 1 for block 0 of a periodic matrix).
     constexpr int H = KIND / 2;
-    if (p <= P - 2) {
+    if (has_next) {
 #pragma unroll
         for (int c = 0; c < H; ++c) red[2 * H * p + c] = x[LB - H + c];
     }
-    if (p >= 1) {
+    if (has_prev) {
 #pragma unroll
-        for (int c = 0; c < H; ++c) red[2 * H * (p - 1) + H + c] = x[c];
+        for (int c = 0; c < H; ++c) red[2 * H * pp + H + c] = x[c];
     }
     __syncthreads();
     // All 2H dot products in one pass over the system's interface values, so
     // each is read from LDS once (the rows of the inverse are shared by the
     // block's systems and broadcast).  Blocks at the ends use a row of the
     // other side in place of the missing one and discard it.
-    const T *ra = p <= P - 2 ? rt : rb, *rz = p >= 1 ? rb : rt;
+    const T *ra = has_next ? rt : rb, *rz = has_prev ? rb : rt;
     T at[H], az[H];
 #pragma unroll
     for (int c = 0; c < H; ++c) at[c] = az[c] = T(0);
@@ -717,8 +721,8 @@ __device__ __forceinline__ void part_interface(const T (&x)[LB], T *red, const T
     }
 #pragma unroll
     for (int c = 0; c < H; ++c) {
-        xt[c] = p <= P - 2 ? at[c] : T(0);
-        xb[c] = p >= 1 ? az[c] : T(0);
+        xt[c] = has_next ? at[c] : T(0);
+        xb[c] = has_prev ? az[c] : T(0);
     }
     __syncthreads();  // red is rewritten next time
 }
@@ -744,13 +748,20 @@ __device__ __forceinline__ void stage_blob(unsigned char *lds, const unsigned ch
     for (int i = threadIdx.x; i < bytes / 16; i += blockDim.x) dst[i] = src[i];
 }
 
-template <int KIND, typename T, typename Tin, typename Tout, int LB, int MAXT>
+// CN: a Crank-Nicolson step (in == out) instead of a solve: after the
+// correction each lane holds its block of u = A^{-1} c, swaps its first and
+// last H values with the neighbouring blocks through LDS, and writes
+// 2 u - A u with the band rows (compact, NB = 2H + 1 per row, in LDS).
+// `periodic`: block 0 and block P-1 are neighbours (one more interface pair).
+template <int KIND, typename T, typename Tin, typename Tout, int LB, int MAXT, bool CN = false>
 __global__ __launch_bounds__(MAXT) void k_part(const unsigned char *__restrict__ blob, int fac_bytes, int spk_bytes,
-                                               int rinv_bytes, int n, int P, int Nr, int S, int ngroups,
-                                               const Tin *in, Tout *out, int64_t m) {
+                                               int rinv_bytes, int n, int P, int Nr, int S, int ngroups, int periodic,
+                                               const BandRow *__restrict__ bands, const Tin *in, Tout *out,
+                                               int64_t m) {
     using R = Rec<KIND, T>;
     using Row = typename R::Row;
     constexpr int H = KIND / 2;
+    constexpr int NB = 2 * H + 1;
     extern __shared__ __align__(16) unsigned char lds[];
     const int blob_bytes = fac_bytes + spk_bytes + rinv_bytes + map_bytes(P);
     stage_blob(lds, blob, blob_bytes);
@@ -760,6 +771,15 @@ __global__ __launch_bounds__(MAXT) void k_part(const unsigned char *__restrict__
     const int *lmap = reinterpret_cast<const int *>(lds + fac_bytes + spk_bytes + rinv_bytes);
     T *lred = reinterpret_cast<T *>(lds + blob_bytes);
     const int ldr = Nr + 1;  // odd stride: the systems' rows fall in different banks
+    const int npad = P * LB;
+    unsigned char *after_red = lds + blob_bytes + (S * ldr * (int)sizeof(T) + 15) / 16 * 16;
+    double *lband = reinterpret_cast<double *>(after_red);                                  // CN: [npad][NB]
+    T *lend = reinterpret_cast<T *>(after_red + (npad * NB * 8 + 15) / 16 * 16);            // CN: [S][P][2H]
+    if constexpr (CN) {
+        for (int i = threadIdx.x; i < npad; i += blockDim.x)
+#pragma unroll
+            for (int k = 0; k < NB; ++k) lband[i * NB + k] = i < n ? bands[i].c[k] : 0.0;
+    }
     __syncthreads();
 
     const int l = threadIdx.x, p = l / S, s = l - p * S;
@@ -768,8 +788,10 @@ __global__ __launch_bounds__(MAXT) void k_part(const unsigned char *__restrict__
     const Row *fr = lfac + q * LB;
     const T *sp = lspk + q * LB * 2 * H;
     T *red = lred + s * ldr;
-    const T *rt = lrinv + (2 * H * p + H) * Nr;        // rows of x_{p+1}[0:H]
-    const T *rb = lrinv + (2 * H * (p - 1)) * Nr;      // rows of x_{p-1}[lb-H:lb]
+    const bool has_next = periodic || p <= P - 2, has_prev = periodic || p >= 1;
+    const int pp = p == 0 ? P - 1 : p - 1, pn = p == P - 1 ? 0 : p + 1;
+    const T *rt = lrinv + (2 * H * p + H) * Nr;  // rows of the next block's first H unknowns
+    const T *rb = lrinv + (2 * H * pp) * Nr;     // rows of the previous block's last H
     const int64_t rs = m;
     for (int g = blockIdx.x; g < ngroups; g += gridDim.x) {
         const int64_t j = min((int64_t)g * S + s, m - 1);
@@ -787,12 +809,56 @@ __global__ __launch_bounds__(MAXT) void k_part(const unsigned char *__restrict__
         typename R::Bwd bs;
         bwd_regs<KIND, T, LB>(fr, x, bs);
         T xt[H], xb[H];
-        part_interface<KIND, T, LB>(x, red, rt, rb, p, P, Nr, xt, xb);
+        part_interface<KIND, T, LB>(x, red, rt, rb, p, pp, has_next, has_prev, Nr, xt, xb);
+        // One store pointer stepped row by row (pinned, so that the 64-bit
+        // addresses of all rows are not computed up front and kept live).
         Tout *dst = out + (int64_t)r0 * rs + j;
+        if constexpr (!CN) {
 #pragma unroll
-        for (int t = 0; t < LB; ++t) {
-            const T v = part_correct<KIND, T>(x[t], sp + t * 2 * H, xt, xb);
-            if (r0 + t < n) __builtin_nontemporal_store(static_cast<Tout>(v), &dst[(int64_t)t * rs]);
+            for (int t = 0; t < LB; ++t) {
+                const T v = part_correct<KIND, T>(x[t], sp + t * 2 * H, xt, xb);
+                if (r0 + t < n) __builtin_nontemporal_store(static_cast<Tout>(v), dst);
+                dst += rs;
+                asm volatile("" : "+v"(dst));
+            }
+        } else {
+            // u = the corrected solution.  Only the block's first and last H
+            // values are formed before the exchange; the rest are corrected
+            // on the fly in a window of 2H + 1 rows, so that each solved value
+            // is dropped as soon as it is used (as in the plain store loop).
+            auto corr = [&](int i) -> T { return part_correct<KIND, T>(x[i], sp + i * 2 * H, xt, xb); };
+            T *e = lend + (s * P + p) * 2 * H;
+#pragma unroll
+            for (int c = 0; c < H; ++c) {
+                e[c] = corr(c);
+                e[H + c] = corr(LB - H + c);
+            }
+            __syncthreads();
+            T lft[H], rgt[H];  // u just before and just after the block (0 past the ends)
+#pragma unroll
+            for (int c = 0; c < H; ++c) {
+                lft[c] = has_prev ? lend[(s * P + pp) * 2 * H + H + c] : T(0);
+                rgt[c] = has_next ? lend[(s * P + pn) * 2 * H + c] : T(0);
+            }
+            __syncthreads();  // lend is rewritten next group
+            T win[NB];        // win[k] = u at row t - H + k
+#pragma unroll
+            for (int k = 0; k < NB - 1; ++k) win[k] = k < H ? lft[k] : corr(k - H);
+#pragma unroll
+            for (int t = 0; t < LB; ++t) {
+                win[NB - 1] = t + H < LB ? corr(t + H) : rgt[t + H - LB];
+                const double *b = lband + (r0 + t) * NB;
+                T ax = T(b[0]) * win[0];
+#pragma unroll
+                for (int k = 1; k < NB; ++k) ax = fma(T(b[k]), win[k], ax);
+                const T v = T(2) * win[H] - ax;
+                if (r0 + t < n) __builtin_nontemporal_store(static_cast<Tout>(v), dst);
+                dst += rs;
+                asm volatile("" : "+v"(dst));
+#pragma unroll
+                for (int k = 0; k < NB - 1; ++k) win[k] = win[k + 1];
+                if (t % kGroup == kGroup - 1) pin(ax);  // band and spike reads stay with their rows
+            }
         }
     }
 }
@@ -853,7 +919,7 @@ __global__ __launch_bounds__(MAXT) void k_part_refine(const unsigned char *__res
             typename R::Bwd bs;
             bwd_regs<KIND, float, LB>(fr, w, bs);
             float xt[H], xb[H];
-            part_interface<KIND, float, LB>(w, red, rt, rb, p, P, Nr, xt, xb);
+            part_interface<KIND, float, LB>(w, red, rt, rb, p, p - 1, p <= P - 2, p >= 1, Nr, xt, xb);
 #pragma unroll
             for (int t = 0; t < LB; ++t) x[t] = (double)part_correct<KIND, float>(w[t], sp + t * 2 * H, xt, xb);
         }
@@ -887,7 +953,7 @@ __global__ __launch_bounds__(MAXT) void k_part_refine(const unsigned char *__res
             typename R::Bwd bs;
             bwd_regs<KIND, float, LB>(fr, w, bs);
             float xt[H], xb[H];
-            part_interface<KIND, float, LB>(w, red, rt, rb, p, P, Nr, xt, xb);
+            part_interface<KIND, float, LB>(w, red, rt, rb, p, p - 1, p <= P - 2, p >= 1, Nr, xt, xb);
 #pragma unroll
             for (int t = 0; t < LB; ++t) x[t] += (double)part_correct<KIND, float>(w[t], sp + t * 2 * H, xt, xb);
         }
@@ -1258,10 +1324,10 @@ constexpr int part_maxt() {
     return (LB == 64 && sizeof(T) == 8) ? 512 : 1024;
 }
 
-// The partitioned kernel of (KIND, T, LB), allowed the whole LDS of a CU.
-template <int KIND, typename T, int LB>
+// The partitioned kernel of (KIND, T, LB, CN), allowed the whole LDS of a CU.
+template <int KIND, typename T, int LB, bool CN>
 hipError_t part_kernel(const void **fn) {
-    auto kern = k_part<KIND, T, T, T, LB, part_maxt<KIND, T, LB>()>;
+    auto kern = k_part<KIND, T, T, T, LB, part_maxt<KIND, T, LB>(), CN>;
     static bool attr = false;
     if (!attr) {
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
@@ -1273,34 +1339,45 @@ hipError_t part_kernel(const void **fn) {
     return hipSuccess;
 }
 
-template <int KIND, typename T>
+template <int KIND, typename T, bool CN>
 int part_wgs_lb(int lb, int threads, size_t lds) {
     const void *fn = nullptr;
-    hipError_t e = lb == 16 ? part_kernel<KIND, T, 16>(&fn) : lb == 32 ? part_kernel<KIND, T, 32>(&fn)
-                                                                       : part_kernel<KIND, T, 64>(&fn);
+    hipError_t e = lb == 16 ? part_kernel<KIND, T, 16, CN>(&fn)
+                            : lb == 32 ? part_kernel<KIND, T, 32, CN>(&fn) : part_kernel<KIND, T, 64, CN>(&fn);
     int wgs = 0;
     if (e != hipSuccess || hipOccupancyMaxActiveBlocksPerMultiprocessor(&wgs, fn, threads, lds) != hipSuccess)
         return 0;
     return wgs;
 }
 
+// The blocks of a periodic tridiagonal matrix are plain tridiagonal.
+int part_kind(int kind) { return kind == SBS_PENTA ? SBS_PENTA : SBS_TRI; }
+
 // Workgroups of the partitioned kernel that one CU holds at once (registers,
 // waves and LDS together).
-int part_wgs_per_cu(int kind, int tc, int lb, int threads, size_t lds) {
-    if (kind == SBS_TRI)
-        return tc == 0 ? part_wgs_lb<SBS_TRI, double>(lb, threads, lds) : part_wgs_lb<SBS_TRI, float>(lb, threads, lds);
-    return tc == 0 ? part_wgs_lb<SBS_PENTA, double>(lb, threads, lds)
-                   : part_wgs_lb<SBS_PENTA, float>(lb, threads, lds);
+int part_wgs_per_cu(int kind, int tc, int lb, int threads, size_t lds, bool cn) {
+    if (part_kind(kind) == SBS_TRI) {
+        if (cn)
+            return tc == 0 ? part_wgs_lb<SBS_TRI, double, true>(lb, threads, lds)
+                           : part_wgs_lb<SBS_TRI, float, true>(lb, threads, lds);
+        return tc == 0 ? part_wgs_lb<SBS_TRI, double, false>(lb, threads, lds)
+                       : part_wgs_lb<SBS_TRI, float, false>(lb, threads, lds);
+    }
+    if (cn)
+        return tc == 0 ? part_wgs_lb<SBS_PENTA, double, true>(lb, threads, lds)
+                       : part_wgs_lb<SBS_PENTA, float, true>(lb, threads, lds);
+    return tc == 0 ? part_wgs_lb<SBS_PENTA, double, false>(lb, threads, lds)
+                   : part_wgs_lb<SBS_PENTA, float, false>(lb, threads, lds);
 }
 
-template <int KIND, typename T, int LB>
+template <int KIND, typename T, int LB, bool CN>
 hipError_t go_part(const sbs_lhs *h, const PartChoice &c, const void *in, void *out, int64_t m, hipStream_t s) {
     constexpr int MAXT = part_maxt<KIND, T, LB>();
     const PartPlan &pp = h->part[c.plan];
     const bool f64 = sizeof(T) == 8;
-    auto kern = k_part<KIND, T, T, T, LB, MAXT>;
+    auto kern = k_part<KIND, T, T, T, LB, MAXT, CN>;
     const void *fn = nullptr;
-    if (hipError_t e = part_kernel<KIND, T, LB>(&fn); e != hipSuccess) return e;
+    if (hipError_t e = part_kernel<KIND, T, LB, CN>(&fn); e != hipSuccess) return e;
     if (c.threads > MAXT) return hipErrorInvalidValue;
     const int ngroups = (int)((m + c.S - 1) / c.S);
     int cus = 256;
@@ -1311,16 +1388,16 @@ hipError_t go_part(const sbs_lhs *h, const PartChoice &c, const void *in, void *
                        static_cast<const unsigned char *>(f64 ? pp.blob64 : pp.blob32),
                        (int)(f64 ? pp.fac_bytes64 : pp.fac_bytes32), (int)(f64 ? pp.spk_bytes64 : pp.spk_bytes32),
                        (int)(f64 ? pp.rinv_bytes64 : pp.rinv_bytes32), (int)h->n, pp.P, pp.Nr, c.S, ngroups,
-                       static_cast<const T *>(in), static_cast<T *>(out), m);
+                       (int)pp.periodic, h->bands, static_cast<const T *>(in), static_cast<T *>(out), m);
     return hipGetLastError();
 }
 
-template <int KIND, typename T>
+template <int KIND, typename T, bool CN>
 hipError_t go_part_lb(const sbs_lhs *h, const PartChoice &c, const void *in, void *out, int64_t m, hipStream_t s) {
     switch (h->part[c.plan].lb) {
-        case 16: return go_part<KIND, T, 16>(h, c, in, out, m, s);
-        case 32: return go_part<KIND, T, 32>(h, c, in, out, m, s);
-        default: return go_part<KIND, T, 64>(h, c, in, out, m, s);
+        case 16: return go_part<KIND, T, 16, CN>(h, c, in, out, m, s);
+        case 32: return go_part<KIND, T, 32, CN>(h, c, in, out, m, s);
+        default: return go_part<KIND, T, 64, CN>(h, c, in, out, m, s);
     }
 }
 }  // namespace
@@ -1407,8 +1484,11 @@ hipError_t launch_partition_refine(const sbs_lhs *h, const PartChoice &c, const 
 // 8 waves per CU).  S >= 16 keeps every row access a whole 128-byte line
 // (FP64); narrower workgroups (down to 4 systems) are only tried when the
 // batch is too small to give every CU a group.
-bool choose_partition(const sbs_lhs *h, int tc, int64_t m, PartChoice *out) {
+// cn: the Crank-Nicolson form also holds the band rows (2h+1 doubles per row)
+// and the exchange of block ends in LDS.
+bool choose_partition(const sbs_lhs *h, int tc, int64_t m, PartChoice *out, bool cn) {
     const size_t elem = tc == 0 ? 8 : 4;
+    const int H = part_kind(h->kind) / 2;
     int cus = 256;
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, h->device);
     PartChoice best;
@@ -1422,9 +1502,12 @@ bool choose_partition(const sbs_lhs *h, int tc, int64_t m, PartChoice *out) {
             if (S < 16 && (m + 2 * S - 1) / (2 * S) >= cus) break;  // the wider S already fills the CUs
             const int threads = S * pp.P;
             if (threads > maxt) continue;
-            const size_t lds = blob + ((size_t)S * (pp.Nr + 1) * elem + 15) / 16 * 16;
+            size_t lds = blob + ((size_t)S * (pp.Nr + 1) * elem + 15) / 16 * 16;
+            if (cn)
+                lds += ((size_t)pp.P * pp.lb * (2 * H + 1) * 8 + 15) / 16 * 16 +
+                       ((size_t)S * pp.P * 2 * H * elem + 15) / 16 * 16;
             if (lds > kMaxPartLdsBytes) continue;
-            const int wgs = part_wgs_per_cu(h->kind, tc, pp.lb, threads, lds);
+            const int wgs = part_wgs_per_cu(h->kind, tc, pp.lb, threads, lds, cn);
             if (wgs < 1) continue;
             const int64_t groups = (m + S - 1) / S;
             const int64_t waves = std::min<int64_t>(
@@ -1445,14 +1528,21 @@ bool choose_partition(const sbs_lhs *h, int tc, int64_t m, PartChoice *out) {
 }
 
 hipError_t launch_partition(const sbs_lhs *h, const PartChoice &c, int tc, int tin, int tout, const void *in, void *out,
-                            int64_t m, hipStream_t stream) {
+                            int64_t m, hipStream_t stream, bool cn) {
     if (m <= 0) return hipSuccess;
     if (tc != tin || tc != tout) return hipErrorInvalidValue;
-    if (h->kind == SBS_TRI)
-        return tc == 0 ? go_part_lb<SBS_TRI, double>(h, c, in, out, m, stream)
-                       : go_part_lb<SBS_TRI, float>(h, c, in, out, m, stream);
-    return tc == 0 ? go_part_lb<SBS_PENTA, double>(h, c, in, out, m, stream)
-                   : go_part_lb<SBS_PENTA, float>(h, c, in, out, m, stream);
+    if (part_kind(h->kind) == SBS_TRI) {
+        if (cn)
+            return tc == 0 ? go_part_lb<SBS_TRI, double, true>(h, c, in, out, m, stream)
+                           : go_part_lb<SBS_TRI, float, true>(h, c, in, out, m, stream);
+        return tc == 0 ? go_part_lb<SBS_TRI, double, false>(h, c, in, out, m, stream)
+                       : go_part_lb<SBS_TRI, float, false>(h, c, in, out, m, stream);
+    }
+    if (cn)
+        return tc == 0 ? go_part_lb<SBS_PENTA, double, true>(h, c, in, out, m, stream)
+                       : go_part_lb<SBS_PENTA, float, true>(h, c, in, out, m, stream);
+    return tc == 0 ? go_part_lb<SBS_PENTA, double, false>(h, c, in, out, m, stream)
+                   : go_part_lb<SBS_PENTA, float, false>(h, c, in, out, m, stream);
 }
 
 hipError_t launch_refine_step(const sbs_lhs *h, int mode, const float *b, double *x,

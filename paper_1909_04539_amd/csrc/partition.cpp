@@ -62,11 +62,18 @@ struct HostPlan {
     std::vector<int> map;            // block p -> stored block map[p]
 };
 
+// kind is 3 or 5 (the bandwidth); `periodic` wraps a tridiagonal matrix
+// round (row 0 couples to row n-1 and back), which needs n to be a whole
+// number of blocks: then block 0's left neighbour is block P-1 and block
+// P-1's right neighbour is block 0, and the interface system gains that pair.
 template <typename Row, typename FactorFn, typename SolveFn>
-bool build_plan(int kind, int64_t n, const double *bands, int lb, FactorFn factor, SolveFn solve, HostPlan &hp) {
+bool build_plan(int kind, bool periodic, int64_t n, const double *bands, int lb, FactorFn factor, SolveFn solve,
+                HostPlan &hp) {
     const int h = kind / 2;
     const int P = (int)((n + lb - 1) / lb);
-    if (P > kMaxBlocks || lb < 2 * h || 2 * h * (P - 1) > kMaxInterface) return false;
+    const int pairs = periodic ? P : P - 1;
+    if (P > kMaxBlocks || lb < 2 * h || 2 * h * pairs > kMaxInterface) return false;
+    if (periodic && (n % lb != 0 || P < 2)) return false;
     const int64_t npad = (int64_t)P * lb;
     std::vector<Row> rows(npad);
     std::vector<double> spk((size_t)npad * 2 * h, 0.0);
@@ -77,38 +84,49 @@ bool build_plan(int kind, int64_t n, const double *bands, int lb, FactorFn facto
         if (col < (int64_t)p * lb || col >= (int64_t)(p + 1) * lb || col >= n) return 0.0;
         return bands[(int64_t)k * n + i];
     };
+    // Entry of row i < n in column col (any index; wrapped when periodic).
+    auto entry = [&](int64_t i, int64_t col) -> double {
+        if (i >= n) return 0.0;
+        int64_t d = col - i;
+        if (periodic) {
+            d = ((d % n) + n) % n;
+            if (d > n / 2) d -= n;
+        } else if (col < 0 || col >= n) {
+            return 0.0;
+        }
+        return (d >= -h && d <= h) ? bands[(int64_t)(d + h) * n + i] : 0.0;
+    };
     std::vector<double> v(lb);
     for (int p = 0; p < P; ++p) {
         const int64_t r0 = (int64_t)p * lb;
         int64_t bad = -1;
         if (!factor(lb, [&](int k, int64_t t) { return local(p, k, r0 + t); }, rows.data() + r0, &bad)) return false;
-        // Right spike columns: coupling of row r0+t to column r0+lb+c.
+        // Right spike columns: coupling of row r0+t to column r0+lb+c
+        // (block p+1's first unknowns; none past the last block unless periodic).
         for (int c = 0; c < h; ++c) {
-            for (int t = 0; t < lb; ++t) {
-                const int64_t i = r0 + t, col = r0 + lb + c;
-                const int k = (int)(col - i + h);
-                v[t] = (i < n && col < n && k >= 0 && k < kind) ? bands[(int64_t)k * n + i] : 0.0;
-            }
+            for (int t = 0; t < lb; ++t)
+                v[t] = (p < P - 1 || periodic) ? entry(r0 + t, r0 + lb + c) : 0.0;
             solve(lb, rows.data() + r0, v.data());
             for (int t = 0; t < lb; ++t) spk[(size_t)(r0 + t) * 2 * h + c] = v[t];
         }
         // Left spike columns: coupling of row r0+t to column r0-h+c.
         for (int c = 0; c < h; ++c) {
-            for (int t = 0; t < lb; ++t) {
-                const int64_t i = r0 + t, col = r0 - h + c;
-                const int k = (int)(col - i + h);
-                v[t] = (p > 0 && i < n && k >= 0 && k < kind) ? bands[(int64_t)k * n + i] : 0.0;
-            }
+            for (int t = 0; t < lb; ++t) v[t] = (p > 0 || periodic) ? entry(r0 + t, r0 - h + c) : 0.0;
             solve(lb, rows.data() + r0, v.data());
             for (int t = 0; t < lb; ++t) spk[(size_t)(r0 + t) * 2 * h + h + c] = v[t];
         }
     }
-    // Interface system.  Unknown order: pair q = 0..P-2 holds
-    // (bottom h of block q, top h of block q+1).
-    const int Nr = 2 * h * (P - 1);
+    // Interface system.  Unknown order: pair q holds (bottom h of block q,
+    // top h of block q+1), q = 0..P-2, and q = P-1 (block P-1, block 0) when
+    // periodic.
+    const int Nr = 2 * h * pairs;
     std::vector<double> R((size_t)Nr * Nr, 0.0);
-    auto ibot = [&](int p, int c) { return 2 * h * p + c; };          // p in [0, P-2]
-    auto itop = [&](int p, int c) { return 2 * h * (p - 1) + h + c; };  // p in [1, P-1]
+    const auto next = [&](int p) { return p == P - 1 ? 0 : p + 1; };
+    const auto prev = [&](int p) { return p == 0 ? P - 1 : p - 1; };
+    const auto has_next = [&](int p) { return periodic || p <= P - 2; };
+    const auto has_prev = [&](int p) { return periodic || p >= 1; };
+    auto ibot = [&](int p, int c) { return 2 * h * p + c; };              // bottom of block p
+    auto itop = [&](int p, int c) { return 2 * h * prev(p) + h + c; };    // top of block p
     auto V = [&](int p, int t, int c) { return spk[(size_t)((int64_t)p * lb + t) * 2 * h + c]; };
     auto Wt = [&](int p, int t, int c) { return spk[(size_t)((int64_t)p * lb + t) * 2 * h + h + c]; };
     for (int p = 0; p < P; ++p) {
@@ -116,19 +134,19 @@ bool build_plan(int kind, int64_t n, const double *bands, int lb, FactorFn facto
             // equation of block p's local row t, for its interface rows
             for (int side = 0; side < 2; ++side) {
                 int row, t;
-                if (side == 0) {  // bottom rows, needed for p <= P-2
-                    if (p > P - 2) continue;
+                if (side == 0) {  // bottom rows
+                    if (!has_next(p)) continue;
                     row = ibot(p, c);
                     t = lb - h + c;
-                } else {  // top rows, needed for p >= 1
-                    if (p < 1) continue;
+                } else {  // top rows
+                    if (!has_prev(p)) continue;
                     row = itop(p, c);
                     t = c;
                 }
                 R[(size_t)row * Nr + row] += 1.0;
                 for (int c2 = 0; c2 < h; ++c2) {
-                    if (p <= P - 2) R[(size_t)row * Nr + itop(p + 1, c2)] += V(p, t, c2);
-                    if (p >= 1) R[(size_t)row * Nr + ibot(p - 1, c2)] += Wt(p, t, c2);
+                    if (has_next(p)) R[(size_t)row * Nr + itop(next(p), c2)] += V(p, t, c2);
+                    if (has_prev(p)) R[(size_t)row * Nr + ibot(prev(p), c2)] += Wt(p, t, c2);
                 }
             }
         }
@@ -214,19 +232,24 @@ void serialise(const HostPlan &hp, std::vector<unsigned char> &b64, std::vector<
 sbs_status build_partitions(sbs_lhs *h, const double *bands) {
     std::vector<unsigned char> b64[3], b32[3];
     size_t total = 0;
+    // A periodic tridiagonal matrix is partitioned directly (the blocks are
+    // plain tridiagonal; the wrap is one more interface pair).
+    const bool periodic = h->kind == SBS_TRI_PERIODIC;
+    const bool tri = h->kind == SBS_TRI || periodic;
     for (int q = 0; q < 3; ++q) {
         HostPlan hp;
         const int lb = kPartLbs[q];
         bool ok;
-        if (h->kind == SBS_TRI)
-            ok = build_plan<TriRow<double>>(h->kind, h->n, bands, lb, factor_tri_rows<std::function<double(int, int64_t)>>,
-                                            solve_tri_rows, hp);
+        if (tri)
+            ok = build_plan<TriRow<double>>(SBS_TRI, periodic, h->n, bands, lb,
+                                            factor_tri_rows<std::function<double(int, int64_t)>>, solve_tri_rows, hp);
         else
-            ok = build_plan<PentaRow<double>>(h->kind, h->n, bands, lb,
+            ok = build_plan<PentaRow<double>>(SBS_PENTA, false, h->n, bands, lb,
                                               factor_penta_rows<std::function<double(int, int64_t)>>, solve_penta_rows, hp);
         if (!ok) continue;
         PartPlan &pp = h->part[q];
-        if (h->kind == SBS_TRI)
+        pp.periodic = periodic;
+        if (tri)
             serialise<TriRow<double>, TriRow<float>>(hp, b64[q], b32[q], pp);
         else
             serialise<PentaRow<double>, PentaRow<float>>(hp, b64[q], b32[q], pp);

@@ -4,7 +4,7 @@
 // p the factor and spikes of stored block map[p], the block solve, the
 // interface unknowns from rows of the stored inverse, the correction.
 //   part_emulate in.bin out.bin
-// in:  int32 kind, int64 n, int64 m, bands (kind x n doubles), rhs (n x m)
+// in:  int32 kind, int64 n, int64 m, bands (3 or 5 x n doubles), rhs (n x m)
 // out: per block length 16, 32, 64: int32 lb (0 if no plan), P, D, Nr, then
 //      the n x m solution (only when the plan exists)
 #include <cstdio>
@@ -18,7 +18,7 @@ using namespace sbs;
 
 template <typename Row, typename Solve>
 void emulate(const sbs_lhs &h, const PartPlan &pp, const double *rhs, int64_t m, double *x, Solve solve) {
-    const int H = h.kind / 2, lb = pp.lb, P = pp.P, Nr = pp.Nr;
+    const int H = h.kind == SBS_PENTA ? 2 : 1, lb = pp.lb, P = pp.P, Nr = pp.Nr;
     const unsigned char *blob = static_cast<const unsigned char *>(pp.blob64);
     const Row *fac = reinterpret_cast<const Row *>(blob);
     const double *spk = reinterpret_cast<const double *>(blob + pp.fac_bytes64);
@@ -29,18 +29,23 @@ void emulate(const sbs_lhs &h, const PartPlan &pp, const double *rhs, int64_t m,
     for (int64_t j = 0; j < m; ++j) {
         for (int64_t i = 0; i < (int64_t)P * lb; ++i) g[i] = i < n ? rhs[i * m + j] : 0.0;
         for (int p = 0; p < P; ++p) solve(lb, fac + (int64_t)map[p] * lb, g.data() + (int64_t)p * lb);
+        // pair q: (bottom of block q, top of the next block); a periodic plan
+        // also pairs block P-1 with block 0
+        auto has_next = [&](int p) { return pp.periodic || p <= P - 2; };
+        auto has_prev = [&](int p) { return pp.periodic || p >= 1; };
+        auto prev = [&](int p) { return p == 0 ? P - 1 : p - 1; };
         for (int p = 0; p < P; ++p) {
-            if (p <= P - 2)
+            if (has_next(p))
                 for (int c = 0; c < H; ++c) red[2 * H * p + c] = g[(int64_t)p * lb + lb - H + c];
-            if (p >= 1)
-                for (int c = 0; c < H; ++c) red[2 * H * (p - 1) + H + c] = g[(int64_t)p * lb + c];
+            if (has_prev(p))
+                for (int c = 0; c < H; ++c) red[2 * H * prev(p) + H + c] = g[(int64_t)p * lb + c];
         }
         for (int p = 0; p < P; ++p) {
             double xt[2] = {0, 0}, xb[2] = {0, 0};
             for (int c = 0; c < H; ++c)
                 for (int k = 0; k < Nr; ++k) {
-                    if (p <= P - 2) xt[c] += rinv[(size_t)(2 * H * p + H + c) * Nr + k] * red[k];
-                    if (p >= 1) xb[c] += rinv[(size_t)(2 * H * (p - 1) + c) * Nr + k] * red[k];
+                    if (has_next(p)) xt[c] += rinv[(size_t)(2 * H * p + H + c) * Nr + k] * red[k];
+                    if (has_prev(p)) xb[c] += rinv[(size_t)(2 * H * prev(p) + c) * Nr + k] * red[k];
                 }
             const double *sp = spk + (size_t)map[p] * lb * 2 * H;
             for (int t = 0; t < lb; ++t) {
@@ -62,7 +67,8 @@ int main(int argc, char **argv) {
     int32_t kind;
     int64_t n, m;
     if (std::fread(&kind, 4, 1, f) != 1 || std::fread(&n, 8, 1, f) != 1 || std::fread(&m, 8, 1, f) != 1) return 2;
-    std::vector<double> bands((size_t)kind * n), rhs((size_t)n * m), x((size_t)n * m);
+    const int nb = kind == SBS_TRI_PERIODIC ? 3 : kind;
+    std::vector<double> bands((size_t)nb * n), rhs((size_t)n * m), x((size_t)n * m);
     if (std::fread(bands.data(), 8, bands.size(), f) != bands.size()) return 2;
     if (std::fread(rhs.data(), 8, rhs.size(), f) != rhs.size()) return 2;
     std::fclose(f);
@@ -77,7 +83,7 @@ int main(int argc, char **argv) {
         int32_t hdr[4] = {pp.ok ? pp.lb : 0, pp.P, pp.D, pp.Nr};
         std::fwrite(hdr, 4, 4, o);
         if (!pp.ok) continue;
-        if (kind == SBS_TRI)
+        if (kind != SBS_PENTA)  // periodic plans have plain tridiagonal blocks
             emulate<TriRow<double>>(h, pp, rhs.data(), m, x.data(), solve_tri_rows);
         else
             emulate<PentaRow<double>>(h, pp, rhs.data(), m, x.data(), solve_penta_rows);

@@ -1,7 +1,8 @@
-"""GPU parity of periodic tridiagonal solves (Section 3.3, Sherman-Morrison
-folded into the two sweeps) against the periodic oracle, every sweep variant,
-FP64 within 1e-12 per column; plus the entry points that reject periodic
-handles and a periodic ADI step."""
+"""GPU parity of periodic tridiagonal solves (Section 3.3) against the
+periodic oracle, FP64 within 1e-12 per column: the sweep variants (the
+Sherman-Morrison correction folded into the two sweeps) and the partitioned
+variant (the wrap as one more interface pair); plus the entry points that
+reject periodic handles and a periodic ADI step."""
 import ctypes
 
 import numpy as np
@@ -36,6 +37,12 @@ def chunked_fits(n, elem=8):
     return ((n + 31) // 32) * 64 * elem + 2 * 32 * row <= 64 * 1024
 
 
+def partition_available(n):
+    """Periodic plans: n a whole number P >= 2 of blocks of 16, 32 or 64 rows,
+    at most 90 interface unknowns (2 per block: the wrap adds one pair)."""
+    return any(n % lb == 0 and 2 <= n // lb and 2 * (n // lb) <= 90 for lb in (16, 32, 64))
+
+
 def gpu_solve(B, rhs, variant=sbs.VARIANT_AUTO, dtype=torch.float64):
     with sbs.SharedLhs(P, B) as lhs:
         x = torch.from_numpy(np.ascontiguousarray(rhs)).to(DEV, dtype)
@@ -44,19 +51,25 @@ def gpu_solve(B, rhs, variant=sbs.VARIANT_AUTO, dtype=torch.float64):
         return x.cpu().numpy().astype(np.float64)
 
 
-SHAPES = [(3, 1), (3, 64), (4, 7), (7, 130), (32, 64), (33, 65), (64, 100), (65, 1000), (200, 4097),
-          (1024, 2000), (4096, 300), (20000, 70)]
+SHAPES = [(3, 1), (3, 64), (4, 7), (7, 130), (32, 64), (33, 65), (64, 100), (65, 1000), (96, 33), (200, 4097),
+          (1024, 2000), (2048, 129), (4096, 300), (20000, 70)]
 
 
 @pytest.mark.parametrize("n,m", SHAPES)
 @pytest.mark.parametrize("variant", [sbs.VARIANT_AUTO, sbs.VARIANT_RESIDENT, sbs.VARIANT_CHUNKED,
-                                     sbs.VARIANT_STREAM])
+                                     sbs.VARIANT_STREAM, sbs.VARIANT_PARTITION])
 def test_periodic_parity(n, m, variant):
     if variant == sbs.VARIANT_RESIDENT and n > 64:
         pytest.skip("resident needs n <= 64")
     if variant == sbs.VARIANT_CHUNKED and not chunked_fits(n):
         pytest.skip("checkpoints exceed the chunked variant's LDS")
+    print(f"case periodic n={n} m={m} variant={variant}", flush=True)
     B = ring_bands(n, n + m)
+    if variant == sbs.VARIANT_PARTITION and not partition_available(n):
+        with pytest.raises(sbs.SbsError) as e:
+            gpu_solve(B, np.zeros((n, m)), variant)
+        assert e.value.status == 1
+        return
     rhs = np.random.default_rng(m).uniform(-1, 1, (n, m))
     got = gpu_solve(B, rhs, variant)
     ref = oracle.solve(oracle.TRI_PERIODIC, B, rhs)
@@ -90,8 +103,10 @@ def test_periodic_fp32_plain_solve(n, m):
 
 def test_periodic_auto_variant_and_rejections():
     B = ring_bands(300, 9)
+    with sbs.SharedLhs(P, ring_bands(1024, 9)) as whole:
+        assert sbs.sbs_auto_variant(whole.handle, 1000) == sbs.VARIANT_PARTITION
     with sbs.SharedLhs(P, B) as lhs:
-        assert sbs.sbs_auto_variant(lhs.handle, 1000) == sbs.VARIANT_CHUNKED
+        assert sbs.sbs_auto_variant(lhs.handle, 1000) == sbs.VARIANT_CHUNKED   # 300 rows: no whole blocks
         x = torch.zeros((300, 64), dtype=torch.float64, device=DEV)
         with pytest.raises(sbs.SbsError):
             lhs.solve(x, sbs.VARIANT_PARTITION)
@@ -104,7 +119,7 @@ def test_periodic_auto_variant_and_rejections():
         assert L.sbs_server_register(srv, lhs.handle, ctypes.byref(i)) == 1   # invalid argument
         assert L.sbs_server_destroy(srv) == 0
         _, n, dev_bytes = sbs.sbs_handle_info(lhs.handle)
-        assert n == 300 and dev_bytes < 300 * 256
+        assert n == 300 and dev_bytes <= 320 * (64 + 32 + 64)
 
 
 def test_periodic_adi_step():

@@ -1,6 +1,7 @@
 """Host side of the partitioned solve, on the CPU: the plan that
 build_partitions serialises (block factors, spikes, inverse of the interface
-system, and the map that lets bit-identical blocks share one stored copy) is
+system, the map that lets bit-identical blocks share one stored copy, and the
+wrap-round pair of periodic matrices) is
 run step for step by tests/host/part_emulate.cpp, built with g++ and
 AddressSanitizer against the CPU stand-in for the device calls, and compared
 with the oracle."""
@@ -101,3 +102,36 @@ def test_constant_bands_store_three_blocks(exe, tmp_path, kind, n, lb):
     _, P, got_d, _, x = plan[lb]
     assert P > 3 and got_d == 3, (P, got_d)
     assert colrel(x, ref) <= 1e-13
+
+
+@pytest.mark.parametrize("n", [32, 64, 96, 512, 1024, 2048])
+def test_periodic_plan_solves_like_the_periodic_oracle(exe, tmp_path, n):
+    # periodic tridiagonal: plans exist when n is a whole number of blocks
+    # (P >= 2, at most 90 interface unknowns, one pair more than banded)
+    rng = np.random.default_rng(n)
+    a, c = rng.uniform(-1, 1, n), rng.uniform(-1, 1, n)
+    B = np.stack([a, np.abs(a) + np.abs(c) + rng.uniform(1, 2, n), c])
+    rhs = rng.uniform(-1, 1, (n, 3))
+    ref = oracle.solve(oracle.TRI_PERIODIC, B, rhs)
+    found = 0
+    for want_lb, (lb, P, D, Nr, x) in zip((16, 32, 64), run(exe, tmp_path, 13, B, rhs)):
+        exists = n % want_lb == 0 and n // want_lb >= 2 and 2 * (n // want_lb) <= 90
+        assert lb == (want_lb if exists else 0)
+        if not lb:
+            continue
+        found += 1
+        assert Nr == 2 * P
+        assert colrel(x, ref) <= 1e-13, (lb, P)
+    assert found >= 1
+
+
+def test_constant_periodic_bands_store_one_block(exe, tmp_path):
+    # with the wrap every block of a constant-band periodic matrix is alike
+    n, s = 1024, 0.7
+    B = np.stack([np.full(n, -s), np.full(n, 1 + 2 * s), np.full(n, -s)])
+    rhs = np.random.default_rng(1).uniform(-1, 1, (n, 2))
+    ref = oracle.solve(oracle.TRI_PERIODIC, B, rhs)
+    plans = [p for p in run(exe, tmp_path, 13, B, rhs) if p[0]]
+    assert plans
+    for lb, P, D, Nr, x in plans:
+        assert D == 1 and colrel(x, ref) <= 1e-13
