@@ -810,16 +810,12 @@ __global__ __launch_bounds__(MAXT) void k_part(const unsigned char *__restrict__
         bwd_regs<KIND, T, LB>(fr, x, bs);
         T xt[H], xb[H];
         part_interface<KIND, T, LB>(x, red, rt, rb, p, pp, has_next, has_prev, Nr, xt, xb);
-        // One store pointer stepped row by row (pinned, so that the 64-bit
-        // addresses of all rows are not computed up front and kept live).
         Tout *dst = out + (int64_t)r0 * rs + j;
         if constexpr (!CN) {
 #pragma unroll
             for (int t = 0; t < LB; ++t) {
                 const T v = part_correct<KIND, T>(x[t], sp + t * 2 * H, xt, xb);
-                if (r0 + t < n) __builtin_nontemporal_store(static_cast<Tout>(v), dst);
-                dst += rs;
-                asm volatile("" : "+v"(dst));
+                if (r0 + t < n) __builtin_nontemporal_store(static_cast<Tout>(v), &dst[(int64_t)t * rs]);
             }
         } else {
             // u = the corrected solution.  Only the block's first and last H
@@ -852,6 +848,8 @@ __global__ __launch_bounds__(MAXT) void k_part(const unsigned char *__restrict__
 #pragma unroll
                 for (int k = 1; k < NB; ++k) ax = fma(T(b[k]), win[k], ax);
                 const T v = T(2) * win[H] - ax;
+                // one store pointer stepped row by row (pinned, so that the
+                // addresses of all rows are not formed up front and kept live)
                 if (r0 + t < n) __builtin_nontemporal_store(static_cast<Tout>(v), dst);
                 dst += rs;
                 asm volatile("" : "+v"(dst));
