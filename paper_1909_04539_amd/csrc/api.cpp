@@ -278,7 +278,17 @@ sbs_status sbs_adi_step(sbs_handle hy, sbs_handle hx, double *grid, double *work
     if (!hy || !hx || ny < 1 || nx < 1 || hy->n != ny || hx->n != nx) return SBS_ERR_INVALID_ARG;
     if (!grid || !work) return SBS_ERR_INVALID_ARG;
     sbs_status st = sbs_solve_batch(hy, grid, nx, SBS_F64, stream);          // along y
-    if (st == SBS_OK) st = sbs_transpose(grid, work, ny, nx, SBS_F64, stream);  // (ny, nx) -> (nx, ny)
+    if (st != SBS_OK) return st;
+    // Along x the systems are the grid's rows.  With a partition plan they
+    // are solved where they are (each lane reads its block of a row as one
+    // contiguous run); otherwise through the interleaved layout of the
+    // transpose.
+    PartChoice pc;
+    if (choose_partition(hx, 0, ny, &pc))
+        return launch_partition_rows(hx, pc, grid, ny, static_cast<hipStream_t>(stream)) == hipSuccess
+                   ? SBS_OK
+                   : SBS_ERR_DEVICE;
+    st = sbs_transpose(grid, work, ny, nx, SBS_F64, stream);                   // (ny, nx) -> (nx, ny)
     if (st == SBS_OK) st = sbs_solve_batch(hx, work, ny, SBS_F64, stream);      // along x
     if (st == SBS_OK) st = sbs_transpose(work, grid, nx, ny, SBS_F64, stream);  // back
     return st;

@@ -148,6 +148,9 @@ struct PartChoice {
 bool choose_partition(const sbs_lhs *h, int tc, int64_t m, PartChoice *out, bool cn = false);
 hipError_t launch_partition(const sbs_lhs *h, const PartChoice &c, int tc, int tin, int tout, const void *in,
                             void *out, int64_t m, hipStream_t stream, bool cn = false);
+// FP64 solve of m systems stored one after another (system j at x + j*n),
+// in place, on the partition chosen for them.
+hipError_t launch_partition_rows(const sbs_lhs *h, const PartChoice &c, double *x, int64_t m, hipStream_t stream);
 sbs_status build_partitions(sbs_lhs *h, const double *bands);
 bool choose_partition_refine(const sbs_lhs *h, int64_t m, PartChoice *out);
 hipError_t launch_partition_refine(const sbs_lhs *h, const PartChoice &c, const float *b, double *x, int64_t m,

@@ -753,7 +753,10 @@ __device__ __forceinline__ void stage_blob(unsigned char *lds, const unsigned ch
 // last H values with the neighbouring blocks through LDS, and writes
 // 2 u - A u with the band rows (compact, NB = 2H + 1 per row, in LDS).
 // `periodic`: block 0 and block P-1 are neighbours (one more interface pair).
-template <int KIND, typename T, typename Tin, typename Tout, int LB, int MAXT, bool CN = false>
+// ROWS: the systems are stored one after another (system j at j*n .. j*n+n-1,
+// the rows of a row-major grid) instead of interleaved; each lane then reads
+// and writes its block as one contiguous run.
+template <int KIND, typename T, typename Tin, typename Tout, int LB, int MAXT, bool CN = false, bool ROWS = false>
 __global__ __launch_bounds__(MAXT) void k_part(const unsigned char *__restrict__ blob, int fac_bytes, int spk_bytes,
                                                int rinv_bytes, int n, int P, int Nr, int S, int ngroups, int periodic,
                                                const BandRow *__restrict__ bands, const Tin *in, Tout *out,
@@ -792,12 +795,26 @@ __global__ __launch_bounds__(MAXT) void k_part(const unsigned char *__restrict__
     const int pp = p == 0 ? P - 1 : p - 1, pn = p == P - 1 ? 0 : p + 1;
     const T *rt = lrinv + (2 * H * p + H) * Nr;  // rows of the next block's first H unknowns
     const T *rb = lrinv + (2 * H * pp) * Nr;     // rows of the previous block's last H
-    const int64_t rs = m;
+    const int64_t rs = ROWS ? 1 : m;  // distance between consecutive unknowns of a system
     for (int g = blockIdx.x; g < ngroups; g += gridDim.x) {
         const int64_t j = min((int64_t)g * S + s, m - 1);
-        const Tin *src = in + (int64_t)r0 * rs + j;
+        const int64_t base = ROWS ? j * n + r0 : (int64_t)r0 * rs + j;
+        const Tin *src = in + base;
         T x[LB];
-        if (r0 + LB <= n) {
+        // row layout with even n: every block starts on a 16-byte boundary,
+        // so pairs of values move as one 16-byte access
+        constexpr bool PAIRS = ROWS && sizeof(T) == 8 && sizeof(Tin) == 8 && sizeof(Tout) == 8;
+        const bool paired = PAIRS && (n % 2 == 0) && r0 + LB <= n;
+        if (paired) {
+            typedef double D2 __attribute__((ext_vector_type(2)));
+            const D2 *s2 = reinterpret_cast<const D2 *>(src);
+#pragma unroll
+            for (int t = 0; t < LB / 2; ++t) {
+                const D2 v = s2[t];
+                x[2 * t] = static_cast<T>(v.x);
+                x[2 * t + 1] = static_cast<T>(v.y);
+            }
+        } else if (r0 + LB <= n) {
 #pragma unroll
             for (int t = 0; t < LB; ++t) x[t] = static_cast<T>(src[(int64_t)t * rs]);
         } else {
@@ -810,7 +827,21 @@ __global__ __launch_bounds__(MAXT) void k_part(const unsigned char *__restrict__
         bwd_regs<KIND, T, LB>(fr, x, bs);
         T xt[H], xb[H];
         part_interface<KIND, T, LB>(x, red, rt, rb, p, pp, has_next, has_prev, Nr, xt, xb);
-        Tout *dst = out + (int64_t)r0 * rs + j;
+        Tout *dst = out + base;
+        if constexpr (PAIRS && !CN) {
+            if (paired) {
+                typedef double D2 __attribute__((ext_vector_type(2)));
+                D2 *d2 = reinterpret_cast<D2 *>(dst);
+#pragma unroll
+                for (int t = 0; t < LB / 2; ++t) {
+                    D2 v;
+                    v.x = static_cast<double>(part_correct<KIND, T>(x[2 * t], sp + 2 * t * 2 * H, xt, xb));
+                    v.y = static_cast<double>(part_correct<KIND, T>(x[2 * t + 1], sp + (2 * t + 1) * 2 * H, xt, xb));
+                    __builtin_nontemporal_store(v, &d2[t]);
+                }
+                continue;
+            }
+        }
         if constexpr (!CN) {
 #pragma unroll
             for (int t = 0; t < LB; ++t) {
@@ -1390,6 +1421,31 @@ hipError_t go_part(const sbs_lhs *h, const PartChoice &c, const void *in, void *
     return hipGetLastError();
 }
 
+// Row layout (FP64 solves only): the same kernel reading each system as one
+// contiguous run.
+template <int KIND, int LB>
+hipError_t go_part_rows(const sbs_lhs *h, const PartChoice &c, double *x, int64_t m, hipStream_t s) {
+    constexpr int MAXT = part_maxt<KIND, double, LB>();
+    const PartPlan &pp = h->part[c.plan];
+    auto kern = k_part<KIND, double, double, double, LB, MAXT, false, true>;
+    static bool attr = false;
+    if (!attr) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxPartLdsBytes);
+        if (e != hipSuccess) return e;
+        attr = true;
+    }
+    if (c.threads > MAXT) return hipErrorInvalidValue;
+    const int ngroups = (int)((m + c.S - 1) / c.S);
+    int cus = 256;
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, h->device);
+    const int grid = (int)std::min<int64_t>(ngroups, (int64_t)cus * std::max(1, c.wgs));
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(c.threads), c.lds, s, static_cast<const unsigned char *>(pp.blob64),
+                       (int)pp.fac_bytes64, (int)pp.spk_bytes64, (int)pp.rinv_bytes64, (int)h->n, pp.P, pp.Nr, c.S,
+                       ngroups, (int)pp.periodic, h->bands, x, x, m);
+    return hipGetLastError();
+}
+
 template <int KIND, typename T, bool CN>
 hipError_t go_part_lb(const sbs_lhs *h, const PartChoice &c, const void *in, void *out, int64_t m, hipStream_t s) {
     switch (h->part[c.plan].lb) {
@@ -1541,6 +1597,18 @@ hipError_t launch_partition(const sbs_lhs *h, const PartChoice &c, int tc, int t
                        : go_part_lb<SBS_PENTA, float, true>(h, c, in, out, m, stream);
     return tc == 0 ? go_part_lb<SBS_PENTA, double, false>(h, c, in, out, m, stream)
                    : go_part_lb<SBS_PENTA, float, false>(h, c, in, out, m, stream);
+}
+
+hipError_t launch_partition_rows(const sbs_lhs *h, const PartChoice &c, double *x, int64_t m, hipStream_t stream) {
+    if (m <= 0) return hipSuccess;
+    const int lb = h->part[c.plan].lb;
+    if (part_kind(h->kind) == SBS_TRI)
+        return lb == 16 ? go_part_rows<SBS_TRI, 16>(h, c, x, m, stream)
+                        : lb == 32 ? go_part_rows<SBS_TRI, 32>(h, c, x, m, stream)
+                                   : go_part_rows<SBS_TRI, 64>(h, c, x, m, stream);
+    return lb == 16 ? go_part_rows<SBS_PENTA, 16>(h, c, x, m, stream)
+                    : lb == 32 ? go_part_rows<SBS_PENTA, 32>(h, c, x, m, stream)
+                               : go_part_rows<SBS_PENTA, 64>(h, c, x, m, stream);
 }
 
 hipError_t launch_refine_step(const sbs_lhs *h, int mode, const float *b, double *x,
