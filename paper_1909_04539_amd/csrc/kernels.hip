@@ -1457,12 +1457,10 @@ hipError_t go_part_lb(const sbs_lhs *h, const PartChoice &c, const void *in, voi
 }  // namespace
 
 namespace {
+// The fused refinement kernel of (KIND, LB), allowed the whole LDS of a CU.
 template <int KIND, int LB>
-hipError_t go_part_refine(const sbs_lhs *h, const PartChoice &c, const float *b, double *x, int64_t m, int sweeps,
-                          hipStream_t s) {
-    constexpr int MAXT = 512;
-    const PartPlan &pp = h->part[c.plan];
-    auto kern = k_part_refine<KIND, LB, MAXT>;
+hipError_t refine_kernel(const void **fn) {
+    auto kern = k_part_refine<KIND, LB, 512>;
     static bool attr = false;
     if (!attr) {
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
@@ -1470,11 +1468,36 @@ hipError_t go_part_refine(const sbs_lhs *h, const PartChoice &c, const float *b,
         if (e != hipSuccess) return e;
         attr = true;
     }
+    *fn = reinterpret_cast<const void *>(kern);
+    return hipSuccess;
+}
+
+int refine_wgs_per_cu(int kind, int lb, int threads, size_t lds) {
+    const void *fn = nullptr;
+    hipError_t e;
+    if (kind == SBS_TRI)
+        e = lb == 16 ? refine_kernel<SBS_TRI, 16>(&fn) : refine_kernel<SBS_TRI, 32>(&fn);
+    else
+        e = lb == 16 ? refine_kernel<SBS_PENTA, 16>(&fn) : refine_kernel<SBS_PENTA, 32>(&fn);
+    int wgs = 0;
+    if (e != hipSuccess || hipOccupancyMaxActiveBlocksPerMultiprocessor(&wgs, fn, threads, lds) != hipSuccess)
+        return 0;
+    return wgs;
+}
+
+template <int KIND, int LB>
+hipError_t go_part_refine(const sbs_lhs *h, const PartChoice &c, const float *b, double *x, int64_t m, int sweeps,
+                          hipStream_t s) {
+    constexpr int MAXT = 512;
+    const PartPlan &pp = h->part[c.plan];
+    auto kern = k_part_refine<KIND, LB, MAXT>;
+    const void *fn = nullptr;
+    if (hipError_t e = refine_kernel<KIND, LB>(&fn); e != hipSuccess) return e;
     if (c.threads > MAXT) return hipErrorInvalidValue;
     const int ngroups = (int)((m + c.S - 1) / c.S);
     int cus = 256;
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, h->device);
-    const int per_cu = (int)std::max<size_t>(1, kMaxPartLdsBytes / c.lds);
+    const int per_cu = std::max(1, c.wgs);
     const int grid = std::min(ngroups, cus * per_cu);
     hipLaunchKernelGGL(kern, dim3(grid), dim3(c.threads), c.lds, s, static_cast<const unsigned char *>(pp.blob32),
                        (int)pp.fac_bytes32, (int)pp.spk_bytes32, (int)pp.rinv_bytes32, h->bands, (int)h->n, pp.P,
@@ -1486,29 +1509,43 @@ hipError_t go_part_refine(const sbs_lhs *h, const PartChoice &c, const float *b,
 // Plan for the fused mixed-precision kernel: blocks of 16 or 32 rows (the
 // lane keeps b, x and a work copy of its block in registers), at most 512
 // threads, and LDS for the FP32 plan, the original bands, the interface
-// values and the neighbour exchange.
+// values and the neighbour exchange.  Scored like the plain partition
+// (concurrent waves, up to 8 per CU), but ties go first to more workgroups
+// per CU: each group crosses several barriers, and two independent
+// workgroups hide them (1M-system tridiagonal batch: 32-row blocks with 16
+// systems per workgroup 2.77 ms, with 32 systems 3.03 ms, 16-row blocks
+// 3.54 ms).
 bool choose_partition_refine(const sbs_lhs *h, int64_t m, PartChoice *out) {
     const int H = h->kind / 2;
+    int cus = 256;
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, h->device);
     PartChoice best;
     int64_t best_waves = -1;
+    int best_wgs = 0;
     for (int q = 1; q >= 0; --q) {  // lb 32, then 16
         const PartPlan &pp = h->part[q];
         if (!pp.ok || m < 1) continue;
-        int S = 64;
-        while (S > 16 && S * pp.P > 512) S /= 2;
-        if (S * pp.P > 512) continue;
-        const size_t npad = (size_t)pp.P * pp.lb;
-        const size_t lds = pp.blob_bytes(1) + npad * sizeof(BandRow) +
-                           ((size_t)S * (pp.Nr + 1) * 4 + 15) / 16 * 16 + (size_t)S * pp.P * 2 * H * 8;
-        if (lds > kMaxPartLdsBytes) continue;
-        const int64_t groups = (m + S - 1) / S;
-        const int64_t waves = std::min<int64_t>(groups * ((S * pp.P + kWave - 1) / kWave), 4096);
-        if (waves > best_waves) {
-            best_waves = waves;
-            best.plan = q;
-            best.S = S;
-            best.threads = S * pp.P;
-            best.lds = lds;
+        for (int S = 64; S >= 16; S /= 2) {
+            const int threads = S * pp.P;
+            if (threads > 512) continue;
+            const size_t npad = (size_t)pp.P * pp.lb;
+            const size_t lds = pp.blob_bytes(1) + npad * sizeof(BandRow) +
+                               ((size_t)S * (pp.Nr + 1) * 4 + 15) / 16 * 16 + (size_t)S * pp.P * 2 * H * 8;
+            if (lds > kMaxPartLdsBytes) continue;
+            const int wgs = refine_wgs_per_cu(h->kind, pp.lb, threads, lds);
+            if (wgs < 1) continue;
+            const int64_t groups = (m + S - 1) / S;
+            const int64_t waves = std::min<int64_t>(
+                std::min<int64_t>(groups, (int64_t)cus * wgs) * ((threads + kWave - 1) / kWave), (int64_t)cus * 8);
+            if (waves > best_waves || (waves == best_waves && wgs > best_wgs)) {
+                best_waves = waves;
+                best_wgs = wgs;
+                best.plan = q;
+                best.S = S;
+                best.threads = threads;
+                best.lds = lds;
+                best.wgs = wgs;
+            }
         }
     }
     if (best.plan < 0) return false;
