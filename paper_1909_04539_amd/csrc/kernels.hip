@@ -727,6 +727,66 @@ __device__ __forceinline__ void part_interface(const T (&x)[LB], T *red, const T
     __syncthreads();  // red is rewritten next time
 }
 
+// FP64 form of the interface step on the matrix cores.  For a group of S
+// systems the interface unknowns are Z = R^{-1} Y, with Y (Nr x S) the
+// published interface values (column s at red + s * ldr): a dense product
+// that the waves share in 16 x 16 tiles of v_mfma_f64_16x16x4f64 (lane l
+// holds A[l % 16][l / 16] and B[l / 16][l % 16]; item r of the result is
+// D[4 r + l / 16][l % 16]).  Each operand is read from LDS once per tile
+// instead of once per lane and product, which is what bounds the per-lane
+// dot products.  The tiles go to zb (same layout as red), and after one
+// barrier each lane takes its 2H values.  Two barriers per group, as in the
+// per-lane form: red is not rewritten before every wave has passed the
+// second one, nor zb before the first barrier of the next group.
+template <int KIND, int LB>
+__device__ __forceinline__ void part_interface_mma(const double (&x)[LB], double *red_all, double *zb,
+                                                   const double *rinv, int s, int p, int pp, bool has_next,
+                                                   bool has_prev, int Nr, int S, int ldr, double (&xt)[KIND / 2],
+                                                   double (&xb)[KIND / 2]) {
+    typedef double D4 __attribute__((ext_vector_type(4)));
+    constexpr int H = KIND / 2;
+    double *red = red_all + s * ldr;
+    if (has_next) {
+#pragma unroll
+        for (int c = 0; c < H; ++c) red[2 * H * p + c] = x[LB - H + c];
+    }
+    if (has_prev) {
+#pragma unroll
+        for (int c = 0; c < H; ++c) red[2 * H * pp + H + c] = x[c];
+    }
+    __syncthreads();
+    // whole waves only (blockDim.x a multiple of 64, so nwaves >= 1)
+    const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave, nwaves = blockDim.x / kWave;
+    const int mt = (Nr + 15) / 16, ntiles = mt * ((S + 15) / 16);
+    const int lr = lane % 16, lk = lane / 16;
+    for (int tile = wave; tile < ntiles; tile += nwaves) {
+        const int i0 = (tile % mt) * 16, j0 = (tile / mt) * 16;
+        const int i = i0 + lr, j = j0 + lr;
+        const double *arow = rinv + (size_t)min(i, Nr - 1) * Nr;
+        const double *bcol = red_all + min(j, S - 1) * ldr;
+        D4 acc = {0.0, 0.0, 0.0, 0.0};
+        for (int k0 = 0; k0 < Nr; k0 += 4) {
+            const int k = k0 + lk, kc = min(k, Nr - 1);
+            const bool kin = k < Nr;
+            const double a = (kin && i < Nr) ? arow[kc] : 0.0;
+            const double b = (kin && j < S) ? bcol[kc] : 0.0;
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int row = i0 + 4 * r + lk;
+            if (row < Nr && j < S) zb[j * ldr + row] = acc[r];
+        }
+    }
+    __syncthreads();
+    const double *z = zb + s * ldr;
+#pragma unroll
+    for (int c = 0; c < H; ++c) {
+        xt[c] = has_next ? z[2 * H * p + H + c] : 0.0;
+        xb[c] = has_prev ? z[2 * H * pp + c] : 0.0;
+    }
+}
+
 template <int KIND, typename T>
 __device__ __forceinline__ T part_correct(T v, const T *spt, const T (&xt)[KIND / 2], const T (&xb)[KIND / 2]) {
     constexpr int H = KIND / 2;
@@ -775,7 +835,13 @@ __global__ __launch_bounds__(MAXT) void k_part(const unsigned char *__restrict__
     T *lred = reinterpret_cast<T *>(lds + blob_bytes);
     const int ldr = Nr + 1;  // odd stride: the systems' rows fall in different banks
     const int npad = P * LB;
-    unsigned char *after_red = lds + blob_bytes + (S * ldr * (int)sizeof(T) + 15) / 16 * 16;
+    // interface step on the matrix cores: FP64 pentadiagonal (4 unknowns per
+    // lane from 4 (P - 1) values); the tridiagonal step is half as wide and
+    // a quarter of the reads, and stays per lane
+    constexpr bool MMA = std::is_same<T, double>::value && KIND == SBS_PENTA;
+    const int red_bytes = (S * ldr * (int)sizeof(T) + 15) / 16 * 16;
+    T *lz = reinterpret_cast<T *>(lds + blob_bytes + red_bytes);  // MMA: the interface unknowns
+    unsigned char *after_red = lds + blob_bytes + red_bytes * (MMA ? 2 : 1);
     double *lband = reinterpret_cast<double *>(after_red);                                  // CN: [npad][NB]
     T *lend = reinterpret_cast<T *>(after_red + (npad * NB * 8 + 15) / 16 * 16);            // CN: [S][P][2H]
     if constexpr (CN) {
@@ -826,7 +892,14 @@ __global__ __launch_bounds__(MAXT) void k_part(const unsigned char *__restrict__
         typename R::Bwd bs;
         bwd_regs<KIND, T, LB>(fr, x, bs);
         T xt[H], xb[H];
-        part_interface<KIND, T, LB>(x, red, rt, rb, p, pp, has_next, has_prev, Nr, xt, xb);
+        // the matrix cores need whole waves: workgroups of fewer than 64
+        // threads (small batches) keep the per-lane dot products
+        if (MMA && blockDim.x % kWave == 0) {
+            if constexpr (MMA)
+                part_interface_mma<KIND, LB>(x, lred, lz, lrinv, s, p, pp, has_next, has_prev, Nr, S, ldr, xt, xb);
+        } else {
+            part_interface<KIND, T, LB>(x, red, rt, rb, p, pp, has_next, has_prev, Nr, xt, xb);
+        }
         Tout *dst = out + base;
         if constexpr (PAIRS && !CN) {
             if (paired) {
@@ -1593,7 +1666,9 @@ bool choose_partition(const sbs_lhs *h, int tc, int64_t m, PartChoice *out, bool
             if (S < 16 && (m + 2 * S - 1) / (2 * S) >= cus) break;  // the wider S already fills the CUs
             const int threads = S * pp.P;
             if (threads > maxt) continue;
-            size_t lds = blob + ((size_t)S * (pp.Nr + 1) * elem + 15) / 16 * 16;
+            // interface values, and for FP64 pentadiagonal the interface unknowns beside them
+            const bool mma = tc == 0 && H == 2;
+            size_t lds = blob + ((size_t)S * (pp.Nr + 1) * elem + 15) / 16 * 16 * (mma ? 2 : 1);
             if (cn)
                 lds += ((size_t)pp.P * pp.lb * (2 * H + 1) * 8 + 15) / 16 * 16 +
                        ((size_t)S * pp.P * 2 * H * elem + 15) / 16 * 16;

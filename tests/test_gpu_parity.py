@@ -48,7 +48,8 @@ def partition_available(kind, n, elem=8, m=1 << 20, cus=256):
     most 90 interface unknowns 2h(P-1), and for some S systems per workgroup
     (64, 32, 16; 8 and 4 only while a batch of m leaves CUs idle) at most
     512 (lb 64, FP64) or 1024 threads and block factors + spikes + interface
-    inverse + block map + interface values within 160 KiB of LDS."""
+    inverse + block map + interface values (and, for FP64 pentadiagonal
+    matrices, the interface unknowns beside them) within 160 KiB of LDS."""
     h = kind // 2
     row = (4 if kind == 3 else 8) * elem
     r16 = lambda v: -(-v // 16) * 16
@@ -64,7 +65,7 @@ def partition_available(kind, n, elem=8, m=1 << 20, cus=256):
                 break
             if S * P <= maxt:
                 lds = (r16(P * lb * row) + r16(P * lb * 2 * h * elem) + r16(Nr * Nr * elem) + r16(P * 4)
-                       + r16(S * (Nr + 1) * elem))
+                       + r16(S * (Nr + 1) * elem) * (2 if elem == 8 and kind == 5 else 1))
                 if lds <= 160 * 1024:
                     return True
             S //= 2
