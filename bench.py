@@ -183,7 +183,8 @@ def bench_tri256(args, torch, sbs, W):
     lhs.close()
     u = wl.n * wl.m
     return {"workload": "tri_f64_n256_m1024", "unknowns_per_s": u / dev, "us_per_solve": dev * 1e6,
-            "hbm_frac_16B": round(16 * u / dev / 1e9 / HBM_PEAK_GBS, 4), "bound": "latency (16 waves)"}
+            "hbm_frac_16B": round(16 * u / dev / 1e9 / HBM_PEAK_GBS, 4),
+            "bound": "latency: back-to-back calls from Python, about 10 us of host work each"}
 
 
 def bench_adi(args, torch, sbs, W):

@@ -800,12 +800,24 @@ __device__ __forceinline__ T part_correct(T v, const T *spt, const T (&xt)[KIND 
 // Bytes of a plan's block map (P ints, 16-byte aligned) at the end of its blob.
 __device__ __forceinline__ int map_bytes(int P) { return (P * 4 + 15) / 16 * 16; }
 
-// Copies a plan blob [fac | spk | rinv | map] into LDS.
+// Copies a plan blob [fac | spk | rinv | map] into LDS, eight 16-byte loads
+// in flight per thread: small workgroups (a few systems of a short matrix)
+// would otherwise wait for one round trip to L2 per 16 bytes.
 __device__ __forceinline__ void stage_blob(unsigned char *lds, const unsigned char *blob, int bytes) {
     typedef unsigned int U4 __attribute__((ext_vector_type(4)));
+    constexpr int U = 8;
     const U4 *src = reinterpret_cast<const U4 *>(blob);
     U4 *dst = reinterpret_cast<U4 *>(lds);
-    for (int i = threadIdx.x; i < bytes / 16; i += blockDim.x) dst[i] = src[i];
+    const int total = bytes / 16, step = blockDim.x;
+    int i = threadIdx.x;
+    for (; i + (U - 1) * step < total; i += U * step) {
+        U4 v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) v[u] = src[i + u * step];
+#pragma unroll
+        for (int u = 0; u < U; ++u) dst[i + u * step] = v[u];
+    }
+    for (; i < total; i += step) dst[i] = src[i];
 }
 
 // CN: a Crank-Nicolson step (in == out) instead of a solve: after the
@@ -1638,10 +1650,14 @@ hipError_t launch_partition_refine(const sbs_lhs *h, const PartChoice &c, const 
 }
 
 // Block length and systems per workgroup S for the partitioned solve.  The
-// score is the number of waves that run at once over the whole batch, counted
-// up to 8 per CU (enough to keep HBM busy: more buys nothing once the batch
-// fills the chip, and a 1M-system tridiagonal batch ran 16% slower on the
-// 32-row blocks that allow 16); ties go to longer blocks (fewer interfaces),
+// score is the number of lanes that run at once over the whole batch, counted
+// up to 8 full waves per CU (enough to keep HBM busy: more buys nothing once
+// the batch fills the chip, and a 1M-system tridiagonal batch ran 16% slower
+// on the 32-row blocks that allow 16).  Lanes, not waves: a workgroup of 16
+// threads fills a quarter of its wave, and for small batches the shorter
+// blocks that give each system more lanes win (1024 tridiagonal systems of
+// 256 rows: 64-row blocks with 4 systems per workgroup 13.5 us, 16-row blocks
+// 9.5 us).  Ties go to longer blocks (fewer interfaces),
 // then to larger S: each row access of a
 // block covers S consecutive systems, and wider runs stream better (measured
 // on the 1024-row pentadiagonal batch: S = 32 274 us, S = 16 299 us, both with
@@ -1656,7 +1672,7 @@ bool choose_partition(const sbs_lhs *h, int tc, int64_t m, PartChoice *out, bool
     int cus = 256;
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, h->device);
     PartChoice best;
-    int64_t best_waves = -1;
+    int64_t best_lanes = -1;
     for (int q = 2; q >= 0; --q) {  // largest block first: fewest interfaces
         const PartPlan &pp = h->part[q];
         if (!pp.ok || m < 1) continue;
@@ -1676,10 +1692,10 @@ bool choose_partition(const sbs_lhs *h, int tc, int64_t m, PartChoice *out, bool
             const int wgs = part_wgs_per_cu(h->kind, tc, pp.lb, threads, lds, cn);
             if (wgs < 1) continue;
             const int64_t groups = (m + S - 1) / S;
-            const int64_t waves = std::min<int64_t>(
-                std::min<int64_t>(groups, (int64_t)cus * wgs) * ((threads + kWave - 1) / kWave), (int64_t)cus * 8);
-            if (waves > best_waves) {
-                best_waves = waves;
+            const int64_t lanes = std::min<int64_t>(std::min<int64_t>(groups, (int64_t)cus * wgs) * threads,
+                                                    (int64_t)cus * 8 * kWave);
+            if (lanes > best_lanes) {
+                best_lanes = lanes;
                 best.plan = q;
                 best.S = S;
                 best.threads = threads;
