@@ -284,7 +284,7 @@ sbs_status sbs_adi_step(sbs_handle hy, sbs_handle hx, double *grid, double *work
     // contiguous run); otherwise through the interleaved layout of the
     // transpose.
     PartChoice pc;
-    if (choose_partition(hx, 0, ny, &pc))
+    if (choose_partition(hx, 0, ny, &pc, false, true))
         return launch_partition_rows(hx, pc, grid, ny, static_cast<hipStream_t>(stream)) == hipSuccess
                    ? SBS_OK
                    : SBS_ERR_DEVICE;

@@ -145,7 +145,8 @@ struct PartChoice {
     int wgs = 1;  // workgroups resident per CU at this size
 };
 // cn: a Crank-Nicolson step c <- A^{-1} (2I - A) c instead of a solve (in == out).
-bool choose_partition(const sbs_lhs *h, int tc, int64_t m, PartChoice *out, bool cn = false);
+// rows: the systems are rows of a row-major grid (launch_partition_rows).
+bool choose_partition(const sbs_lhs *h, int tc, int64_t m, PartChoice *out, bool cn = false, bool rows = false);
 hipError_t launch_partition(const sbs_lhs *h, const PartChoice &c, int tc, int tin, int tout, const void *in,
                             void *out, int64_t m, hipStream_t stream, bool cn = false);
 // FP64 solve of m systems stored one after another (system j at x + j*n),

@@ -1665,14 +1665,17 @@ hipError_t launch_partition_refine(const sbs_lhs *h, const PartChoice &c, const 
 // (FP64); narrower workgroups (down to 4 systems) are only tried when the
 // batch is too small to give every CU a group.
 // cn: the Crank-Nicolson form also holds the band rows (2h+1 doubles per row)
-// and the exchange of block ends in LDS.
-bool choose_partition(const sbs_lhs *h, int tc, int64_t m, PartChoice *out, bool cn) {
+// and the exchange of block ends in LDS.  rows: each lane reads its block as
+// one contiguous run, so S sets no access width; ties on lanes go first to the
+// shape that engages more CUs (2048 rows of a 2048 x 2048 grid: 8 systems per
+// workgroup on 256 CUs 29.5 us, 16 on 128 CUs 36.9 us).
+bool choose_partition(const sbs_lhs *h, int tc, int64_t m, PartChoice *out, bool cn, bool rows) {
     const size_t elem = tc == 0 ? 8 : 4;
     const int H = part_kind(h->kind) / 2;
     int cus = 256;
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, h->device);
     PartChoice best;
-    int64_t best_lanes = -1;
+    int64_t best_lanes = -1, best_cus = -1;
     for (int q = 2; q >= 0; --q) {  // largest block first: fewest interfaces
         const PartPlan &pp = h->part[q];
         if (!pp.ok || m < 1) continue;
@@ -1694,8 +1697,10 @@ bool choose_partition(const sbs_lhs *h, int tc, int64_t m, PartChoice *out, bool
             const int64_t groups = (m + S - 1) / S;
             const int64_t lanes = std::min<int64_t>(std::min<int64_t>(groups, (int64_t)cus * wgs) * threads,
                                                     (int64_t)cus * 8 * kWave);
-            if (lanes > best_lanes) {
+            const int64_t engaged = rows ? std::min<int64_t>(groups, cus) : 0;
+            if (lanes > best_lanes || (lanes == best_lanes && engaged > best_cus)) {
                 best_lanes = lanes;
+                best_cus = engaged;
                 best.plan = q;
                 best.S = S;
                 best.threads = threads;
