@@ -37,6 +37,29 @@ PeriodicRow<float> narrow(const PeriodicRow<double> &r) {
 
 int nbands(int kind) { return kind == SBS_TRI_PERIODIC ? 3 : kind; }
 
+// Whether each band holds one value wherever it lies inside the matrix (every
+// row of a periodic matrix); if so, those values.  A band with no entry inside
+// (a penta band of a 1-row matrix) counts as constant 0.
+bool constant_bands(const double *bands, int kind, int64_t n, BandCoef *c) {
+    const int nb = nbands(kind), H = nb / 2;
+    for (int k = 0; k < nb; ++k) {
+        bool have = false;
+        c->c[k] = 0.0;
+        for (int64_t i = 0; i < n; ++i) {
+            const int64_t col = i + k - H;
+            if (kind != SBS_TRI_PERIODIC && (col < 0 || col >= n)) continue;
+            const double v = bands[(int64_t)k * n + i];
+            if (!have) {
+                c->c[k] = v;
+                have = true;
+            } else if (v != c->c[k]) {
+                return false;
+            }
+        }
+    }
+    return true;
+}
+
 // Band k of row i as the matrix uses it: 0 outside a banded matrix; every
 // entry (the corners a_0 and c_{n-1} included) for a periodic one.
 double entry(const double *bands, int kind, int64_t n, int k, int64_t i) {
@@ -131,6 +154,7 @@ sbs_status sbs_factor_shared_lhs(int32_t kind, int64_t n, const double *bands, s
             if (st == SBS_OK) st = upload<PeriodicRow<double>, PeriodicRow<float>>(h, r, bands);
         }
         if (st == SBS_OK) st = build_partitions(h, bands);
+        h->constant_bands = constant_bands(bands, kind, n, &h->coef);
     } catch (const std::bad_alloc &) {
         st = SBS_ERR_NO_MEMORY;
     }
@@ -252,9 +276,10 @@ sbs_status sbs_cn_step(sbs_handle h, void *c, int64_t m, int32_t dtype, int32_t 
     const int t = dtype == SBS_F64 ? 0 : 1;
     hipStream_t s = static_cast<hipStream_t>(stream);
     PartChoice pc;
-    const bool part = choose_partition(h, t, m, &pc, true);
+    const int cn = h->constant_bands ? 2 : 1;  // constant bands: coefficients by value, no band rows in LDS
+    const bool part = choose_partition(h, t, m, &pc, cn);
     for (int k = 0; k < steps; ++k) {
-        const hipError_t e = part ? launch_partition(h, pc, t, t, t, c, c, m, s, true) : launch_cn(h, t, c, m, s);
+        const hipError_t e = part ? launch_partition(h, pc, t, t, t, c, c, m, s, cn) : launch_cn(h, t, c, m, s);
         if (e != hipSuccess) return SBS_ERR_DEVICE;
     }
     return SBS_OK;

@@ -48,6 +48,12 @@ struct alignas(64) BandRow {
     double c[8];
 };
 
+// The 2h+1 coefficients of a matrix whose bands are constant, passed to
+// kernels by value.
+struct BandCoef {
+    double c[5];
+};
+
 constexpr int kWave = 64;       // lanes per wavefront on gfx950
 constexpr int kRowPad = 64;     // factor rows are padded with zero rows to a multiple of this
                                 // (every chunk length divides it, so chunks never read past the end)
@@ -99,6 +105,10 @@ struct sbs_lhs {
     sbs::BandRow *bands = nullptr;  // BandRow[rows]
     void *pdev = nullptr;       // partition data (one allocation for all plans)
     sbs::PartPlan part[3];      // block lengths 16, 32, 64
+    // every band constant over the rows where it lies inside the matrix
+    // (every row for a periodic matrix): the coefficients themselves
+    bool constant_bands = false;
+    sbs::BandCoef coef{};
     int64_t device_bytes = 0;
     int device = 0;
 };
@@ -144,11 +154,13 @@ struct PartChoice {
     size_t lds = 0;
     int wgs = 1;  // workgroups resident per CU at this size
 };
-// cn: a Crank-Nicolson step c <- A^{-1} (2I - A) c instead of a solve (in == out).
+// cn: 0 a solve; 1 a Crank-Nicolson step c <- A^{-1} (2I - A) c (in == out)
+// with the band rows staged in LDS; 2 the same for a matrix with constant
+// bands (coefficients passed by value, nothing staged).
 // rows: the systems are rows of a row-major grid (launch_partition_rows).
-bool choose_partition(const sbs_lhs *h, int tc, int64_t m, PartChoice *out, bool cn = false, bool rows = false);
+bool choose_partition(const sbs_lhs *h, int tc, int64_t m, PartChoice *out, int cn = 0, bool rows = false);
 hipError_t launch_partition(const sbs_lhs *h, const PartChoice &c, int tc, int tin, int tout, const void *in,
-                            void *out, int64_t m, hipStream_t stream, bool cn = false);
+                            void *out, int64_t m, hipStream_t stream, int cn = 0);
 // FP64 solve of m systems stored one after another (system j at x + j*n),
 // in place, on the partition chosen for them.
 hipError_t launch_partition_rows(const sbs_lhs *h, const PartChoice &c, double *x, int64_t m, hipStream_t stream);

@@ -823,16 +823,17 @@ __device__ __forceinline__ void stage_blob(unsigned char *lds, const unsigned ch
 // CN: a Crank-Nicolson step (in == out) instead of a solve: after the
 // correction each lane holds its block of u = A^{-1} c, swaps its first and
 // last H values with the neighbouring blocks through LDS, and writes
-// 2 u - A u with the band rows (compact, NB = 2H + 1 per row, in LDS).
+// 2 u - A u with the band rows (CN 1: compact, NB = 2H + 1 per row, in LDS;
+// CN 2: constant bands, the NB coefficients in `coef`).
 // `periodic`: block 0 and block P-1 are neighbours (one more interface pair).
 // ROWS: the systems are stored one after another (system j at j*n .. j*n+n-1,
 // the rows of a row-major grid) instead of interleaved; each lane then reads
 // and writes its block as one contiguous run.
-template <int KIND, typename T, typename Tin, typename Tout, int LB, int MAXT, bool CN = false, bool ROWS = false>
+template <int KIND, typename T, typename Tin, typename Tout, int LB, int MAXT, int CN = 0, bool ROWS = false>
 __global__ __launch_bounds__(MAXT) void k_part(const unsigned char *__restrict__ blob, int fac_bytes, int spk_bytes,
                                                int rinv_bytes, int n, int P, int Nr, int S, int ngroups, int periodic,
-                                               const BandRow *__restrict__ bands, const Tin *in, Tout *out,
-                                               int64_t m) {
+                                               const BandRow *__restrict__ bands, BandCoef coef, const Tin *in,
+                                               Tout *out, int64_t m) {
     using R = Rec<KIND, T>;
     using Row = typename R::Row;
     constexpr int H = KIND / 2;
@@ -854,9 +855,9 @@ __global__ __launch_bounds__(MAXT) void k_part(const unsigned char *__restrict__
     const int red_bytes = (S * ldr * (int)sizeof(T) + 15) / 16 * 16;
     T *lz = reinterpret_cast<T *>(lds + blob_bytes + red_bytes);  // MMA: the interface unknowns
     unsigned char *after_red = lds + blob_bytes + red_bytes * (MMA ? 2 : 1);
-    double *lband = reinterpret_cast<double *>(after_red);                                  // CN: [npad][NB]
-    T *lend = reinterpret_cast<T *>(after_red + (npad * NB * 8 + 15) / 16 * 16);            // CN: [S][P][2H]
-    if constexpr (CN) {
+    double *lband = reinterpret_cast<double *>(after_red);                                  // CN 1: [npad][NB]
+    T *lend = reinterpret_cast<T *>(after_red + (CN == 1 ? (npad * NB * 8 + 15) / 16 * 16 : 0));  // CN: [S][P][2H]
+    if constexpr (CN == 1) {
         for (int i = threadIdx.x; i < npad; i += blockDim.x)
 #pragma unroll
             for (int k = 0; k < NB; ++k) lband[i * NB + k] = i < n ? bands[i].c[k] : 0.0;
@@ -959,7 +960,9 @@ __global__ __launch_bounds__(MAXT) void k_part(const unsigned char *__restrict__
 #pragma unroll
             for (int t = 0; t < LB; ++t) {
                 win[NB - 1] = t + H < LB ? corr(t + H) : rgt[t + H - LB];
-                const double *b = lband + (r0 + t) * NB;
+                // constant bands: the coefficients are kernel arguments (the
+                // values they meet outside the matrix are 0 in the window)
+                const double *b = CN == 2 ? coef.c : lband + (r0 + t) * NB;
                 T ax = T(b[0]) * win[0];
 #pragma unroll
                 for (int k = 1; k < NB; ++k) ax = fma(T(b[k]), win[k], ax);
@@ -1439,7 +1442,7 @@ constexpr int part_maxt() {
 }
 
 // The partitioned kernel of (KIND, T, LB, CN), allowed the whole LDS of a CU.
-template <int KIND, typename T, int LB, bool CN>
+template <int KIND, typename T, int LB, int CN>
 hipError_t part_kernel(const void **fn) {
     auto kern = k_part<KIND, T, T, T, LB, part_maxt<KIND, T, LB>(), CN>;
     static bool attr = false;
@@ -1453,7 +1456,7 @@ hipError_t part_kernel(const void **fn) {
     return hipSuccess;
 }
 
-template <int KIND, typename T, bool CN>
+template <int KIND, typename T, int CN>
 int part_wgs_lb(int lb, int threads, size_t lds) {
     const void *fn = nullptr;
     hipError_t e = lb == 16 ? part_kernel<KIND, T, 16, CN>(&fn)
@@ -1469,22 +1472,21 @@ int part_kind(int kind) { return kind == SBS_PENTA ? SBS_PENTA : SBS_TRI; }
 
 // Workgroups of the partitioned kernel that one CU holds at once (registers,
 // waves and LDS together).
-int part_wgs_per_cu(int kind, int tc, int lb, int threads, size_t lds, bool cn) {
-    if (part_kind(kind) == SBS_TRI) {
-        if (cn)
-            return tc == 0 ? part_wgs_lb<SBS_TRI, double, true>(lb, threads, lds)
-                           : part_wgs_lb<SBS_TRI, float, true>(lb, threads, lds);
-        return tc == 0 ? part_wgs_lb<SBS_TRI, double, false>(lb, threads, lds)
-                       : part_wgs_lb<SBS_TRI, float, false>(lb, threads, lds);
-    }
-    if (cn)
-        return tc == 0 ? part_wgs_lb<SBS_PENTA, double, true>(lb, threads, lds)
-                       : part_wgs_lb<SBS_PENTA, float, true>(lb, threads, lds);
-    return tc == 0 ? part_wgs_lb<SBS_PENTA, double, false>(lb, threads, lds)
-                   : part_wgs_lb<SBS_PENTA, float, false>(lb, threads, lds);
+template <int KIND, typename T>
+int part_wgs_cn(int cn, int lb, int threads, size_t lds) {
+    return cn == 2 ? part_wgs_lb<KIND, T, 2>(lb, threads, lds)
+                   : cn == 1 ? part_wgs_lb<KIND, T, 1>(lb, threads, lds) : part_wgs_lb<KIND, T, 0>(lb, threads, lds);
 }
 
-template <int KIND, typename T, int LB, bool CN>
+int part_wgs_per_cu(int kind, int tc, int lb, int threads, size_t lds, int cn) {
+    if (part_kind(kind) == SBS_TRI)
+        return tc == 0 ? part_wgs_cn<SBS_TRI, double>(cn, lb, threads, lds)
+                       : part_wgs_cn<SBS_TRI, float>(cn, lb, threads, lds);
+    return tc == 0 ? part_wgs_cn<SBS_PENTA, double>(cn, lb, threads, lds)
+                   : part_wgs_cn<SBS_PENTA, float>(cn, lb, threads, lds);
+}
+
+template <int KIND, typename T, int LB, int CN>
 hipError_t go_part(const sbs_lhs *h, const PartChoice &c, const void *in, void *out, int64_t m, hipStream_t s) {
     constexpr int MAXT = part_maxt<KIND, T, LB>();
     const PartPlan &pp = h->part[c.plan];
@@ -1502,7 +1504,7 @@ hipError_t go_part(const sbs_lhs *h, const PartChoice &c, const void *in, void *
                        static_cast<const unsigned char *>(f64 ? pp.blob64 : pp.blob32),
                        (int)(f64 ? pp.fac_bytes64 : pp.fac_bytes32), (int)(f64 ? pp.spk_bytes64 : pp.spk_bytes32),
                        (int)(f64 ? pp.rinv_bytes64 : pp.rinv_bytes32), (int)h->n, pp.P, pp.Nr, c.S, ngroups,
-                       (int)pp.periodic, h->bands, static_cast<const T *>(in), static_cast<T *>(out), m);
+                       (int)pp.periodic, h->bands, h->coef, static_cast<const T *>(in), static_cast<T *>(out), m);
     return hipGetLastError();
 }
 
@@ -1512,7 +1514,7 @@ template <int KIND, int LB>
 hipError_t go_part_rows(const sbs_lhs *h, const PartChoice &c, double *x, int64_t m, hipStream_t s) {
     constexpr int MAXT = part_maxt<KIND, double, LB>();
     const PartPlan &pp = h->part[c.plan];
-    auto kern = k_part<KIND, double, double, double, LB, MAXT, false, true>;
+    auto kern = k_part<KIND, double, double, double, LB, MAXT, 0, true>;
     static bool attr = false;
     if (!attr) {
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
@@ -1527,11 +1529,11 @@ hipError_t go_part_rows(const sbs_lhs *h, const PartChoice &c, double *x, int64_
     const int grid = (int)std::min<int64_t>(ngroups, (int64_t)cus * std::max(1, c.wgs));
     hipLaunchKernelGGL(kern, dim3(grid), dim3(c.threads), c.lds, s, static_cast<const unsigned char *>(pp.blob64),
                        (int)pp.fac_bytes64, (int)pp.spk_bytes64, (int)pp.rinv_bytes64, (int)h->n, pp.P, pp.Nr, c.S,
-                       ngroups, (int)pp.periodic, h->bands, x, x, m);
+                       ngroups, (int)pp.periodic, h->bands, h->coef, x, x, m);
     return hipGetLastError();
 }
 
-template <int KIND, typename T, bool CN>
+template <int KIND, typename T, int CN>
 hipError_t go_part_lb(const sbs_lhs *h, const PartChoice &c, const void *in, void *out, int64_t m, hipStream_t s) {
     switch (h->part[c.plan].lb) {
         case 16: return go_part<KIND, T, 16, CN>(h, c, in, out, m, s);
@@ -1669,7 +1671,7 @@ hipError_t launch_partition_refine(const sbs_lhs *h, const PartChoice &c, const 
 // one contiguous run, so S sets no access width; ties on lanes go first to the
 // shape that engages more CUs (2048 rows of a 2048 x 2048 grid: 8 systems per
 // workgroup on 256 CUs 29.5 us, 16 on 128 CUs 36.9 us).
-bool choose_partition(const sbs_lhs *h, int tc, int64_t m, PartChoice *out, bool cn, bool rows) {
+bool choose_partition(const sbs_lhs *h, int tc, int64_t m, PartChoice *out, int cn, bool rows) {
     const size_t elem = tc == 0 ? 8 : 4;
     const int H = part_kind(h->kind) / 2;
     int cus = 256;
@@ -1688,9 +1690,8 @@ bool choose_partition(const sbs_lhs *h, int tc, int64_t m, PartChoice *out, bool
             // interface values, and for FP64 pentadiagonal the interface unknowns beside them
             const bool mma = tc == 0 && H == 2;
             size_t lds = blob + ((size_t)S * (pp.Nr + 1) * elem + 15) / 16 * 16 * (mma ? 2 : 1);
-            if (cn)
-                lds += ((size_t)pp.P * pp.lb * (2 * H + 1) * 8 + 15) / 16 * 16 +
-                       ((size_t)S * pp.P * 2 * H * elem + 15) / 16 * 16;
+            if (cn == 1) lds += ((size_t)pp.P * pp.lb * (2 * H + 1) * 8 + 15) / 16 * 16;  // band rows
+            if (cn) lds += ((size_t)S * pp.P * 2 * H * elem + 15) / 16 * 16;              // block ends
             if (lds > kMaxPartLdsBytes) continue;
             const int wgs = part_wgs_per_cu(h->kind, tc, pp.lb, threads, lds, cn);
             if (wgs < 1) continue;
@@ -1714,22 +1715,22 @@ bool choose_partition(const sbs_lhs *h, int tc, int64_t m, PartChoice *out, bool
     return true;
 }
 
+template <int KIND, typename T>
+hipError_t go_part_cn(const sbs_lhs *h, const PartChoice &c, const void *in, void *out, int64_t m, hipStream_t s,
+                      int cn) {
+    return cn == 2 ? go_part_lb<KIND, T, 2>(h, c, in, out, m, s)
+                   : cn == 1 ? go_part_lb<KIND, T, 1>(h, c, in, out, m, s) : go_part_lb<KIND, T, 0>(h, c, in, out, m, s);
+}
+
 hipError_t launch_partition(const sbs_lhs *h, const PartChoice &c, int tc, int tin, int tout, const void *in, void *out,
-                            int64_t m, hipStream_t stream, bool cn) {
+                            int64_t m, hipStream_t stream, int cn) {
     if (m <= 0) return hipSuccess;
-    if (tc != tin || tc != tout) return hipErrorInvalidValue;
-    if (part_kind(h->kind) == SBS_TRI) {
-        if (cn)
-            return tc == 0 ? go_part_lb<SBS_TRI, double, true>(h, c, in, out, m, stream)
-                           : go_part_lb<SBS_TRI, float, true>(h, c, in, out, m, stream);
-        return tc == 0 ? go_part_lb<SBS_TRI, double, false>(h, c, in, out, m, stream)
-                       : go_part_lb<SBS_TRI, float, false>(h, c, in, out, m, stream);
-    }
-    if (cn)
-        return tc == 0 ? go_part_lb<SBS_PENTA, double, true>(h, c, in, out, m, stream)
-                       : go_part_lb<SBS_PENTA, float, true>(h, c, in, out, m, stream);
-    return tc == 0 ? go_part_lb<SBS_PENTA, double, false>(h, c, in, out, m, stream)
-                   : go_part_lb<SBS_PENTA, float, false>(h, c, in, out, m, stream);
+    if (tc != tin || tc != tout || cn < 0 || cn > 2 || (cn == 2 && !h->constant_bands)) return hipErrorInvalidValue;
+    if (part_kind(h->kind) == SBS_TRI)
+        return tc == 0 ? go_part_cn<SBS_TRI, double>(h, c, in, out, m, stream, cn)
+                       : go_part_cn<SBS_TRI, float>(h, c, in, out, m, stream, cn);
+    return tc == 0 ? go_part_cn<SBS_PENTA, double>(h, c, in, out, m, stream, cn)
+                   : go_part_cn<SBS_PENTA, float>(h, c, in, out, m, stream, cn);
 }
 
 hipError_t launch_partition_rows(const sbs_lhs *h, const PartChoice &c, double *x, int64_t m, hipStream_t stream) {

@@ -73,6 +73,25 @@ def test_cn_fp32(kind):
     assert colrel(got, oracle.cn_steps(kind, B, C.astype(np.float64), 2)) <= 1e-5
 
 
+CONSTANT = {3: [-0.3, 1.6, -0.3], 5: [0.2, -0.8, 2.2, -0.8, 0.2], 13: [-0.4, 1.8, -0.3]}
+
+
+@pytest.mark.parametrize("kind", [3, 5, 13])
+@pytest.mark.parametrize("n,m", [(64, 256), (96, 70), (512, 1000), (1024, 333)])
+@pytest.mark.parametrize("dtype,tol", [(torch.float64, 1e-12), (torch.float32, 1e-5)])
+def test_cn_constant_bands(kind, n, m, dtype, tol):
+    # Constant bands (the paper's two schemes are of this form) take the form
+    # with the coefficients passed by value.  The band array also holds values
+    # outside the matrix (a_0, c_{n-1} for a banded matrix), which both sides
+    # ignore; a periodic matrix uses them as its corners.
+    print(f"case kind={kind} n={n} m={m} dtype={dtype}", flush=True)
+    B = np.array(CONSTANT[kind])[:, None] * np.ones(n)
+    C = np.random.default_rng(n + m + kind).uniform(-1, 1, (n, m))
+    got = gpu_cn(kind, B, C.astype(np.float32) if dtype == torch.float32 else C, 2, dtype)
+    assert colrel(got, oracle.cn_steps(kind, B, C.astype(np.float32).astype(np.float64)
+                                       if dtype == torch.float32 else C, 2)) <= tol
+
+
 def test_cn_noop_and_errors():
     B = bands(3, 50, 4)
     with sbs.SharedLhs(3, B) as lhs:
