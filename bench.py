@@ -96,9 +96,16 @@ def cpu_baseline(kind, bands, rhs_sample, target_s=10.0):
         oracle.solve_inplace_mt(kind, bands, X, threads)
         t_solve += time.perf_counter() - t
     per = t_solve / 3
+    # the same sample on one thread (serial oracle, no OpenMP team)
+    X[...] = rhs_sample
+    t = time.perf_counter()
+    oracle.solve_inplace_mt(kind, bands, X, 1)
+    one = time.perf_counter() - t
     return {"value": n * m / per, "unit": "unknowns/s", "cores": threads, "kind": "oracle",
+            "value_1_thread": n * m / one,
             "sample": f"n={n}, m={m} columns of the same workload (seeded), {reps} solves over "
-                      f"{el:.1f} s, median-free mean of 3 timed solves"}
+                      f"{el:.1f} s, median-free mean of 3 timed solves; value_1_thread: one solve "
+                      f"of the same sample on 1 thread"}
 
 
 def bench_headline(args, torch, sbs, W):
