@@ -1696,8 +1696,9 @@ bool choose_partition(const sbs_lhs *h, int tc, int64_t m, PartChoice *out, int 
             const int wgs = part_wgs_per_cu(h->kind, tc, pp.lb, threads, lds, cn);
             if (wgs < 1) continue;
             const int64_t groups = (m + S - 1) / S;
-            const int64_t lanes = std::min<int64_t>(std::min<int64_t>(groups, (int64_t)cus * wgs) * threads,
-                                                    (int64_t)cus * 8 * kWave);
+            // lanes that hold a system (a last group may be partly empty)
+            const int64_t systems = std::min<int64_t>(m, std::min<int64_t>(groups, (int64_t)cus * wgs) * S);
+            const int64_t lanes = std::min<int64_t>(systems * pp.P, (int64_t)cus * 8 * kWave);
             const int64_t engaged = rows ? std::min<int64_t>(groups, cus) : 0;
             if (lanes > best_lanes || (lanes == best_lanes && engaged > best_cus)) {
                 best_lanes = lanes;

@@ -104,6 +104,20 @@ def test_fp64_matches_oracle(kind, variant, n, m):
     assert colrel(got, oracle.solve(kind, B, rhs)) <= TOL64
 
 
+@pytest.mark.parametrize("n", [900, 1000])
+def test_penta_interface_forms(n):
+    # FP64 pentadiagonal plans with 64-row blocks: 15 blocks give workgroups
+    # of 15 x 32 = 480 threads, not whole waves, so the interface unknowns
+    # come from per-lane dot products; 16 blocks give 512 threads and the
+    # matrix-core product.  Both against the oracle.
+    m = 4096
+    assert partition_available(5, n, m=m)
+    B = bands_for(5, n, 77 + n)
+    rhs = np.random.default_rng(n).uniform(-1, 1, (n, m))
+    got = gpu_solve(5, B, rhs, sbs.VARIANT_PARTITION)
+    assert colrel(got, oracle.solve(5, B, rhs)) <= TOL64
+
+
 def test_partition_plan_rule():
     # penta n = 2048 needs 31 blocks of 64 rows: 120 interface unknowns, over the limit
     assert not partition_available(5, 2048) and partition_available(5, 1024) and partition_available(3, 2048)
