@@ -192,6 +192,29 @@ def test_config1_full_size_sampled_columns():
     assert colrel(got, wl.extra["x_true"][:, cols]) <= 1e-12
 
 
+def test_full_size_random_bands_sampled_columns():
+    # the headline's size with random diagonally dominant bands: every block
+    # of the partition plan is stored (no two alike), right-hand sides drawn
+    # on the device; sampled columns (wave and group edges, the last one)
+    # against the oracle
+    n, m = 1024, 65536
+    B = bands_for(5, n, 11)
+    g = torch.Generator(device=DEV)
+    g.manual_seed(12)
+    x = torch.rand((n, m), dtype=torch.float64, device=DEV, generator=g) * 2 - 1
+    cols = np.unique(np.concatenate([[0, 31, 32, 63, 64, m - 33, m - 32, m - 1],
+                                     np.random.default_rng(3).choice(m, 200, replace=False)]))
+    idx = torch.from_numpy(cols).to(DEV)
+    rhs_cols = x[:, idx].cpu().numpy()
+    with sbs.SharedLhs(5, B) as lhs:
+        assert sbs.sbs_auto_variant(lhs.handle, m) == sbs.VARIANT_PARTITION
+        lhs.solve(x)
+        torch.cuda.synchronize()
+    got = x[:, idx].cpu().numpy()
+    del x
+    assert colrel(got, oracle.solve(5, B, rhs_cols)) <= TOL64
+
+
 def test_handle_storage_is_independent_of_batch_size():
     for kind, n in ((3, 1000), (5, 1000), (5, 3)):
         B = bands_for(kind, n, 3)
