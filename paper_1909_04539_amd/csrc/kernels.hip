@@ -1445,13 +1445,12 @@ constexpr int part_maxt() {
 template <int KIND, typename T, int LB, int CN>
 hipError_t part_kernel(const void **fn) {
     auto kern = k_part<KIND, T, T, T, LB, part_maxt<KIND, T, LB>(), CN>;
-    static bool attr = false;
-    if (!attr) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxPartLdsBytes);
-        if (e != hipSuccess) return e;
-        attr = true;
-    }
+    // once per instantiation; thread-safe static initialisation, so that
+    // concurrent first launches from several host threads do not race
+    static const hipError_t attr = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
+                                                       hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                       (int)kMaxPartLdsBytes);
+    if (attr != hipSuccess) return attr;
     *fn = reinterpret_cast<const void *>(kern);
     return hipSuccess;
 }
@@ -1515,13 +1514,12 @@ hipError_t go_part_rows(const sbs_lhs *h, const PartChoice &c, double *x, int64_
     constexpr int MAXT = part_maxt<KIND, double, LB>();
     const PartPlan &pp = h->part[c.plan];
     auto kern = k_part<KIND, double, double, double, LB, MAXT, 0, true>;
-    static bool attr = false;
-    if (!attr) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxPartLdsBytes);
-        if (e != hipSuccess) return e;
-        attr = true;
-    }
+    // once per instantiation; thread-safe static initialisation, so that
+    // concurrent first launches from several host threads do not race
+    static const hipError_t attr = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
+                                                       hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                       (int)kMaxPartLdsBytes);
+    if (attr != hipSuccess) return attr;
     if (c.threads > MAXT) return hipErrorInvalidValue;
     const int ngroups = (int)((m + c.S - 1) / c.S);
     int cus = 256;
@@ -1548,13 +1546,12 @@ namespace {
 template <int KIND, int LB>
 hipError_t refine_kernel(const void **fn) {
     auto kern = k_part_refine<KIND, LB, 512>;
-    static bool attr = false;
-    if (!attr) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxPartLdsBytes);
-        if (e != hipSuccess) return e;
-        attr = true;
-    }
+    // once per instantiation; thread-safe static initialisation, so that
+    // concurrent first launches from several host threads do not race
+    static const hipError_t attr = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
+                                                       hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                       (int)kMaxPartLdsBytes);
+    if (attr != hipSuccess) return attr;
     *fn = reinterpret_cast<const void *>(kern);
     return hipSuccess;
 }
