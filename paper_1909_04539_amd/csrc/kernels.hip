@@ -1,12 +1,16 @@
-// HIP kernels for gfx950: the per-system forward / backward sweeps, the
-// mixed-precision residual and update passes, and the tiled transpose.
+// HIP kernels for gfx950: the per-system forward / backward sweeps (resident,
+// chunked, stream; plain, periodic and Crank-Nicolson forms), the partitioned
+// solve with several lanes per system (plain, Crank-Nicolson, row layout and
+// the fused mixed-precision form), the residual and update passes of the
+// multi-pass refinement, the serving tile kernel and the tiled transpose.
 //
-// Execution model (Section 2 of the paper, re-done for CDNA4): one lane of a
-// 64-wide wavefront owns one system.  Row i of the interleaved right-hand
-// sides is contiguous across the wave's 64 systems, so each row is one
-// coalesced 512-byte (FP64) access; the shared factor row i is the same for
-// every lane and is read with wave-uniform scalar loads.  Each workgroup is
-// exactly one wavefront.
+// Execution model of the sweeps (Section 2 of the paper, re-done for CDNA4):
+// one lane of a 64-wide wavefront owns one system, and each workgroup is one
+// wavefront.  Row i of the interleaved right-hand sides is contiguous across
+// the wave's 64 systems, so each row is one coalesced 512-byte (FP64) access;
+// the shared factor row i is the same for every lane and is staged in LDS and
+// broadcast.  The partitioned kernels give each system P lanes (one block of
+// rows each) in workgroups of S systems x P blocks.
 #include <algorithm>
 #include <type_traits>
 
@@ -1649,22 +1653,25 @@ hipError_t launch_partition_refine(const sbs_lhs *h, const PartChoice &c, const 
 }
 
 // Block length and systems per workgroup S for the partitioned solve.  The
-// score is the number of lanes that run at once over the whole batch, counted
-// up to 8 full waves per CU (enough to keep HBM busy: more buys nothing once
-// the batch fills the chip, and a 1M-system tridiagonal batch ran 16% slower
-// on the 32-row blocks that allow 16).  Lanes, not waves: a workgroup of 16
-// threads fills a quarter of its wave, and for small batches the shorter
-// blocks that give each system more lanes win (1024 tridiagonal systems of
-// 256 rows: 64-row blocks with 4 systems per workgroup 13.5 us, 16-row blocks
-// 9.5 us).  Ties go to longer blocks (fewer interfaces),
-// then to larger S: each row access of a
-// block covers S consecutive systems, and wider runs stream better (measured
-// on the 1024-row pentadiagonal batch: S = 32 274 us, S = 16 299 us, both with
-// 8 waves per CU).  S >= 16 keeps every row access a whole 128-byte line
+// score is the number of lanes that run at once over the whole batch and hold
+// a system, counted up to 8 full waves per CU (enough to keep HBM busy: more
+// buys nothing once the batch fills the chip, and a 1M-system tridiagonal
+// batch ran 16% slower on the 32-row blocks that allow 16).  Lanes, not
+// waves: a workgroup of 16 threads fills a quarter of its wave, and for small
+// batches the shorter blocks that give each system more lanes win (1024
+// tridiagonal systems of 256 rows: 64-row blocks with 4 systems per workgroup
+// 13.5 us, 16-row blocks 9.5 us).  Ties go to longer blocks (fewer
+// interfaces), then to larger S: each row access of a block covers S
+// consecutive systems, and wider runs stream better (measured on the
+// 1024-row pentadiagonal batch: S = 32 274 us, S = 16 299 us, both with 8
+// waves per CU).  S >= 16 keeps every row access a whole 128-byte line
 // (FP64); narrower workgroups (down to 4 systems) are only tried when the
 // batch is too small to give every CU a group.
-// cn: the Crank-Nicolson form also holds the band rows (2h+1 doubles per row)
-// and the exchange of block ends in LDS.  rows: each lane reads its block as
+// cn: 0 a solve; 1 a Crank-Nicolson step, which also holds the band rows
+// (2h+1 doubles per row) and the exchange of block ends in LDS; 2 the same
+// step for constant bands (no band rows).  In FP64 pentadiagonal plans the
+// interface unknowns take a second array the size of the interface values
+// (the matrix-core form).  rows: each lane reads its block as
 // one contiguous run, so S sets no access width; ties on lanes go first to the
 // shape that engages more CUs (2048 rows of a 2048 x 2048 grid: 8 systems per
 // workgroup on 256 CUs 29.5 us, 16 on 128 CUs 36.9 us).
