@@ -222,11 +222,15 @@ sbs_status sbs_transpose(const void *src, void *dst, int64_t rows,
 /*
  * One alternating-direction step on a row-major FP64 grid g[y*nx + x]:
  * solve along y with hy (n == ny; the columns are already interleaved with
- * m = nx), transpose into `work`, solve along x with hx (n == nx, m = ny),
- * transpose back into g.  Either handle may be of any kind (periodic
- * handles give periodic directions).
+ * m = nx), then along x with hx (n == nx, m = ny).  The x systems are the
+ * grid's rows: when hx has a partition plan they are solved in place, each
+ * lane reading its block of a row as one contiguous run, and `work` is not
+ * touched; otherwise the grid is transposed into `work`, solved there and
+ * transposed back (the route of the paper's layout).  Either handle may be
+ * of any kind (periodic handles give periodic directions).
  *  grid  device, ny*nx doubles, overwritten.
- *  work  device scratch, ny*nx doubles (caller-owned).
+ *  work  device scratch, ny*nx doubles (caller-owned; required even when
+ *        the in-place route leaves it untouched).
  */
 sbs_status sbs_adi_step(sbs_handle hy, sbs_handle hx, double *grid,
                         double *work, int64_t ny, int64_t nx, void *stream);
