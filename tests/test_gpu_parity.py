@@ -118,6 +118,17 @@ def test_penta_interface_forms(n):
     assert colrel(got, oracle.solve(5, B, rhs)) <= TOL64
 
 
+@pytest.mark.parametrize("n", [900, 1000, 1024])
+@pytest.mark.parametrize("m", [1, 2, 3, 5])
+def test_penta_partition_tiny_batches(n, m):
+    # a workgroup of 4 systems x 15 or 16 blocks with most of its systems
+    # missing: per-lane form at 60 threads, matrix-core form at 64
+    B = bands_for(5, n, 5 * n + m)
+    rhs = np.random.default_rng(m).uniform(-1, 1, (n, m))
+    got = gpu_solve(5, B, rhs, sbs.VARIANT_PARTITION)
+    assert colrel(got, oracle.solve(5, B, rhs)) <= TOL64
+
+
 def test_partition_plan_rule():
     # penta n = 2048 needs 31 blocks of 64 rows: 120 interface unknowns, over the limit
     assert not partition_available(5, 2048) and partition_available(5, 1024) and partition_available(3, 2048)
