@@ -386,6 +386,24 @@ class _Borrowed:
         return sbs.sbs_solve_batch_variant(self.handle, rhs, variant)
 
 
+@pytest.mark.parametrize("ny,nx", [(64, 1024), (300, 1000), (130, 900), (100, 65)])
+def test_adi_step_with_pentadiagonal_rows(ny, nx):
+    # a pentadiagonal x-matrix: its row-layout partition uses the matrix-core
+    # interface step (1024 rows: 16 blocks) or the per-lane one (900: 15);
+    # against the oracle's solves along y and then along x
+    By = W.diffusion_bands(ny, 0.5)
+    Bx = bands_for(5, nx, nx + 1)
+    g = np.random.default_rng(ny * nx).uniform(-1, 1, (ny, nx))
+    with sbs.SharedLhs(3, By) as hy, sbs.SharedLhs(5, Bx) as hx:
+        G = torch.from_numpy(g.copy()).to(DEV)
+        work = torch.empty_like(G)
+        sbs.sbs_adi_step(hy.handle, hx.handle, G, work)
+        torch.cuda.synchronize()
+        got = G.cpu().numpy()
+    ref = oracle.solve(5, Bx, np.ascontiguousarray(oracle.solve(3, By, g).T)).T
+    assert colrel(got.T, ref.T) <= TOL64
+
+
 @pytest.mark.parametrize("ny,nx", [(64, 2048), (333, 1024), (1000, 96), (257, 64), (100, 65), (40, 1001)])
 def test_adi_rows_equal_the_transposed_path(ny, nx):
     # The x-direction solve reads the grid's rows in place when the x-matrix
