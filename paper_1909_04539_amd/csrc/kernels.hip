@@ -1658,23 +1658,25 @@ hipError_t launch_partition_refine(const sbs_lhs *h, const PartChoice &c, const 
 // buys nothing once the batch fills the chip, and a 1M-system tridiagonal
 // batch ran 16% slower on the 32-row blocks that allow 16).  Lanes, not
 // waves: a workgroup of 16 threads fills a quarter of its wave, and for small
-// batches the shorter blocks that give each system more lanes win (1024
-// tridiagonal systems of 256 rows: 64-row blocks with 4 systems per workgroup
-// 13.5 us, 16-row blocks 9.5 us).  Ties go to longer blocks (fewer
-// interfaces), then to larger S: each row access of a block covers S
-// consecutive systems, and wider runs stream better (measured on the
-// 1024-row pentadiagonal batch: S = 32 274 us, S = 16 299 us, both with 8
-// waves per CU).  S >= 16 keeps every row access a whole 128-byte line
-// (FP64); narrower workgroups (down to 4 systems) are only tried when the
-// batch is too small to give every CU a group.
+// batches the shorter blocks that give each system more lanes win.  Ties go,
+// in order, to row accesses that are whole 128-byte lines (S >= 16 in FP64,
+// 32 in FP32), to more CUs engaged, to longer blocks (fewer interfaces) and
+// to larger S (each row access of a block covers S consecutive systems, and
+// wider runs stream better: on the 1024-row pentadiagonal batch S = 32 274
+// us, S = 16 299 us, both with 8 waves per CU).  1024 tridiagonal systems of
+// 256 rows, replayed from a graph: 16-row blocks with S = 16 (64 CUs) 5.1
+// us, S = 8 5.5, S = 64 (16 CUs) 8.7; 64-row blocks with S = 4 13.5 us.
+// Workgroups narrower than 16 systems are only tried when the batch is too
+// small to give every CU a group.
 // cn: 0 a solve; 1 a Crank-Nicolson step, which also holds the band rows
 // (2h+1 doubles per row) and the exchange of block ends in LDS; 2 the same
 // step for constant bands (no band rows).  In FP64 pentadiagonal plans the
 // interface unknowns take a second array the size of the interface values
-// (the matrix-core form).  rows: each lane reads its block as
-// one contiguous run, so S sets no access width; ties on lanes go first to the
-// shape that engages more CUs (2048 rows of a 2048 x 2048 grid: 8 systems per
-// workgroup on 256 CUs 29.5 us, 16 on 128 CUs 36.9 us).
+// (the matrix-core form).  rows: each lane reads its block as one contiguous
+// run, so every S counts as whole lines and more CUs decide (2048 rows of a
+// 2048 x 2048 grid: 8 systems per workgroup on 256 CUs 29.5 us, 16 on 128
+// CUs 36.9 us; in the interleaved layout of its columns 16 systems, whole
+// lines, 19.9 us against 26.3 us with 8).
 bool choose_partition(const sbs_lhs *h, int tc, int64_t m, PartChoice *out, int cn, bool rows) {
     const size_t elem = tc == 0 ? 8 : 4;
     const int H = part_kind(h->kind) / 2;
@@ -1682,6 +1684,7 @@ bool choose_partition(const sbs_lhs *h, int tc, int64_t m, PartChoice *out, int 
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, h->device);
     PartChoice best;
     int64_t best_lanes = -1, best_cus = -1;
+    bool best_lines = false;
     for (int q = 2; q >= 0; --q) {  // largest block first: fewest interfaces
         const PartPlan &pp = h->part[q];
         if (!pp.ok || m < 1) continue;
@@ -1703,9 +1706,17 @@ bool choose_partition(const sbs_lhs *h, int tc, int64_t m, PartChoice *out, int 
             // lanes that hold a system (a last group may be partly empty)
             const int64_t systems = std::min<int64_t>(m, std::min<int64_t>(groups, (int64_t)cus * wgs) * S);
             const int64_t lanes = std::min<int64_t>(systems * pp.P, (int64_t)cus * 8 * kWave);
-            const int64_t engaged = rows ? std::min<int64_t>(groups, cus) : 0;
-            if (lanes > best_lanes || (lanes == best_lanes && engaged > best_cus)) {
+            // the row layout reads each block as one run whatever S is
+            const bool lines = rows || (size_t)S * elem >= 128;
+            const int64_t engaged = std::min<int64_t>(groups, cus);
+            // larger scores first; the loops visit longer blocks and then
+            // larger S first, so a full tie keeps the earlier shape
+            const bool better =
+                lanes != best_lanes ? lanes > best_lanes
+                                    : lines != best_lines ? lines : engaged > best_cus;
+            if (better) {
                 best_lanes = lanes;
+                best_lines = lines;
                 best_cus = engaged;
                 best.plan = q;
                 best.S = S;
