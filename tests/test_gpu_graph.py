@@ -1,4 +1,5 @@
-"""Solves captured in a HIP graph (torch.cuda.CUDAGraph is hipGraph on ROCm):
+"""Solves, refined solves, Crank-Nicolson and ADI steps captured in a HIP graph
+(torch.cuda.CUDAGraph is hipGraph on ROCm):
 the entry points launch kernels only (no allocation, no memset), so a caller
 can capture them.  Each graph is replayed several times with eager work and
 synchronisation between the replays, and every replay is compared bit for
@@ -43,6 +44,38 @@ def test_solve_in_a_graph(kind, n, m):
         lhs.solve(want)
         torch.cuda.synchronize()
         replays_match(lambda y: lhs.solve(y), torch.empty_like(rhs), rhs, want)
+
+
+def test_refined_solve_in_a_graph():
+    wl = W.config3(n=512, m=4096)
+    b = torch.from_numpy(wl.rhs).to(DEV)
+    with sbs.SharedLhs(3, wl.bands) as lhs:
+        work = torch.empty(sbs.sbs_refined_workspace_bytes(lhs.handle, wl.m), dtype=torch.uint8, device=DEV)
+        want = torch.empty((wl.n, wl.m), dtype=torch.float64, device=DEV)
+        lhs.solve_refined(b, sweeps=2, x=want, work=work)
+        torch.cuda.synchronize()
+        x = torch.empty_like(want)
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            lhs.solve_refined(b, sweeps=2, x=x, work=work)
+        for _ in range(3):
+            x.zero_()
+            torch.cuda.synchronize()
+            g.replay()
+            torch.cuda.synchronize()
+            assert torch.equal(x, want)
+
+
+def test_adi_step_in_a_graph():
+    ny, nx = 256, 1024
+    By, Bx = W.diffusion_bands(ny, 0.5), W.diffusion_bands(nx, 0.3)
+    g0 = torch.from_numpy(np.random.default_rng(6).uniform(-1, 1, (ny, nx))).to(DEV)
+    with sbs.SharedLhs(3, By) as hy, sbs.SharedLhs(3, Bx) as hx:
+        work = torch.empty_like(g0)
+        want = g0.clone()
+        sbs.sbs_adi_step(hy.handle, hx.handle, want, work)
+        torch.cuda.synchronize()
+        replays_match(lambda y: sbs.sbs_adi_step(hy.handle, hx.handle, y, work), torch.empty_like(g0), g0, want)
 
 
 def test_cn_step_in_a_graph():
