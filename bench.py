@@ -5,7 +5,8 @@ second for the pentadiagonal FP64 workload -- n = 1024 unknowns, m = 65536
 systems sharing one matrix (1-D hyperdiffusion Crank--Nicolson step, s = 0.5)
 -- one in-place solve per step, inputs resident in HBM.  Beside it: the
 roofline of the kernel that runs it (algorithmic 16 B per unknown against 8 TB/s),
-the oracle timed on the host cores, and the other workloads (tridiagonal
+the oracle timed on the host cores, and the other workloads (pentadiagonal
+systems beyond the partition limit, tridiagonal
 n=256 batch, 2-D ADI step, mixed-precision refinement, serving).
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--only headline]
@@ -151,6 +152,28 @@ def bench_penta_general(args, torch, sbs, W):
     u = n * m
     return {"workload": "penta_f64_n1024_m65536_random_bands", "variant": {v: k for k, v in VARIANTS.items()}[ran],
             "unknowns_per_s": u / dev, "us_per_solve": dev * 1e6, "hbm_frac_16B": round(16 * u / dev / 1e9 / HBM_PEAK_GBS, 4)}
+
+
+def bench_penta_large(args, torch, sbs, W):
+    """Pentadiagonal systems too long for a partition plan (2048 rows, random
+    diagonally dominant bands): the chunked sweep, 24 B per unknown moved, of
+    16 B algorithmic."""
+    n, m = 2048, 65536
+    rng = np.random.default_rng(21)
+    B = rng.uniform(-1, 1, (5, n))
+    B[2] = np.sum(np.abs(np.delete(B, 2, axis=0)), axis=0) + rng.uniform(1, 2, n)
+    B = W.zero_outside(B)
+    g = torch.Generator(device="cuda:0")
+    g.manual_seed(22)
+    rhs = torch.rand((n, m), dtype=torch.float64, device="cuda:0", generator=g)
+    lhs = sbs.SharedLhs(5, B)
+    ran = sbs.sbs_auto_variant(lhs.handle, m)
+    wall, dev = timed_steps(lambda: lhs.solve(rhs), 10, 2, torch)
+    lhs.close()
+    u = n * m
+    return {"workload": "penta_f64_n2048_m65536_random_bands", "variant": {v: k for k, v in VARIANTS.items()}[ran],
+            "unknowns_per_s": u / dev, "us_per_solve": dev * 1e6,
+            "hbm_frac_16B": round(16 * u / dev / 1e9 / HBM_PEAK_GBS, 4)}
 
 
 def bench_periodic_and_cn(args, torch, sbs, W):
@@ -421,7 +444,7 @@ def main():
         return
     if args.only != "headline":
         for name, fn in (("penta_general", bench_penta_general), ("periodic_and_cn", bench_periodic_and_cn),
-                         ("tri_n256_m1024", bench_tri256),
+                         ("penta_n2048_m65536", bench_penta_large), ("tri_n256_m1024", bench_tri256),
                          ("adi_2048", bench_adi), ("refined_n512_m1M", bench_refined), ("serving", bench_serving)):
             log(f"workload {name}")
             try:

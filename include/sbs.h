@@ -163,7 +163,7 @@ sbs_status sbs_solve_batch_variant(sbs_handle h, void *rhs, int64_t m,
 
 /* The variant SBS_VARIANT_AUTO runs for m systems of this dtype: the
  * partitioned variant when a plan exists and fits, otherwise resident
- * (n <= 64), chunked (checkpoints fit 64 KiB of LDS) or stream.  Host only,
+ * (n <= 64), chunked (checkpoints fit 160 KiB of LDS) or stream.  Host only,
  * no device work.  Errors: SBS_ERR_INVALID_ARG (NULL handle or output,
  * m < 1, dtype). */
 sbs_status sbs_auto_variant(sbs_handle h, int64_t m, int32_t dtype,

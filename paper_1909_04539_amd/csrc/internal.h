@@ -144,7 +144,7 @@ hipError_t launch_cn(const sbs_lhs *h, int tc, void *c, int64_t m, hipStream_t s
 // needs (tc: 0 = f64, 1 = f32).
 int choose_variant(const sbs_lhs *h, int tc);
 size_t chunked_lds_bytes(const sbs_lhs *h, int tc);
-constexpr size_t kMaxLdsBytes = 64 * 1024;        // LDS budget of the chunked variant (one wave)
+constexpr size_t kMaxLdsBytes = 160 * 1024;       // LDS budget of the chunked variant (one wave)
 constexpr size_t kMaxPartLdsBytes = 160 * 1024;   // LDS one workgroup may allocate on gfx950
 
 // Partitioned solve (SBS_VARIANT_PARTITION): choose a plan and systems per

@@ -1324,6 +1324,19 @@ hipError_t go(const sbs_lhs *h, const void *fac, const void *in, void *out, int6
     const int64_t blocks = (m + kWave - 1) / kWave;
     const size_t lds = wave_lds_bytes<KIND, T, L, MODE>((int)((h->n + L - 1) / L));
     if (lds > kMaxLdsBytes) return hipErrorInvalidValue;
+    // One wave may take up to the whole LDS of a CU: long systems keep their
+    // chunk checkpoints on chip (24 bytes per unknown) instead of streaming
+    // (32), at one or two waves per CU (pentadiagonal, 65536 systems: 2048
+    // rows 671 us against 847 us, 3000 rows 1093 us against 1283 us).  Set
+    // once per kernel (thread-safe static initialisation).
+    static const hipError_t attr_small = hipFuncSetAttribute(
+        reinterpret_cast<const void *>(k_sweep<KIND, T, Tin, Tout, L, MODE, false>),
+        hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxLdsBytes);
+    static const hipError_t attr_big = hipFuncSetAttribute(
+        reinterpret_cast<const void *>(k_sweep<KIND, T, Tin, Tout, L, MODE, true>),
+        hipFuncAttributeMaxDynamicSharedMemorySize, (int)kMaxLdsBytes);
+    if (attr_small != hipSuccess) return attr_small;
+    if (attr_big != hipSuccess) return attr_big;
     // Row offsets inside a chunk must fit the 31-bit buffer offset, with room
     // for the lane offset; wider batches take one buffer resource per row.
     const int64_t span = (int64_t)L * m * (int64_t)(sizeof(Tin) > sizeof(Tout) ? sizeof(Tin) : sizeof(Tout));
@@ -1361,6 +1374,14 @@ hipError_t go_cn(const sbs_lhs *h, const void *fac, void *c, int64_t m, hipStrea
     const int64_t blocks = (m + kWave - 1) / kWave;
     const size_t lds = wave_lds_bytes<KIND, T, L, MODE, true>((int)((h->n + L - 1) / L));
     if (lds > kMaxLdsBytes) return hipErrorInvalidValue;
+    static const hipError_t attr_small = hipFuncSetAttribute(
+        reinterpret_cast<const void *>(k_cn<KIND, T, L, MODE, false>), hipFuncAttributeMaxDynamicSharedMemorySize,
+        (int)kMaxLdsBytes);
+    static const hipError_t attr_big = hipFuncSetAttribute(
+        reinterpret_cast<const void *>(k_cn<KIND, T, L, MODE, true>), hipFuncAttributeMaxDynamicSharedMemorySize,
+        (int)kMaxLdsBytes);
+    if (attr_small != hipSuccess) return attr_small;
+    if (attr_big != hipSuccess) return attr_big;
     // the output pass stores up to two rows past the chunk
     const int64_t span = (int64_t)(L + 2) * m * (int64_t)sizeof(T);
     const auto *f = reinterpret_cast<const typename R::Row *>(fac);

@@ -35,11 +35,11 @@ def bands_for(kind, n, seed):
 
 def chunked_fits(kind, n, elem=8):
     """The chunked variant keeps per-chunk checkpoints plus two factor chunks
-    in one workgroup's LDS, at most 64 KiB."""
+    in one workgroup's LDS, at most 160 KiB (the whole LDS of a CU)."""
     K = (n + 31) // 32
     S = 1 if kind == 3 else 2
     row = (4 if kind == 3 else 8) * elem
-    return K * S * 64 * elem + 2 * 32 * row <= 64 * 1024
+    return K * S * 64 * elem + 2 * 32 * row <= 160 * 1024
 
 
 def partition_available(kind, n, elem=8, m=1 << 20, cus=256):

@@ -34,7 +34,7 @@ def ring_bands(n, seed, margin=(1.0, 2.0)):
 def chunked_fits(n, elem=8):
     # checkpoints (one value per 32-row chunk per lane) + two factor chunks of 32 rows
     row = 8 * elem
-    return ((n + 31) // 32) * 64 * elem + 2 * 32 * row <= 64 * 1024
+    return ((n + 31) // 32) * 64 * elem + 2 * 32 * row <= 160 * 1024
 
 
 def partition_available(n):
