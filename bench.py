@@ -309,15 +309,63 @@ class _Server:
         self.L.sbs_server_destroy(self.p)
 
 
+def serving_cpu_oracle(lhss, trace, pool64_host, offs, loads, budget_s):
+    """The oracle serving the same requests on the host cores, one request
+    at a time in arrival order (FIFO): each request's service time is
+    measured (the C oracle, OpenMP over column blocks; FP32 requests are
+    solved in FP64 from their promoted values, the reference of the mixed
+    precision form), on the longest prefix of the trace that fits in
+    `budget_s` seconds of service.  Arrivals keep the trace's shape, rescaled
+    to each offered load of the host's own saturation rate, and latencies
+    (arrival to completion, queueing included) follow from the measured
+    service times: completion_k = max(arrival_k, completion_{k-1}) + S_k."""
+    import oracle
+    threads = oracle.max_threads()
+    serv = []
+    unknowns = 0.0
+    t_all = time.perf_counter()
+    for k, r in enumerate(trace):
+        L = lhss[r.lhs]
+        X = pool64_host[offs[k]:offs[k] + L.n * r.m].reshape(L.n, r.m)
+        X = (X.astype(np.float32).astype(np.float64) if r.fp32 else X.copy())
+        t = time.perf_counter()
+        oracle.solve_inplace_mt(L.kind, L.bands, X, threads)
+        serv.append(time.perf_counter() - t)
+        unknowns += L.n * r.m
+        if time.perf_counter() - t_all >= budget_s:
+            break
+    S = np.array(serv)
+    count = len(S)
+    lam_sat = count / S.sum()
+    gaps = np.array([r.t_arrival for r in trace[:count]])          # unit-rate Poisson arrivals
+    out = {"requests": count, "cores": threads, "saturation_req_per_s": lam_sat,
+           "unknowns_per_s_at_saturation": unknowns / S.sum(), "loads": {}}
+    for rho in loads:
+        arr = gaps / (rho * lam_sat)
+        done = 0.0
+        lat = np.empty(count)
+        for k in range(count):
+            done = max(arr[k], done) + S[k]
+            lat[k] = done - arr[k]
+        out["loads"][str(rho)] = {"p50_us": float(np.percentile(lat, 50) * 1e6),
+                                  "p99_us": float(np.percentile(lat, 99) * 1e6)}
+    return out
+
+
 def bench_serving(args, torch, sbs, W):
-    """Serving form: 64 shared matrices (n log-uniform 64..8192), requests with
-    m log-uniform 1..4096, FP32 or FP64.  Right-hand sides are read-only
-    slices of a resident random pool (inputs pre-staged, untimed).  First a
-    closed-loop run gives the saturation rate, then Poisson arrivals at 0.8 of
-    it; the same arrivals are replayed through a plain FP64 FIFO (one
-    sbs_solve_batch per request, no coalescing) for comparison."""
+    """Serving form: 64 shared matrices (half tridiagonal, half
+    pentadiagonal, n log-uniform 64..8192), 1e5 requests with m
+    log-uniform 1..4096, FP32 or FP64, HBM budget 200 GB.  Right-hand sides
+    are read-only slices of a resident random pool (inputs pre-staged,
+    untimed).  A closed-loop run gives the saturation rate; then Poisson
+    arrivals at 0.5, 0.8 and 0.95 of it, each reporting p50 / p99 latency
+    (submit to completion, queueing included) and throughput.  The 0.8
+    arrivals are replayed through a plain FP64 FIFO (one sbs_solve_batch per
+    request, no coalescing), and the oracle serves the same requests on the
+    host cores."""
     import threading
     count = args.serve_requests
+    loads = (0.5, 0.8, 0.95)
     lhss = W.serving_lhs_set()
     hs = [sbs.SharedLhs(l.kind, l.bands) for l in lhss]
     pool_elems = 1 << 28
@@ -340,13 +388,13 @@ def bench_serving(args, torch, sbs, W):
     unknowns = float(sum(lhss[r.lhs].n * r.m for r in trace))
     torch.cuda.synchronize()
 
-    def run(arrivals):
-        tickets = [None] * count
-        lat = [0.0] * count
+    def run(arrivals, reqs=count):
+        tickets = [None] * reqs
+        lat = [0.0] * reqs
         done = threading.Event()
 
         def waiter():
-            for k in range(count):
+            for k in range(reqs):
                 while tickets[k] is None:
                     time.sleep(0)
                 st, l = srv.wait_release(tickets[k])
@@ -356,25 +404,34 @@ def bench_serving(args, torch, sbs, W):
         th = threading.Thread(target=waiter)
         th.start()
         t0 = time.perf_counter()
-        for k, r in enumerate(trace):
+        for k in range(reqs):
             if arrivals is not None:
                 while time.perf_counter() - t0 < arrivals[k]:
                     pass
-            tickets[k] = srv.submit(ids[r.lhs], ptr[k], r.m, dt[k])
+            tickets[k] = srv.submit(ids[trace[k].lhs], ptr[k], trace[k].m, dt[k])
         done.wait()
         th.join()
         return time.perf_counter() - t0, np.array(lat)
 
-    run(None)                                   # warm-up pass
-    make, lat_closed = run(None)
+    pct = lambda a, q: float(np.percentile(a, q))
+    run(None, min(count, 20000))                # warm-up pass
+    make, _ = run(None)
     lam_sat = count / make
     base_gaps = np.array([r.t_arrival for r in trace])       # arrivals of a unit-rate Poisson process
-    arrivals = base_gaps / (0.8 * lam_sat)
-    span, lat = run(arrivals)
-    s = srv.stats(sbs)
+    res = {"workload": f"serving_64lhs_{count}req", "requests": count, "unknowns": unknowns,
+           "saturation_req_per_s": lam_sat, "saturation_unknowns_per_s": unknowns / make, "loads": {}}
+    launches0 = srv.stats(sbs).launches
+    for rho in loads:
+        log(f"  serving at {rho} of saturation")
+        span, lat = run(base_gaps / (rho * lam_sat))
+        res["loads"][str(rho)] = {"offered_req_per_s": rho * lam_sat, "p50_us": pct(lat, 50), "p99_us": pct(lat, 99),
+                                  "max_us": float(lat.max()), "unknowns_per_s": unknowns / span}
+    res["launches_per_run"] = (srv.stats(sbs).launches - launches0) / len(loads)
     srv.close()
 
-    # Plain FP64 FIFO on the same arrivals: one solve per request, in order.
+    # Plain FP64 FIFO on the 0.8 arrivals: one solve per request, in order.
+    log("  plain FP64 FIFO at 0.8")
+    arrivals = base_gaps / (0.8 * lam_sat)
     stream = torch.cuda.current_stream()
     lat_f = np.zeros(count)
     t0 = time.perf_counter()
@@ -387,31 +444,98 @@ def bench_serving(args, torch, sbs, W):
         stream.synchronize()
         lat_f[k] = (time.perf_counter() - t0 - arrivals[k]) * 1e6
     fifo_span = time.perf_counter() - t0
+    res["fifo_f64_at_0.8"] = {"p50_us": pct(lat_f, 50), "p99_us": pct(lat_f, 99),
+                              "unknowns_per_s": unknowns / fifo_span}
     for h in hs:
         h.close()
-    pct = lambda a, q: float(np.percentile(a, q))
-    return {"workload": f"serving_64lhs_{count}req_rho0.8", "requests": count, "unknowns": unknowns,
-            "saturation_req_per_s": lam_sat, "saturation_unknowns_per_s": unknowns / make,
-            "offered_req_per_s": 0.8 * lam_sat, "launches": int(s.launches),
-            "p50_us": pct(lat, 50), "p99_us": pct(lat, 99), "max_us": float(lat.max()),
-            "unknowns_per_s": unknowns / span,
-            "fifo_f64_p50_us": pct(lat_f, 50), "fifo_f64_p99_us": pct(lat_f, 99),
-            "fifo_f64_unknowns_per_s": unknowns / fifo_span,
-            "note": "latency = submit to completion incl. queueing; rhs device-resident; FIFO baseline solves "
-                    "every request in FP64 on one stream without coalescing"}
+    log("  oracle serving on the host")
+    res["cpu_oracle"] = serving_cpu_oracle(lhss, trace, pool64.cpu().numpy(), offs, loads, args.cpu_seconds)
+    del pool32, pool64
+    res["note"] = ("latency = submit to completion incl. queueing; rhs device-resident; FP32 requests get the "
+                   "mixed-precision solve with 2 corrections (FP64 result); the FIFO baseline solves every "
+                   "request in FP64 on one stream without coalescing; cpu_oracle: the oracle on the host cores, "
+                   "FIFO, on a prefix of the same trace at the same loads of its own saturation rate")
+    return res
 
 
-def copy_probe(args):
-    """Plain device copy of 1 GiB (torch's copy kernel): the practical HBM
-    ceiling, and the calibration run for the FETCH_SIZE / WRITE_SIZE counters
-    (it reads 1 GiB and writes 1 GiB per launch)."""
-    import torch
+def _event_median(launch, reps, warm, torch, restore=None):
+    """Median (and min) device time of `launch` over `reps` runs, each
+    bracketed by its own pair of HIP events on the current stream; all runs
+    are queued back to back (the host is far ahead of the device), so the
+    events measure the kernel alone.  `restore`, if given, runs untimed
+    before every run (e.g. the pristine right-hand side copied back)."""
+    s = torch.cuda.current_stream()
+    for _ in range(warm):
+        if restore:
+            restore()
+        launch()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    for e0, e1 in ev:
+        if restore:
+            restore()
+        e0.record(s)
+        launch()
+        e1.record(s)
+    torch.cuda.synchronize()
+    t = sorted(e0.elapsed_time(e1) * 1e-3 for e0, e1 in ev)
+    return t[len(t) // 2], t[0]
+
+
+def stream_ceiling(torch, sbs, reps=20):
+    """The hand-written streaming probes (libsbs, include/sbs_probe.h):
+    a linear copy of 1 GiB (best of the unroll / occupancy settings tried),
+    read-only and write-only sweeps, and the partitioned solve's own access
+    pattern on the headline's (1024, 65536) FP64 array with no arithmetic.
+    Returns (records, best copy GB/s of read + write)."""
+    import ctypes
+    L = sbs.lib()
+    st = torch.cuda.current_stream().cuda_stream
     nbytes = 1 << 30
     a = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda:0").uniform_()
     b = torch.empty_like(a)
-    wall, dev = timed_steps(lambda: b.copy_(a), args.steps, args.warmup, torch)
-    print(json.dumps({"probe": "copy", "bytes_read": nbytes, "bytes_written": nbytes, "ms": dev * 1e3,
-                      "GBps_read_plus_write": 2 * nbytes / dev / 1e9}), flush=True)
+    out = []
+
+    def lin(mode, unroll, wgs):
+        def go():
+            r = L.sbs_probe_linear(mode, a.data_ptr(), b.data_ptr(), nbytes, unroll, wgs, st)
+            assert r == 0, r
+        med, mn = _event_median(go, reps, 3, torch)
+        moved = nbytes * (2 if mode == 0 else 1)
+        return {"probe": ["copy", "read", "write"][mode], "unroll": unroll, "wg_per_cu": wgs,
+                "us_median": med * 1e6, "GBps": moved / med / 1e9, "GBps_best": moved / mn / 1e9}
+
+    for unroll in (1, 2, 4, 8):
+        for wgs in (2, 4, 8):
+            out.append(lin(0, unroll, wgs))
+    best = max((r for r in out if r["probe"] == "copy"), key=lambda r: r["GBps"])
+    out.append(lin(1, best["unroll"], best["wg_per_cu"]))
+    out.append(lin(2, best["unroll"], best["wg_per_cu"]))
+    med, mn = _event_median(lambda: b.copy_(a), reps, 3, torch)
+    out.append({"probe": "torch_copy_", "us_median": med * 1e6, "GBps": 2 * nbytes / med / 1e9})
+    del a, b
+    # the partitioned solve's access pattern: (lb, vec, S, workgroups per CU)
+    n, m = 1024, 65536
+    x = torch.empty((n, m), dtype=torch.float64, device="cuda:0").uniform_()
+    for lb, vec, S, wgs in ((64, 1, 32, 1), (64, 1, 16, 2), (64, 2, 32, 1), (64, 2, 32, 2), (32, 1, 32, 1),
+                            (32, 2, 32, 1), (32, 2, 32, 2), (32, 1, 16, 2), (16, 2, 32, 1), (16, 1, 16, 1),
+                            (16, 2, 16, 2)):
+        def go():
+            r = L.sbs_probe_blocks(x.data_ptr(), n, m, lb, vec, S, wgs, st)
+            assert r == 0, (lb, vec, S, wgs, r)
+        med, mn = _event_median(go, reps, 3, torch)
+        out.append({"probe": "solve_pattern", "n": n, "m": m, "lb": lb, "vec": vec, "S": S, "wg_per_cu": wgs,
+                    "us_median": med * 1e6, "GBps": 16 * n * m / med / 1e9, "GBps_best": 16 * n * m / mn / 1e9})
+    del x
+    return out, best["GBps"]
+
+
+def copy_probe(args):
+    """Streaming probes: each record on its own JSON line."""
+    import torch
+    from paper_1909_04539_amd import sbs
+    recs, _ = stream_ceiling(torch, sbs)
+    for r in recs:
+        print(json.dumps(r), flush=True)
 
 
 def main():
@@ -422,7 +546,7 @@ def main():
     ap.add_argument("--variant", default="auto", choices=list(VARIANTS))
     ap.add_argument("--only", default="", help="'headline' skips the other workloads")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
-    ap.add_argument("--serve-requests", type=int, default=20000)
+    ap.add_argument("--serve-requests", type=int, default=100000)
     ap.add_argument("--probe", default="", choices=["", "copy"], help="run a calibration probe instead")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:

@@ -81,7 +81,7 @@ const char *sbs_version(void);
  * delta, epsilon).  The paper performs this step on the CPU (Section 2).
  *
  *  kind     SBS_TRI, SBS_PENTA or SBS_TRI_PERIODIC.
- *  n        number of unknowns per system, n >= 1 (n >= 3 for
+ *  n        number of unknowns per system, 1 <= n <= INT32_MAX (n >= 3 for
  *           SBS_TRI_PERIODIC).
  *  bands    host, kind*n doubles, band-major and row-aligned: band k, entry i
  *           is the coefficient in row i.  Tridiagonal row i reads
@@ -113,8 +113,8 @@ const char *sbs_version(void);
  * There is no pivoting (the paper has none): a zero or non-finite pivot is
  * reported as SBS_ERR_ZERO_PIVOT.  Diagonally dominant and symmetric
  * positive definite matrices never produce one.
- * Errors: SBS_ERR_INVALID_ARG (kind, n < 1 or periodic n < 3, NULL
- *         bands/out),
+ * Errors: SBS_ERR_INVALID_ARG (kind, n < 1, n > INT32_MAX or periodic
+ *         n < 3, NULL bands/out),
  *         SBS_ERR_NONFINITE, SBS_ERR_ZERO_PIVOT, SBS_ERR_NO_MEMORY,
  *         SBS_ERR_DEVICE.
  */
@@ -123,7 +123,8 @@ sbs_status sbs_factor_shared_lhs(int32_t kind, int64_t n, const double *bands,
 
 /*
  * As sbs_factor_shared_lhs for a matrix with constant bands (the uniform
- * variant of Section 4.2): coeffs holds one value per band, in band order
+ * variant described at the close of Section 4.1 and measured in Section
+ * 4.3): coeffs holds one value per band, in band order
  * (tri a, b, c; penta a, b, c, d, e).  The ends are truncated as for banded
  * kinds; SBS_TRI_PERIODIC wraps round.  The result is the handle the general
  * call gives for the expanded bands (same solutions bit for bit); with

@@ -1,5 +1,6 @@
 // C-ABI entry points: argument checking, the host-side FP64 factorisation of
 // the shared matrix, its upload, and dispatch to the HIP kernels.
+#include <climits>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
@@ -125,7 +126,8 @@ sbs_status sbs_factor_shared_lhs(int32_t kind, int64_t n, const double *bands, s
     if (out) *out = nullptr;
     if (!out || !bands || n < 1 || (kind != SBS_TRI && kind != SBS_PENTA && kind != SBS_TRI_PERIODIC))
         return SBS_ERR_INVALID_ARG;
-    if (n > (int64_t(1) << 40) || (kind == SBS_TRI_PERIODIC && n < 3)) return SBS_ERR_INVALID_ARG;
+    // the kernels index rows with 32-bit integers
+    if (n > (int64_t)INT32_MAX || (kind == SBS_TRI_PERIODIC && n < 3)) return SBS_ERR_INVALID_ARG;
     for (int64_t i = 0; i < n; ++i)
         for (int k = 0; k < nbands(kind); ++k)
             if (!std::isfinite(entry(bands, kind, n, k, i))) {
@@ -170,7 +172,7 @@ sbs_status sbs_factor_shared_lhs(int32_t kind, int64_t n, const double *bands, s
 sbs_status sbs_factor_uniform(int32_t kind, int64_t n, const double *coeffs, sbs_handle *out, int64_t *bad_row) {
     if (bad_row) *bad_row = -1;
     if (out) *out = nullptr;
-    if (!out || !coeffs || n < 1 || n > (int64_t(1) << 40)) return SBS_ERR_INVALID_ARG;
+    if (!out || !coeffs || n < 1 || n > (int64_t)INT32_MAX) return SBS_ERR_INVALID_ARG;
     if (kind != SBS_TRI && kind != SBS_PENTA && kind != SBS_TRI_PERIODIC) return SBS_ERR_INVALID_ARG;
     const int nb = nbands(kind);
     std::vector<double> bands;

@@ -10,8 +10,9 @@
 
 namespace sbs {
 
-// Factor rows, one per matrix row, laid out so that a wave reads a whole row
-// with one wave-uniform scalar load (32 B tri / 64 B penta in FP64).
+// Factor rows, one per matrix row (32 B tri / 64 B penta in FP64).  The
+// sweeps stage chunks of them through LDS and broadcast each row to the
+// wave; the partitioned kernels copy a plan's rows into LDS once.
 //
 // Tridiagonal (Section 3.1): with den_i = b_i - a_i chat_{i-1},
 //   forward   y_i = d_i / den_i - (a_i / den_i) y_{i-1}

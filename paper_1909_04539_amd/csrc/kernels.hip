@@ -1086,20 +1086,55 @@ __global__ __launch_bounds__(MAXT) void k_part_refine(const unsigned char *__res
 }
 
 // ---------------------------------------------------------------------------
-// Mixed-precision passes.  Lane per system again; a lane walks its column
-// with a window of 2H+1 solution values (H = 1 tri, 2 penta).
+// Mixed-precision passes.  Lane per system again; a wave walks its 64
+// columns in chunks of RL rows, with the next chunk's loads (x, delta, b and
+// the band rows, staged through LDS) in flight while the current chunk is
+// computed.
 //  MODE 0: r_i = fl32(b_i - (A x)_i)
 //  MODE 1: x_i += delta_i for every row, then r from the updated x
 // (A x)_i is summed left to right over the row's coefficients, in FP64.
+constexpr int kResRows = 16;  // RL: rows per residual chunk
+constexpr size_t kResLds = 2 * kResRows * sizeof(BandRow);  // band rows of two chunks
+
+// One residual chunk's inputs: x and delta of rows r0 .. r0+RL+H-1 (the
+// last H rows are the next chunk's first, re-read from cache: row i's
+// residual needs x_{i+H}), b of rows r0 .. r0+RL-1.  Rows at or beyond n read
+// as 0.
+template <int H, int MODE>
+struct ResChunk {
+    static constexpr int RL = kResRows;
+    double x[RL + H];
+    float d[RL + H], b[RL];
+    __device__ __forceinline__ void load(const char *px, const char *pd, const char *pb, uint32_t l8, uint32_t l4,
+                                         int r0, int n, int64_t rs8, int64_t rs4) {
+#pragma unroll
+        for (int t = 0; t < RL + H; ++t) {
+            const bool in = r0 + t < n;
+            x[t] = in ? ld<double>(px + (int64_t)(r0 + t) * rs8, l8) : 0.0;
+            if constexpr (MODE == 1) d[t] = in ? ld<float>(pd + (int64_t)(r0 + t) * rs4, l4) : 0.0f;
+            if (t < RL) b[t] = in ? ld<float>(pb + (int64_t)(r0 + t) * rs4, l4) : 0.0f;
+        }
+    }
+};
+
 template <int KIND, int MODE>
-__device__ __forceinline__ void residual_wave(const BandRow *__restrict__ bands, int64_t n,
+__device__ __forceinline__ void residual_wave(const BandRow *__restrict__ bands, int64_t n64,
                                               const float *__restrict__ b, double *__restrict__ x,
-                                              const float *dl, float *r, int64_t m, int64_t j0) {
-    // dl and r may be the same buffer: delta_i is read (when row i enters the
-    // window) before the residual of row i, which depends on it, is written.
-    constexpr int H = KIND / 2;
-    constexpr int U = 8;  // rows per load batch
+                                              const float *dl, float *r, int64_t m, int64_t j0,
+                                              unsigned char *lds) {
+    // dl and r may be the same buffer: a chunk's delta values are loaded
+    // before any residual of that chunk is stored, and the H rows past the
+    // chunk are loaded with the next chunk, before its residuals are stored.
+    constexpr int H = KIND / 2, RL = kResRows, CBB = RL * (int)sizeof(BandRow);
     const int lane = threadIdx.x;
+    bands = uni(bands);
+    b = uni(b);
+    x = uni(x);
+    dl = uni(dl);
+    r = uni(r);
+    m = (int64_t)uni64((uint64_t)m);
+    j0 = (int64_t)uni64((uint64_t)j0);
+    const int n = __builtin_amdgcn_readfirstlane((int)n64);
     const int jl = (j0 + lane < m) ? lane : (int)(m - 1 - j0);
     const uint32_t l4 = (uint32_t)jl * 4, l8 = (uint32_t)jl * 8;
     const char *pb = reinterpret_cast<const char *>(b + j0);
@@ -1107,61 +1142,52 @@ __device__ __forceinline__ void residual_wave(const BandRow *__restrict__ bands,
     const char *pd = reinterpret_cast<const char *>(dl + j0);
     char *pr = reinterpret_cast<char *>(r + j0);
     const int64_t rs4 = m * 4, rs8 = m * 8;
+    const int K = (n + RL - 1) / RL;
+    auto brow = [&](int k) { return reinterpret_cast<const BandRow *>(lds + (k & 1) * CBB); };
+    FacRegs<CBB> bv;  // band rows of a chunk on their way to LDS
 
-    // w[0..2H] holds x_{i-H} .. x_{i+H} (updated when MODE == 1), 0 outside.
-    double w[2 * H + 1];
+    // x_{r0-H} .. x_{r0-1} (updated), 0 above the matrix
+    double prev[H];
 #pragma unroll
-    for (int q = 0; q < 2 * H + 1; ++q) w[q] = 0.0;
+    for (int q = 0; q < H; ++q) prev[q] = 0.0;
+    ResChunk<H, MODE> cur, nxt;
+    bv.load(bands, lane);
+    cur.load(px, pd, pb, l8, l4, 0, n, rs8, rs4);
+    bv.stage(lds, lane);
+    if (K > 1) bv.load(bands + RL, lane);
+    for (int k = 0; k < K; ++k) {
+        const int r0 = k * RL;
+        const bool more = k + 1 < K;
+        if (more) nxt.load(px, pd, pb, l8, l4, r0 + RL, n, rs8, rs4);
+        // the chunk's x (and the H rows after it), updated by delta
+        double xs[RL + H];
 #pragma unroll
-    for (int q = 0; q < H; ++q) {  // rows 0 .. H-1 enter the window
-        double v = 0.0;
-        if (q < n) {
-            v = ld<double>(px + q * rs8, l8);
-            if constexpr (MODE == 1) {
-                v += (double)ld<float>(pd + q * rs4, l4);
-                st<double>(px + q * rs8, l8, v);
-            }
+        for (int t = 0; t < RL + H; ++t) {
+            xs[t] = cur.x[t];
+            if constexpr (MODE == 1) xs[t] += (double)cur.d[t];
         }
-        w[H + 1 + q] = v;  // shifted into place before row 0 is summed
-    }
-    for (int64_t i0 = 0; i0 < n; i0 += U) {
-        double xa[U];
-        float bv[U], dv[U];
-        const char *qx = px + (i0 + H) * rs8;
-        const char *qd = pd + (i0 + H) * rs4;
-        const char *qb = pb + i0 * rs4;
+        if constexpr (MODE == 1) {
 #pragma unroll
-        for (int t = 0; t < U; ++t) {
-            const bool in_a = i0 + t + H < n;  // row entering the window exists
-            xa[t] = in_a ? ld<double>(qx, l8) : 0.0;
-            if constexpr (MODE == 1) dv[t] = in_a ? ld<float>(qd, l4) : 0.0f;
-            bv[t] = (i0 + t < n) ? ld<float>(qb, l4) : 0.0f;
-            qx += rs8;
-            qd += rs4;
-            qb += rs4;
+            for (int t = 0; t < RL; ++t)
+                if (r0 + t < n) st<double>(px + (int64_t)(r0 + t) * rs8, l8, xs[t]);
         }
-        char *sx = px + (i0 + H) * rs8;
-        char *sr = pr + i0 * rs4;
+        const BandRow *br = brow(k);
 #pragma unroll
-        for (int t = 0; t < U; ++t) {
-            const int64_t i = i0 + t;
-            double v = xa[t];
-            if constexpr (MODE == 1) {
-                v += (double)dv[t];
-                if (i + H < n) st<double>(sx, l8, v);
-            }
+        for (int t = 0; t < RL; ++t) {
+            // window x_{i-H} .. x_{i+H} of row i = r0 + t
+            auto xw = [&](int q) -> double { return t + q - H < 0 ? prev[t + q] : xs[t + q - H]; };
+            double ax = br[t].c[0] * xw(0);
 #pragma unroll
-            for (int q = 0; q < 2 * H; ++q) w[q] = w[q + 1];
-            w[2 * H] = v;
-            if (i < n) {
-                const BandRow &row = bands[i];
-                double ax = row.c[0] * w[0];
+            for (int q = 1; q < 2 * H + 1; ++q) ax = fma(br[t].c[q], xw(q), ax);
+            if (r0 + t < n) st<float>(pr + (int64_t)(r0 + t) * rs4, l4, (float)((double)cur.b[t] - ax));
+            if (t % kGroup == kGroup - 1) pin(ax);
+        }
 #pragma unroll
-                for (int q = 1; q < 2 * H + 1; ++q) ax = fma(row.c[q], w[q], ax);
-                st<float>(sr, l4, (float)((double)bv[t] - ax));
-            }
-            sx += rs8;
-            sr += rs4;
+        for (int q = 0; q < H; ++q) prev[q] = xs[RL - H + q];
+        if (more) {
+            bv.stage(lds + ((k + 1) & 1) * CBB, lane);  // chunk k+1's band rows, loaded one chunk ago
+            if (k + 2 < K) bv.load(bands + (k + 2) * RL, lane);
+            cur = nxt;
         }
     }
 }
@@ -1170,22 +1196,49 @@ template <int KIND, int MODE>
 __global__ __launch_bounds__(kWave) void k_residual(const BandRow *__restrict__ bands, int64_t n,
                                                     const float *__restrict__ b, double *__restrict__ x,
                                                     const float *dl, float *r, int64_t m) {
-    residual_wave<KIND, MODE>(bands, n, b, x, dl, r, m, (int64_t)blockIdx.x * kWave);
+    __shared__ __align__(16) unsigned char lds[kResLds];
+    residual_wave<KIND, MODE>(bands, n, b, x, dl, r, m, (int64_t)blockIdx.x * kWave, lds);
 }
 
-// x += delta over one wave's 64 systems (final correction inside a tile).
-__device__ __forceinline__ void update_wave(double *x, const float *dl, int64_t n, int64_t m, int64_t j0) {
+// x += delta over one wave's 64 systems (final correction inside a tile),
+// U rows per batch with the next batch's loads in flight.
+__device__ __forceinline__ void update_wave(double *x, const float *dl, int64_t n64, int64_t m, int64_t j0) {
+    constexpr int U = 16;
     const int lane = threadIdx.x;
+    x = uni(x);
+    dl = uni(dl);
+    m = (int64_t)uni64((uint64_t)m);
+    j0 = (int64_t)uni64((uint64_t)j0);
+    const int n = __builtin_amdgcn_readfirstlane((int)n64);
     const int jl = (j0 + lane < m) ? lane : (int)(m - 1 - j0);
     char *px = reinterpret_cast<char *>(x + j0);
     const char *pd = reinterpret_cast<const char *>(dl + j0);
     const uint32_t l4 = (uint32_t)jl * 4, l8 = (uint32_t)jl * 8;
     const int64_t rs4 = m * 4, rs8 = m * 8;
-    for (int64_t i = 0; i < n; ++i) {
-        const double v = ld<double>(px, l8) + (double)ld<float>(pd, l4);
-        st<double>(px, l8, v);
-        px += rs8;
-        pd += rs4;
+    double xc[U], xn[U];
+    float dc[U], dn[U];
+    auto load = [&](double (&xb)[U], float (&db)[U], int r0) {
+#pragma unroll
+        for (int t = 0; t < U; ++t) {
+            const bool in = r0 + t < n;
+            xb[t] = in ? ld<double>(px + (int64_t)(r0 + t) * rs8, l8) : 0.0;
+            db[t] = in ? ld<float>(pd + (int64_t)(r0 + t) * rs4, l4) : 0.0f;
+        }
+    };
+    load(xc, dc, 0);
+    for (int r0 = 0; r0 < n; r0 += U) {
+        const bool more = r0 + U < n;
+        if (more) load(xn, dn, r0 + U);
+#pragma unroll
+        for (int t = 0; t < U; ++t)
+            if (r0 + t < n) st<double>(px + (int64_t)(r0 + t) * rs8, l8, xc[t] + (double)dc[t]);
+        if (more) {
+#pragma unroll
+            for (int t = 0; t < U; ++t) {
+                xc[t] = xn[t];
+                dc[t] = dn[t];
+            }
+        }
     }
 }
 
@@ -1234,18 +1287,18 @@ __device__ __forceinline__ void run_tile_f64(const Tile &t, unsigned char *lds) 
         sweep_wave<KIND, double, double, double, 32, MODE_STREAM>(fac, n, in, t.x, t.m, t.col0, lds);
 }
 
-// The phases of an FP32 tile are kept out of line so that each gets its own
-// register allocation instead of one allocation spanning all five.
+// The phases of an FP32 tile (solve, two residual / correction rounds, the
+// final update) run one after another on the tile's 64 systems.
 template <int KIND, typename Tout, int MODE>
-__device__ __noinline__ void tile_sweep_f32(const typename Rec<KIND, float>::Row *fac, int n, const float *in,
+__device__ __forceinline__ void tile_sweep_f32(const typename Rec<KIND, float>::Row *fac, int n, const float *in,
                                             Tout *out, int64_t m, int64_t j0, unsigned char *lds) {
     sweep_wave<KIND, float, float, Tout, 32, MODE>(fac, n, in, out, m, j0, lds);
 }
 
 template <int KIND, int MODE>
-__device__ __noinline__ void tile_residual(const BandRow *bands, int64_t n, const float *b, double *x,
-                                           float *r, int64_t m, int64_t j0) {
-    residual_wave<KIND, MODE>(bands, n, b, x, r, r, m, j0);
+__device__ __forceinline__ void tile_residual(const BandRow *bands, int64_t n, const float *b, double *x,
+                                           float *r, int64_t m, int64_t j0, unsigned char *lds) {
+    residual_wave<KIND, MODE>(bands, n, b, x, r, r, m, j0, lds);
 }
 
 template <int KIND>
@@ -1261,9 +1314,9 @@ __device__ __forceinline__ void run_tile_f32(const Tile &t, unsigned char *lds) 
         tile_sweep_f32<KIND, double, MODE_STREAM>(fac, n, b, t.x, t.m, t.col0, lds);
     for (int pass = 0; pass < 2; ++pass) {
         if (pass == 0)
-            tile_residual<KIND, 0>(t.bands, n, b, t.x, t.scratch, t.m, t.col0);
+            tile_residual<KIND, 0>(t.bands, n, b, t.x, t.scratch, t.m, t.col0, lds);
         else
-            tile_residual<KIND, 1>(t.bands, n, b, t.x, t.scratch, t.m, t.col0);
+            tile_residual<KIND, 1>(t.bands, n, b, t.x, t.scratch, t.m, t.col0, lds);
         if (chunk)
             tile_sweep_f32<KIND, float, MODE_CHUNKED>(fac, n, t.scratch, t.scratch, t.m, t.col0, lds);
         else
@@ -1277,8 +1330,10 @@ template <int KIND, int FP32>
 __global__ __launch_bounds__(kWave) void k_tiles(const Tile *__restrict__ tiles, int ntiles, int *counter) {
     __shared__ __align__(16) unsigned char lds[kTileLds];
     for (;;) {
-        int t = 0;
-        if (threadIdx.x == 0) t = atomicAdd(counter, 1);
+        // Every lane issues the fetch (lane 0 adds 1, the others 0) and the
+        // wave takes lane 0's ticket: no lane-dependent branch in the loop,
+        // so no lane can reach the next fetch on a path of its own.
+        int t = atomicAdd(counter, threadIdx.x == 0 ? 1 : 0);
         t = __builtin_amdgcn_readfirstlane(t);
         if (t >= ntiles) break;
         const Tile tl = tiles[t];

@@ -62,6 +62,114 @@ struct HostPlan {
     std::vector<int> map;            // block p -> stored block map[p]
 };
 
+// Accuracy gate of a plan.  The partition reaches the same solution as the
+// sweeps in exact arithmetic, but it rounds differently: through the block
+// pivots and the interface inverse.  A block whose own pivots are tiny, or an
+// ill-conditioned matrix whose interface system amplifies rounding, can move
+// the partitioned result far from the recurrences of Sections 3.1 / 4.1 even
+// when every pivot is nonzero.  So the plan is run on the host, in FP64, on a
+// few seeded right-hand sides and compared with the sweep recurrences on the
+// whole matrix; a plan whose result differs by more than kPlanTolerance
+// (relative, per column, infinity norm) is dropped and the sweeps serve that
+// matrix.
+constexpr double kPlanTolerance = 1e-13;
+constexpr int kPlanChecks = 4;  // seeded right-hand sides
+
+// Reference: the whole matrix through its factor rows, the recurrences the
+// sweep kernels run.  Periodic matrices (Section 3.3): y = A'^{-1} d, then
+// x = y - (wt.d) z.
+void reference_solve(int kind, bool periodic, int64_t n, const double *bands, std::vector<double> &x) {
+    auto cf = [&](int k, int64_t i) -> double {
+        if (periodic) return bands[(int64_t)k * n + i];
+        const int64_t col = i + k - kind / 2;
+        return (col < 0 || col >= n) ? 0.0 : bands[(int64_t)k * n + i];
+    };
+    int64_t bad = -1;
+    if (periodic) {
+        std::vector<PeriodicRow<double>> r(n);
+        std::vector<TriRow<double>> t(n);
+        if (!factor_periodic_rows(n, cf, r.data(), &bad)) return;
+        double acc = 0.0;
+        for (int64_t i = 0; i < n; ++i) {
+            t[i] = {r[i].a_s, r[i].chat, r[i].inv, 0.0};
+            acc += r[i].wt * x[i];
+        }
+        solve_tri_rows(n, t.data(), x.data());
+        for (int64_t i = 0; i < n; ++i) x[i] -= acc * r[i].z;
+    } else if (kind == SBS_TRI) {
+        std::vector<TriRow<double>> r(n);
+        if (factor_tri_rows(n, cf, r.data(), &bad)) solve_tri_rows(n, r.data(), x.data());
+    } else {
+        std::vector<PentaRow<double>> r(n);
+        if (factor_penta_rows(n, cf, r.data(), &bad)) solve_penta_rows(n, r.data(), x.data());
+    }
+}
+
+// The plan's own solve of one column, as the kernel runs it: block solves,
+// interface unknowns from the stored inverse, correction.
+template <typename Row, typename SolveFn>
+void plan_solve(const HostPlan &hp, int h, bool periodic, int64_t n, SolveFn solve, std::vector<double> &x) {
+    const int lb = hp.lb, P = hp.P, Nr = hp.Nr;
+    const Row *fac = reinterpret_cast<const Row *>(hp.fac.data());
+    std::vector<double> g((size_t)P * lb, 0.0), y(Nr > 0 ? Nr : 1, 0.0);
+    for (int64_t i = 0; i < n; ++i) g[i] = x[i];
+    for (int p = 0; p < P; ++p) solve(lb, fac + (int64_t)hp.map[p] * lb, g.data() + (int64_t)p * lb);
+    auto has_next = [&](int p) { return periodic || p <= P - 2; };
+    auto has_prev = [&](int p) { return periodic || p >= 1; };
+    auto prev = [&](int p) { return p == 0 ? P - 1 : p - 1; };
+    for (int p = 0; p < P; ++p) {
+        if (has_next(p))
+            for (int c = 0; c < h; ++c) y[2 * h * p + c] = g[(int64_t)p * lb + lb - h + c];
+        if (has_prev(p))
+            for (int c = 0; c < h; ++c) y[2 * h * prev(p) + h + c] = g[(int64_t)p * lb + c];
+    }
+    for (int p = 0; p < P; ++p) {
+        double xt[2] = {0.0, 0.0}, xb[2] = {0.0, 0.0};
+        for (int c = 0; c < h; ++c)
+            for (int k = 0; k < Nr; ++k) {
+                if (has_next(p)) xt[c] += hp.rinv[(size_t)(2 * h * p + h + c) * Nr + k] * y[k];
+                if (has_prev(p)) xb[c] += hp.rinv[(size_t)(2 * h * prev(p) + c) * Nr + k] * y[k];
+            }
+        const double *sp = hp.spk.data() + (size_t)hp.map[p] * lb * 2 * h;
+        for (int t = 0; t < lb; ++t) {
+            const int64_t i = (int64_t)p * lb + t;
+            if (i >= n) break;
+            double v = g[i];
+            for (int c = 0; c < h; ++c) v -= sp[t * 2 * h + c] * xt[c];
+            for (int c = 0; c < h; ++c) v -= sp[t * 2 * h + h + c] * xb[c];
+            x[i] = v;
+        }
+    }
+}
+
+template <typename Row, typename SolveFn>
+double plan_deviation(const HostPlan &hp, int kind, bool periodic, int64_t n, const double *bands, SolveFn solve) {
+    const int h = kind / 2;
+    uint64_t st = 0x9e3779b97f4a7c15ull;  // xorshift64, fixed seed
+    double worst = 0.0;
+    std::vector<double> d(n), a, b;
+    for (int q = 0; q < kPlanChecks; ++q) {
+        for (int64_t i = 0; i < n; ++i) {
+            st ^= st << 13;
+            st ^= st >> 7;
+            st ^= st << 17;
+            d[i] = (double)(st >> 11) * 0x1.0p-52 - 1.0;  // U[-1, 1)
+        }
+        a = d;
+        b = d;
+        reference_solve(kind, periodic, n, bands, a);
+        plan_solve<Row>(hp, h, periodic, n, solve, b);
+        double num = 0.0, den = 0.0;
+        for (int64_t i = 0; i < n; ++i) {
+            num = std::max(num, std::fabs(b[i] - a[i]));
+            den = std::max(den, std::fabs(a[i]));
+        }
+        const double e = den > 0.0 ? num / den : num;
+        if (!(e <= worst)) worst = e;  // a NaN stays
+    }
+    return worst;
+}
+
 // kind is 3 or 5 (the bandwidth); `periodic` wraps a tridiagonal matrix
 // round (row 0 couples to row n-1 and back), which needs n to be a whole
 // number of blocks: then block 0's left neighbour is block P-1 and block
@@ -174,7 +282,8 @@ bool build_plan(int kind, bool periodic, int64_t n, const double *bands, int lb,
         }
     }
     hp.rinv.swap(R);
-    return true;
+    const double dev = plan_deviation<Row>(hp, kind, periodic, n, bands, solve);
+    return dev <= kPlanTolerance;
 }
 
 template <typename Row32, typename Row64>

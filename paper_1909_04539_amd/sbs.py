@@ -20,7 +20,7 @@ import torch  # loads the HIP runtime first, so the library binds to the same on
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libsbs.so")
-HEADER = os.path.join(os.path.dirname(HERE), "include", "sbs.h")
+INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 
 SBS_TRI, SBS_PENTA, SBS_TRI_PERIODIC = 3, 5, 13
 SBS_F64, SBS_F32 = 0, 1
@@ -88,6 +88,8 @@ def lib() -> ctypes.CDLL:
         "sbs_server_fetch": ([vp, ctypes.c_uint64, vp, vp], i32),
         "sbs_server_stats_get": ([vp, P(ServerStats)], i32),
         "sbs_server_destroy": ([vp], i32),
+        "sbs_probe_linear": ([i32, vp, vp, i64, i32, i32, vp], i32),
+        "sbs_probe_blocks": ([vp, i64, i64, i32, i32, i32, i32, vp], i32),
     }
     for name, (args, res) in sig.items():
         fn = getattr(L, name)  # AttributeError if the library lacks a declared entry point
@@ -98,9 +100,13 @@ def lib() -> ctypes.CDLL:
 
 
 def declared_symbols() -> list[str]:
-    """Every function name declared in include/sbs.h."""
-    text = open(HEADER).read()
-    return sorted(set(re.findall(r"^\s*(?:const\s+)?[\w\s\*]+?\b(sbs_\w+)\s*\(", text, re.M)))
+    """Every function name declared in the headers under include/."""
+    names = set()
+    for f in sorted(os.listdir(INCLUDE)):
+        if f.endswith(".h"):
+            text = open(os.path.join(INCLUDE, f)).read()
+            names.update(re.findall(r"^\s*(?:const\s+)?[\w\s\*]+?\b(sbs_\w+)\s*\(", text, re.M))
+    return sorted(names)
 
 
 def _check(st: int, what: str, bad_row: int = -1) -> None:

@@ -147,3 +147,33 @@ def test_uniform_factor_errors_without_device(L):
     assert st == 2 and h is None and bad == 0
     st, h, bad = fac(13, 16, [-1.0, 2.0, -1.0])          # periodic Laplacian: singular
     assert st == 2 and h is None and bad == 16
+
+
+def test_factor_rejects_n_beyond_32_bit_rows(L):
+    # The kernels index rows with 32-bit integers: n > INT32_MAX is an
+    # argument error, reported before the bands are read (the 3-entry arrays
+    # passed here would be far too short for such n).
+    big = 2 ** 31
+    for kind in (3, 5, 13):
+        coeffs = np.ones(3 if kind != 5 else 5)
+        st, h, bad = _factor(L, kind, big, coeffs)
+        assert (st, h, bad) == (1, None, -1)
+        h2 = ctypes.c_void_p(9)
+        c = np.ascontiguousarray(coeffs)
+        assert L.sbs_factor_uniform(kind, big, c.ctypes.data, ctypes.byref(h2), None) == 1
+        assert h2.value is None
+
+
+def test_probe_argument_checks(L):
+    # the measurement probes reject shapes whose accesses would leave the array
+    buf = ctypes.create_string_buffer(4096 + 16)
+    p = (ctypes.addressof(buf) + 15) // 16 * 16
+    assert L.sbs_probe_linear(3, p, p, 4096, 4, 1, None) == 1       # mode
+    assert L.sbs_probe_linear(0, p, p, 4000 + 8, 4, 1, None) == 1   # not a multiple of 16
+    assert L.sbs_probe_linear(0, p, p, 4096, 3, 1, None) == 1       # unroll
+    assert L.sbs_probe_linear(0, None, p, 4096, 4, 1, None) == 1
+    assert L.sbs_probe_blocks(p, 100, 64, 64, 1, 32, 1, None) == 1   # n not whole blocks
+    assert L.sbs_probe_blocks(p, 128, 100, 64, 1, 32, 1, None) == 1  # m not whole groups
+    assert L.sbs_probe_blocks(p, 1024, 64, 16, 1, 32, 1, None) == 1  # 2048 threads
+    assert L.sbs_probe_blocks(p, 128, 64, 64, 2, 33, 1, None) == 1   # S not whole pairs
+    assert L.sbs_probe_blocks(None, 128, 64, 64, 1, 32, 1, None) == 1

@@ -426,3 +426,29 @@ def test_adi_rows_equal_the_transposed_path(ny, nx):
         assert torch.equal(G, R)
         ref = oracle.adi_step(By, Bx, g)
         assert colrel(G.cpu().numpy(), ref) <= TOL64
+
+
+@pytest.mark.parametrize("n", [1024, 2048])
+def test_auto_on_the_ill_conditioned_laplacian(n):
+    # T = tridiag(-1, 2, -1), condition number ~ 4e5 (n = 1024) and 1.7e6
+    # (n = 2048): whatever variant AUTO picks stays within the bar.
+    B = W.zero_outside(np.stack([-np.ones(n), np.full(n, 2.0), -np.ones(n)]))
+    rhs = np.random.default_rng(n).uniform(-1, 1, (n, 300))
+    got = gpu_solve(3, B, rhs)
+    assert colrel(got, oracle.solve(3, B, rhs)) <= TOL64
+
+
+@pytest.mark.parametrize("n", [256, 1000, 2048])
+def test_auto_with_tiny_block_pivots(n):
+    # a = c = 1, b = 3 but b = 1e-12 at the start of every 16-row block after
+    # the first: well conditioned, global pivots of order one, but every
+    # block of a partition plan starts with a 1e-12 pivot.  The plans are
+    # dropped at factor time and AUTO runs the sweeps.
+    B = np.stack([np.ones(n), np.full(n, 3.0), np.ones(n)])
+    B[1, 16::16] = 1e-12
+    B = W.zero_outside(B)
+    rhs = np.random.default_rng(n + 1).uniform(-1, 1, (n, 257))
+    with sbs.SharedLhs(3, B) as lhs:
+        assert sbs.sbs_auto_variant(lhs.handle, 257) != sbs.VARIANT_PARTITION
+    got = gpu_solve(3, B, rhs)
+    assert colrel(got, oracle.solve(3, B, rhs)) <= TOL64

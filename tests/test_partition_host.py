@@ -135,3 +135,37 @@ def test_constant_periodic_bands_store_one_block(exe, tmp_path):
     assert plans
     for lb, P, D, Nr, x in plans:
         assert D == 1 and colrel(x, ref) <= 1e-13
+
+
+def tiny_block_pivot_bands(n):
+    """a = c = 1, b = 3 except b = 1e-12 at every row that starts a 16-row
+    block after the first: the global recurrence's pivots stay of order one
+    (den_i = b_i - chat_{i-1} ~ -0.38 there), but each block's own first
+    pivot is 1e-12, so a partition plan built on those blocks loses about
+    twelve digits."""
+    B = np.stack([np.ones(n), np.full(n, 3.0), np.ones(n)])
+    B[1, 16::16] = 1e-12
+    return W.zero_outside(B)
+
+
+@pytest.mark.parametrize("n", [256, 1000, 2048])
+def test_plans_with_tiny_block_pivots_are_dropped(exe, tmp_path, n):
+    B = tiny_block_pivot_bands(n)
+    rhs = np.random.default_rng(n).uniform(-1, 1, (n, 2))
+    plans = run(exe, tmp_path, 3, B, rhs)
+    assert all(lb == 0 for lb, *_ in plans), [p[:4] for p in plans]
+
+
+@pytest.mark.parametrize("n", [1024, 2048])
+def test_ill_conditioned_plans_stay_within_the_parity_bar(exe, tmp_path, n):
+    # T = tridiag(-1, 2, -1): condition number ~ 4(n+1)^2 / pi^2 (4e5 at
+    # n = 1024, 1.7e6 at 2048).  A plan is kept only if its result stays
+    # within 1e-13 of the recurrences on the whole matrix; any plan that
+    # survives is within the 1e-12 bar of the oracle.
+    B = np.stack([-np.ones(n), np.full(n, 2.0), -np.ones(n)])
+    B = W.zero_outside(B)
+    rhs = np.random.default_rng(3).uniform(-1, 1, (n, 4))
+    ref = oracle.solve(3, B, rhs)
+    for lb, P, D, Nr, x in run(exe, tmp_path, 3, B, rhs):
+        if lb:
+            assert colrel(x, ref) <= 1e-12, (lb, colrel(x, ref))
