@@ -196,6 +196,35 @@ sbs_status sbs_solve_batch_refined(sbs_handle h, const float *b, double *x,
 size_t sbs_refined_workspace_bytes(sbs_handle h, int64_t m);
 
 /*
+ * sbs_solve_batch_refined without any device allocation, for callers that
+ * cannot allocate (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same arguments, kernels and results as
+ * sbs_solve_batch_refined, except that the FP32 residual scratch is a
+ * library-owned device array of sbs_refined_static_scratch_bytes() bytes
+ * (64 MiB) per GPU, held from the library's load until the process ends.
+ * Its device address is looked up on the first call on each device (that
+ * device must be current); the call itself allocates nothing.
+ *  - Systems that the fused kernel serves (a partition plan exists) use no
+ *    scratch and have no size limit.
+ *  - Otherwise sbs_refined_workspace_bytes(h, m) must not exceed the array:
+ *    larger requests return SBS_ERR_INVALID_ARG before any work is queued.
+ *  - Every call on one GPU shares that GPU's array.  Calls that overlap on
+ *    one GPU (different streams or host threads without ordering between
+ *    them) race on it and give wrong results; calls queued on one stream are
+ *    ordered and safe.  The array keeps the last call's contents; each call
+ *    writes all of the scratch it reads before reading it.
+ * Errors: as sbs_solve_batch_refined, plus SBS_ERR_INVALID_ARG for a
+ *         request beyond the scratch size and SBS_ERR_DEVICE if the array's
+ *         address cannot be found.
+ */
+sbs_status sbs_solve_batch_refined_noalloc(sbs_handle h, const float *b,
+                                           double *x, int64_t m,
+                                           int32_t sweeps, void *stream);
+
+/* Bytes of the library's static scratch array (per GPU). */
+size_t sbs_refined_static_scratch_bytes(void);
+
+/*
  * Crank-Nicolson time steps in place (Sections 3.2 and 4.2): `steps` times
  *   A c' = (2I - A) c,
  * the scheme of both benchmark problems (the explicit half of diffusion,

@@ -99,6 +99,44 @@ bool aligned(const void *p, size_t a) { return (reinterpret_cast<uintptr_t>(p) %
 
 }  // namespace
 
+namespace sbs {
+
+sbs_status refined_check(const sbs_lhs *h, const float *b, const double *x, int64_t m, int32_t sweeps) {
+    if (!h || m < 0 || sweeps < 0 || sweeps > 8 || h->kind == SBS_TRI_PERIODIC) return SBS_ERR_INVALID_ARG;
+    if (m == 0) return SBS_OK;
+    if (!b || !x || !aligned(b, 8) || !aligned(x, 16)) return SBS_ERR_INVALID_ARG;
+    const size_t nb = (size_t)h->n * (size_t)m;
+    const char *bx = reinterpret_cast<const char *>(x), *bbp = reinterpret_cast<const char *>(b);
+    if (bx < bbp + nb * 4 && bbp < bx + nb * 8) return SBS_ERR_INVALID_ARG;  // b and x overlap
+    return SBS_OK;
+}
+
+bool refined_fused(const sbs_lhs *h, int64_t m) {
+    PartChoice pc;
+    return choose_partition_refine(h, m, &pc);
+}
+
+sbs_status refined_run(const sbs_lhs *h, const float *b, double *x, int64_t m, int32_t sweeps, float *r,
+                       hipStream_t s) {
+    // Fused path: one kernel keeps each block of b and x on chip through all
+    // passes (needs a partition plan); r is not touched.
+    PartChoice pc;
+    if (choose_partition_refine(h, m, &pc))
+        return launch_partition_refine(h, pc, b, x, m, sweeps, s) == hipSuccess ? SBS_OK : SBS_ERR_DEVICE;
+    // x0 = FP32 solve of b, written as FP64.  r is written in full by the
+    // first residual pass before anything reads it.
+    hipError_t e = launch_sweep(h, SBS_VARIANT_AUTO, 1, 1, 0, b, x, m, s);
+    for (int k = 0; k < sweeps && e == hipSuccess; ++k) {
+        // r = fl32(b - A x)   (on later passes fused with x += delta)
+        e = launch_refine_step(h, k == 0 ? 0 : 1, b, x, r, r, m, s);
+        if (e == hipSuccess) e = launch_sweep(h, SBS_VARIANT_AUTO, 1, 1, 1, r, r, m, s);  // delta
+    }
+    if (e == hipSuccess && sweeps > 0) e = launch_refine_step(h, 2, b, x, r, nullptr, m, s);  // x += delta
+    return e == hipSuccess ? SBS_OK : SBS_ERR_DEVICE;
+}
+
+}  // namespace sbs
+
 extern "C" {
 
 const char *sbs_status_str(sbs_status s) {
@@ -245,29 +283,10 @@ size_t sbs_refined_workspace_bytes(sbs_handle h, int64_t m) {
 
 sbs_status sbs_solve_batch_refined(sbs_handle h, const float *b, double *x, int64_t m, int32_t sweeps, void *work,
                                    size_t work_bytes, void *stream) {
-    if (!h || m < 0 || sweeps < 0 || sweeps > 8 || h->kind == SBS_TRI_PERIODIC) return SBS_ERR_INVALID_ARG;
-    if (m == 0) return SBS_OK;
-    if (!b || !x || !work || work_bytes < sbs_refined_workspace_bytes(h, m)) return SBS_ERR_INVALID_ARG;
-    if (!aligned(b, 8) || !aligned(x, 16) || !aligned(work, 8)) return SBS_ERR_INVALID_ARG;
-    const size_t nb = (size_t)h->n * (size_t)m;
-    const char *bx = reinterpret_cast<const char *>(x), *bbp = reinterpret_cast<const char *>(b);
-    if (bx < bbp + nb * 4 && bbp < bx + nb * 8) return SBS_ERR_INVALID_ARG;  // b and x overlap
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    // Fused path: one kernel keeps each block of b and x on chip through all
-    // passes (needs a partition plan).
-    PartChoice pc;
-    if (choose_partition_refine(h, m, &pc))
-        return launch_partition_refine(h, pc, b, x, m, sweeps, s) == hipSuccess ? SBS_OK : SBS_ERR_DEVICE;
-    float *r = static_cast<float *>(work);
-    // x0 = FP32 solve of b, written as FP64.
-    hipError_t e = launch_sweep(h, SBS_VARIANT_AUTO, 1, 1, 0, b, x, m, s);
-    for (int k = 0; k < sweeps && e == hipSuccess; ++k) {
-        // r = fl32(b - A x)   (on later passes fused with x += delta)
-        e = launch_refine_step(h, k == 0 ? 0 : 1, b, x, r, r, m, s);
-        if (e == hipSuccess) e = launch_sweep(h, SBS_VARIANT_AUTO, 1, 1, 1, r, r, m, s);  // delta
-    }
-    if (e == hipSuccess && sweeps > 0) e = launch_refine_step(h, 2, b, x, r, nullptr, m, s);  // x += delta
-    return e == hipSuccess ? SBS_OK : SBS_ERR_DEVICE;
+    const sbs_status st = refined_check(h, b, x, m, sweeps);
+    if (st != SBS_OK || m == 0) return st;
+    if (!work || work_bytes < sbs_refined_workspace_bytes(h, m) || !aligned(work, 8)) return SBS_ERR_INVALID_ARG;
+    return refined_run(h, b, x, m, sweeps, static_cast<float *>(work), static_cast<hipStream_t>(stream));
 }
 
 sbs_status sbs_cn_step(sbs_handle h, void *c, int64_t m, int32_t dtype, int32_t steps, void *stream) {

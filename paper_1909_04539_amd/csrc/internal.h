@@ -170,6 +170,14 @@ bool choose_partition_refine(const sbs_lhs *h, int64_t m, PartChoice *out);
 hipError_t launch_partition_refine(const sbs_lhs *h, const PartChoice &c, const float *b, double *x, int64_t m,
                                    int sweeps, hipStream_t stream);
 
+// Mixed-precision solve (sbs_solve_batch_refined): argument checks, whether
+// the fused kernel serves m systems (then no scratch is used), and the run
+// itself with r, the FP32 residual scratch of n*m floats (unused when fused).
+sbs_status refined_check(const sbs_lhs *h, const float *b, const double *x, int64_t m, int32_t sweeps);
+bool refined_fused(const sbs_lhs *h, int64_t m);
+sbs_status refined_run(const sbs_lhs *h, const float *b, double *x, int64_t m, int32_t sweeps, float *r,
+                       hipStream_t s);
+
 // Serving: heterogeneous tile launches (see server.cpp).
 struct Tile {
     const void *fac;            // factor rows of this tile's matrix (type per dtype)

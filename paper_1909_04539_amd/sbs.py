@@ -75,6 +75,8 @@ def lib() -> ctypes.CDLL:
         "sbs_auto_variant": ([vp, i64, i32, P(i32)], i32),
         "sbs_solve_batch_refined": ([vp, vp, vp, i64, i32, vp, sz, vp], i32),
         "sbs_refined_workspace_bytes": ([vp, i64], sz),
+        "sbs_solve_batch_refined_noalloc": ([vp, vp, vp, i64, i32, vp], i32),
+        "sbs_refined_static_scratch_bytes": ([], sz),
         "sbs_cn_step": ([vp, vp, i64, i32, i32, vp], i32),
         "sbs_transpose": ([vp, vp, i64, i64, i32, vp], i32),
         "sbs_adi_step": ([vp, vp, vp, vp, i64, i64, vp], i32),
@@ -228,6 +230,22 @@ def sbs_solve_batch_refined(h: int, b: torch.Tensor, x: torch.Tensor | None = No
     _check(lib().sbs_solve_batch_refined(h, p, _rhs(x, n), m, sweeps, work.data_ptr(),
                                          work.numel() * work.element_size(), _stream(stream)),
            "sbs_solve_batch_refined")
+    return x
+
+
+def sbs_refined_static_scratch_bytes() -> int:
+    return int(lib().sbs_refined_static_scratch_bytes())
+
+
+def sbs_solve_batch_refined_noalloc(h: int, b: torch.Tensor, x: torch.Tensor, sweeps: int = 2,
+                                    stream=None) -> torch.Tensor:
+    """sbs_solve_batch_refined with the library's static scratch: the caller
+    passes b (n, m) FP32 and x (n, m) FP64, nothing is allocated."""
+    _, n, _ = sbs_handle_info(h)
+    if b.dtype != torch.float32 or x.dtype != torch.float64 or x.shape != b.shape:
+        raise TypeError("b must be float32 and x float64 of the same shape")
+    _check(lib().sbs_solve_batch_refined_noalloc(h, _rhs(b, n), _rhs(x, n), b.shape[1], sweeps, _stream(stream)),
+           "sbs_solve_batch_refined_noalloc")
     return x
 
 
