@@ -73,40 +73,87 @@ def timed_steps(step, K, W, torch):
     return wall, dev
 
 
+def host_cpu():
+    """The host the oracle runs on: usable cores and the CPU model (the
+    `model name` field that lscpu also prints)."""
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"nproc": len(os.sched_getaffinity(0)), "model": model}
+
+
+def _median_host(fn, X, src, reps=5):
+    """Median wall time of `reps` runs of fn(X), X restored from src before
+    each (untimed)."""
+    ts = []
+    for _ in range(reps):
+        X[...] = src
+        t = time.perf_counter()
+        fn(X)
+        ts.append(time.perf_counter() - t)
+    return sorted(ts)[reps // 2]
+
+
 def cpu_baseline(kind, bands, rhs_sample, target_s=10.0):
-    """The oracle (C, OpenMP over column blocks) on a bounded sample."""
+    """The oracle (C, OpenMP over column blocks) on a bounded sample: the
+    median of 5 timed solves on all host cores and on one thread, after
+    repeated solves for about `target_s` seconds."""
     import oracle
     threads = oracle.max_threads()
     X = rhs_sample.copy()
     n, m = X.shape
-    oracle.solve_inplace_mt(kind, bands, X, threads)       # warm
     reps, t0 = 0, time.perf_counter()
-    while True:
+    while True:                                   # warm the caches and the thread team
         X[...] = rhs_sample
-        t = time.perf_counter()
         oracle.solve_inplace_mt(kind, bands, X, threads)
         reps += 1
         el = time.perf_counter() - t0
         if el >= target_s or reps >= 1000:
             break
-    # time only the solves (the copy back to the pristine input is excluded)
-    t_solve = 0.0
-    for _ in range(3):
-        X[...] = rhs_sample
-        t = time.perf_counter()
-        oracle.solve_inplace_mt(kind, bands, X, threads)
-        t_solve += time.perf_counter() - t
-    per = t_solve / 3
-    # the same sample on one thread (serial oracle, no OpenMP team)
-    X[...] = rhs_sample
-    t = time.perf_counter()
-    oracle.solve_inplace_mt(kind, bands, X, 1)
-    one = time.perf_counter() - t
+    per = _median_host(lambda Y: oracle.solve_inplace_mt(kind, bands, Y, threads), X, rhs_sample)
+    one = _median_host(lambda Y: oracle.solve_inplace_mt(kind, bands, Y, 1), X, rhs_sample)
     return {"value": n * m / per, "unit": "unknowns/s", "cores": threads, "kind": "oracle",
-            "value_1_thread": n * m / one,
-            "sample": f"n={n}, m={m} columns of the same workload (seeded), {reps} solves over "
-                      f"{el:.1f} s, median-free mean of 3 timed solves; value_1_thread: one solve "
-                      f"of the same sample on 1 thread"}
+            "value_1_thread": n * m / one, "host": host_cpu(),
+            "sample": f"n={n}, m={m} columns of the same workload (seeded); median of 5 timed solves "
+                      f"(input restored untimed) after {reps} warm-up solves over {el:.1f} s; "
+                      f"value_1_thread: median of 5 on one thread"}
+
+
+def cpu_other_configs(W):
+    """The oracle on the other workloads (medians of 5, inputs restored
+    untimed): the tridiagonal n=256 batch (whole), the ADI step at 2048^2
+    (whole, serial: columns then rows), and the mixed-precision workload's
+    reference (the FP64 solve of the promoted FP32 right-hand sides) on its
+    first 65536 of 2^20 columns."""
+    import oracle
+    threads = oracle.max_threads()
+    out = {"cores": threads, "host": host_cpu()}
+    wl = W.config0()
+    X = wl.rhs.copy()
+    t = _median_host(lambda Y: oracle.solve_inplace_mt(3, wl.bands, Y, threads), X, wl.rhs)
+    t1 = _median_host(lambda Y: oracle.solve_inplace_mt(3, wl.bands, Y, 1), X, wl.rhs)
+    out["tri_f64_n256_m1024"] = {"unknowns_per_s": wl.n * wl.m / t, "unknowns_per_s_1_thread": wl.n * wl.m / t1,
+                                 "us_per_solve": t * 1e6}
+    wl = W.config2()
+    ts = []
+    for _ in range(5):
+        t0 = time.perf_counter()
+        oracle.adi_step(wl.bands, wl.extra["bands_x"], wl.rhs)
+        ts.append(time.perf_counter() - t0)
+    t = sorted(ts)[2]
+    out["adi_f64_2048x2048"] = {"points_per_s": wl.n * wl.m / t, "ms_per_step": t * 1e3, "threads": 1}
+    wl = W.config3()
+    src = np.ascontiguousarray(wl.rhs[:, :65536].astype(np.float64))
+    X = src.copy()
+    t = _median_host(lambda Y: oracle.solve_inplace_mt(3, wl.bands, Y, threads), X, src)
+    out["refined_reference_n512"] = {"unknowns_per_s": src.size / t, "sample": "first 65536 of 2^20 columns"}
+    return out
 
 
 def bench_headline(args, torch, sbs, W):
@@ -119,14 +166,23 @@ def bench_headline(args, torch, sbs, W):
     kernel = KERNEL_OF[ran]
     step = lambda: lhs.solve(rhs, variant)
     wall, dev = timed_steps(step, args.steps, args.warmup, torch)
+    # the kernel alone: median of 20 launches, each bracketed by its own
+    # events, the right-hand side restored from a pristine copy (untimed)
+    # before each, so every launch solves the same input
+    pristine = rhs.clone()
+    med, mn = _event_median(step, 20, 3, torch, restore=lambda: rhs.copy_(pristine))
+    del pristine
     unknowns = n * m
-    achieved = 16.0 * unknowns / dev / 1e9
+    achieved = 16.0 * unknowns / med / 1e9
     res = {
         "wall_s": wall, "dev_s": dev, "unknowns": unknowns,
         "variant": {v: k for k, v in VARIANTS.items()}[ran], "kernel": kernel,
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(kernel),
-                     "kernel": kernel},
+                     "kernel": kernel, "kernel_us_median": round(med * 1e6, 2), "kernel_us_min": round(mn * 1e6, 2),
+                     "kernel_us_mean_of_timed_steps": round(dev * 1e6, 2),
+                     "timing": "median of 20 launches with HIP events on the launch stream, input restored "
+                               "untimed before each"},
         "cpu_sample": wl.rhs[:, :8192].copy(), "bands": wl.bands,
     }
     lhs.close()
@@ -205,13 +261,28 @@ def bench_periodic_and_cn(args, torch, sbs, W):
     return out
 
 
+def mall_flush(torch):
+    """A function that overwrites 1 GiB of device memory (more than the
+    256 MB last-level cache and the L2s together), for cold-cache timing."""
+    junk = torch.empty(1 << 27, dtype=torch.float64, device="cuda:0")
+    return lambda: junk.fill_(1.0)
+
+
 def bench_tri256(args, torch, sbs, W):
-    """Back-to-back calls from Python, and the same solves replayed from a HIP
-    graph (50 solves per replay), which leaves out the host's cost per call."""
+    """Back-to-back calls from Python, the kernel alone (per-launch events,
+    warm and with the caches flushed before each launch), and the same
+    solves replayed from a HIP graph (50 solves per replay), which leaves out
+    the host's cost per call."""
     wl = W.config0()
     rhs = torch.from_numpy(wl.rhs).to("cuda:0")
     lhs = sbs.SharedLhs(3, wl.bands)
     wall, dev = timed_steps(lambda: lhs.solve(rhs), 200, 20, torch)
+    pristine = rhs.clone()
+    warm, _ = _event_median(lambda: lhs.solve(rhs), 50, 5, torch, restore=lambda: rhs.copy_(pristine))
+    flush = mall_flush(torch)
+    cold, _ = _event_median(lambda: lhs.solve(rhs), 20, 3, torch,
+                            restore=lambda: (rhs.copy_(pristine), flush()))
+    del flush
     x = rhs.clone()
     per_graph = 50
     g = torch.cuda.CUDAGraph()
@@ -224,9 +295,11 @@ def bench_tri256(args, torch, sbs, W):
     u = wl.n * wl.m
     return {"workload": "tri_f64_n256_m1024", "unknowns_per_s": u / dev, "us_per_solve": dev * 1e6,
             "hbm_frac_16B": round(16 * u / dev / 1e9 / HBM_PEAK_GBS, 4),
+            "us_kernel_median_warm": warm * 1e6, "us_kernel_median_cold": cold * 1e6,
             "us_per_solve_graph": gdev / per_graph * 1e6,
             "bound": "latency: back-to-back calls from Python cost about 10 us of host work each; "
-                     "us_per_solve_graph is the device's own time per solve"}
+                     "us_per_solve_graph is the device's own time per solve; cold = 1 GiB written "
+                     "between the input's restore and the launch (median of 20)"}
 
 
 def bench_adi(args, torch, sbs, W):
@@ -236,12 +309,19 @@ def bench_adi(args, torch, sbs, W):
     hy, hx = sbs.SharedLhs(3, wl.bands), sbs.SharedLhs(3, wl.extra["bands_x"])
     step = lambda: sbs.sbs_adi_step(hy.handle, hx.handle, g, work)
     wall, dev = timed_steps(step, 20, 3, torch)
+    pristine = g.clone()
+    warm, _ = _event_median(step, 20, 3, torch, restore=lambda: g.copy_(pristine))
+    flush = mall_flush(torch)
+    cold, _ = _event_median(step, 20, 3, torch, restore=lambda: (g.copy_(pristine), flush()))
+    del flush
     hy.close()
     hx.close()
     pts = wl.n * wl.m
     return {"workload": "adi_f64_2048x2048", "points_per_s": pts / dev, "unknowns_per_s": 2 * pts / dev,
             "ms_per_step": dev * 1e3, "hbm_frac_32B_per_point": round(32 * pts / dev / 1e9 / HBM_PEAK_GBS, 4),
-            "bound": "latency: 2048 systems per solve do not fill the chip"}
+            "us_median_warm": warm * 1e6, "us_median_cold": cold * 1e6,
+            "bound": "latency: 2048 systems per solve do not fill the chip; cold = 1 GiB written between "
+                     "the grid's restore and the step (median of 20)"}
 
 
 def bench_refined(args, torch, sbs, W):
@@ -577,6 +657,9 @@ def main():
                 extra[name] = {"error": repr(e)}
     log("cpu baseline (oracle)")
     cpu = cpu_baseline(5, h["bands"], h["cpu_sample"], args.cpu_seconds)
+    if args.only != "headline":
+        log("oracle on the other workloads")
+        cpu["other_workloads"] = cpu_other_configs(W)
     line = {
         "metric": "RHS unknowns solved/s (pentadiagonal FP64, shared LHS)",
         "value": h["unknowns"] / h["wall_s"],

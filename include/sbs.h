@@ -100,10 +100,11 @@ const char *sbs_version(void);
  *           + a_0 c_{n-1} / b_0, no corners).  z = A'^{-1} u and
  *           w = A'^{-T} v / (1 + v.z) are computed here, so that each solve
  *           is x = y - (w.d) z with y = A'^{-1} d, in the same two sweeps.
- *           Periodic handles take the plain solves (resident, chunked and
- *           stream variants, FP64 or FP32) and the ADI step; the refined
- *           solve, the partitioned variant and the serving loop reject them
- *           with SBS_ERR_INVALID_ARG.
+ *           Periodic handles take the plain solves (every variant, FP64
+ *           or FP32; the partitioned variant solves the periodic system
+ *           directly when n is a whole number of blocks), Crank-Nicolson
+ *           steps and the ADI step; the refined solve and the serving loop
+ *           reject them with SBS_ERR_INVALID_ARG.
  *  out      receives the new handle (owned by the caller; free with
  *           sbs_release).  Set to NULL on every error.
  *  bad_row  optional (may be NULL): on SBS_ERR_ZERO_PIVOT or
