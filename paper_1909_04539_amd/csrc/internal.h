@@ -187,11 +187,17 @@ struct Tile {
     float *scratch;             // FP32 residual scratch (mixed precision only)
     int64_t n, m, col0;         // system range [col0, col0 + 64) of the request
     int32_t kind, fp32;
+    int32_t req;                // the request's slot in the launch's completion arrays
+    int32_t pad;
 };
 
 // Runs tiles [0, ntiles), all of one kind and precision, with `grid`
 // persistent waves; *dev_counter must be 0 when the kernel starts.
-hipError_t launch_tiles(int kind, int fp32, const Tile *dev_tiles, int ntiles, int *dev_counter, int grid,
-                        hipStream_t stream);
+// Per-request completion: left[r] holds the number of tiles of request r
+// (device memory); the wave that finishes the last of them sets done[r] = 1
+// (host-visible memory), after every result of the request is visible to the
+// host and to other work on the device.
+hipError_t launch_tiles(int kind, int fp32, const Tile *dev_tiles, int ntiles, int *dev_counter, int *left,
+                        int *done, int grid, hipStream_t stream);
 
 }  // namespace sbs

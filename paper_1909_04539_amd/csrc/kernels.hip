@@ -1326,14 +1326,22 @@ __device__ __forceinline__ void run_tile_f32(const Tile &t, unsigned char *lds) 
 }
 
 // One kernel per (kind, precision) group of a launch's tiles.
+//
+// Control flow in the persistent loop is wave-uniform throughout: every lane
+// issues each atomic (lane 0 adds its amount, the others add 0) and the wave
+// takes lane 0's result through readfirstlane, so every branch below is
+// taken by the whole wave and no lane can reach the next ticket on a path of
+// its own.  Completion of a request: after its tile each wave releases its
+// results at system scope with its decrement of left[req]; the decrement that
+// takes the count to zero also acquires every earlier one, and the flag store
+// that follows releases them all to the host.
 template <int KIND, int FP32>
-__global__ __launch_bounds__(kWave) void k_tiles(const Tile *__restrict__ tiles, int ntiles, int *counter) {
+__global__ __launch_bounds__(kWave) void k_tiles(const Tile *__restrict__ tiles, int ntiles, int *counter, int *left,
+                                                 int *done) {
     __shared__ __align__(16) unsigned char lds[kTileLds];
+    const int one = threadIdx.x == 0 ? 1 : 0;
     for (;;) {
-        // Every lane issues the fetch (lane 0 adds 1, the others 0) and the
-        // wave takes lane 0's ticket: no lane-dependent branch in the loop,
-        // so no lane can reach the next fetch on a path of its own.
-        int t = atomicAdd(counter, threadIdx.x == 0 ? 1 : 0);
+        int t = atomicAdd(counter, one);
         t = __builtin_amdgcn_readfirstlane(t);
         if (t >= ntiles) break;
         const Tile tl = tiles[t];
@@ -1341,6 +1349,10 @@ __global__ __launch_bounds__(kWave) void k_tiles(const Tile *__restrict__ tiles,
             run_tile_f32<KIND>(tl, lds);
         else
             run_tile_f64<KIND>(tl, lds);
+        const int req = __builtin_amdgcn_readfirstlane(tl.req);
+        int before = __hip_atomic_fetch_add(&left[req], -one, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_SYSTEM);
+        before = __builtin_amdgcn_readfirstlane(before);
+        if (before == 1) __hip_atomic_store(&done[req], 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
     }
 }
 
@@ -1863,19 +1875,19 @@ hipError_t launch_refine_step(const sbs_lhs *h, int mode, const float *b, double
     return hipGetLastError();
 }
 
-hipError_t launch_tiles(int kind, int fp32, const Tile *dev_tiles, int ntiles, int *dev_counter, int grid,
-                        hipStream_t stream) {
+hipError_t launch_tiles(int kind, int fp32, const Tile *dev_tiles, int ntiles, int *dev_counter, int *left,
+                        int *done, int grid, hipStream_t stream) {
     if (ntiles <= 0) return hipSuccess;
     if (grid > ntiles) grid = ntiles;
     const dim3 g((unsigned)grid), b(kWave);
     if (kind == SBS_TRI && !fp32)
-        hipLaunchKernelGGL((k_tiles<SBS_TRI, 0>), g, b, 0, stream, dev_tiles, ntiles, dev_counter);
+        hipLaunchKernelGGL((k_tiles<SBS_TRI, 0>), g, b, 0, stream, dev_tiles, ntiles, dev_counter, left, done);
     else if (kind == SBS_TRI)
-        hipLaunchKernelGGL((k_tiles<SBS_TRI, 1>), g, b, 0, stream, dev_tiles, ntiles, dev_counter);
+        hipLaunchKernelGGL((k_tiles<SBS_TRI, 1>), g, b, 0, stream, dev_tiles, ntiles, dev_counter, left, done);
     else if (!fp32)
-        hipLaunchKernelGGL((k_tiles<SBS_PENTA, 0>), g, b, 0, stream, dev_tiles, ntiles, dev_counter);
+        hipLaunchKernelGGL((k_tiles<SBS_PENTA, 0>), g, b, 0, stream, dev_tiles, ntiles, dev_counter, left, done);
     else
-        hipLaunchKernelGGL((k_tiles<SBS_PENTA, 1>), g, b, 0, stream, dev_tiles, ntiles, dev_counter);
+        hipLaunchKernelGGL((k_tiles<SBS_PENTA, 1>), g, b, 0, stream, dev_tiles, ntiles, dev_counter, left, done);
     return hipGetLastError();
 }
 

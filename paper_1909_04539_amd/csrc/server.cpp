@@ -2,7 +2,10 @@
 //
 // Requests arrive on any thread (sbs_server_submit) and join a FIFO queue.
 // One scheduler thread
-//   1. retires finished launches (event polling) and stamps latencies,
+//   1. retires finished requests and stamps their latencies: a request is
+//      done when the wave that finishes its last tile raises the request's
+//      flag in host memory (so a small request completes while the rest of
+//      its launch still runs); a launch is retired when its event completes,
 //   2. admits queued requests, in arrival order, while their result and
 //      scratch bytes fit in the device arena (the HBM budget),
 //   3. coalesces every admitted request into the next launch on a free
@@ -91,11 +94,21 @@ struct Req {
 struct Slot {
     hipStream_t stream = nullptr;
     hipEvent_t done = nullptr;
-    unsigned char *host = nullptr;  // pinned staging: counters + tiles
+    unsigned char *host = nullptr;  // pinned staging: tile counters, tiles left per request, tiles
     unsigned char *dev = nullptr;
+    int *flag_host = nullptr;       // per request of the launch: set to 1 by the device when it is done
+    int *flag_dev = nullptr;        // the same memory as the device addresses it
+    // requests of the running launch, by their index in the flag array;
+    // nullptr once a request has completed (it may then be released and freed
+    // while the launch still runs)
     std::vector<Req *> reqs;
     bool busy = false;
 };
+
+// Staging layout of a slot: kGroups tile counters (one 64-byte line each),
+// the tiles left of each request (max_batch ints), then the tiles.
+size_t left_offset() { return kGroups * 64; }
+size_t tiles_offset(int max_batch) { return round_up(left_offset() + (size_t)max_batch * 4, 64); }
 
 }  // namespace
 
@@ -124,30 +137,51 @@ struct sbs_server {
     std::vector<double> lat_us;
 
     void loop();
+    void finish(Req *r, sbs_status st, Clock::time_point now);
     void retire();
     void admit();
     bool launch(Slot &s);
 };
 
+void sbs_server::finish(Req *r, sbs_status st, Clock::time_point now) {
+    r->state = DONE;
+    r->t_done = now;
+    r->status = st;
+    lat_us.push_back(std::chrono::duration<double, std::micro>(now - r->t_submit).count());
+    ++completed;
+    --in_flight;
+    unknowns += (double)lhs[r->lhs]->n * (double)r->m;
+}
+
 void sbs_server::retire() {
+    bool any = false;
     for (Slot &s : slots) {
         if (!s.busy) continue;
+        // the event is queried first: if it has completed, every flag it
+        // covers has been written
         const hipError_t q = hipEventQuery(s.done);
-        if (q == hipErrorNotReady) continue;
         const auto now = Clock::now();
-        for (Req *r : s.reqs) {
-            r->state = DONE;
-            r->t_done = now;
-            if (q != hipSuccess) r->status = SBS_ERR_DEVICE;
-            lat_us.push_back(std::chrono::duration<double, std::micro>(now - r->t_submit).count());
-            ++completed;
-            --in_flight;
-            unknowns += (double)lhs[r->lhs]->n * (double)r->m;
+        for (size_t k = 0; k < s.reqs.size(); ++k) {
+            Req *r = s.reqs[k];
+            if (!r) continue;
+            if (__atomic_load_n(&s.flag_host[k], __ATOMIC_ACQUIRE) == 1) {
+                finish(r, SBS_OK, now);
+            } else if (q != hipErrorNotReady) {
+                // launch over without this request's flag: only a failed launch
+                finish(r, q == hipSuccess ? SBS_ERR_DEVICE : SBS_ERR_DEVICE, now);
+            } else {
+                continue;
+            }
+            s.reqs[k] = nullptr;
+            any = true;
         }
-        s.reqs.clear();
-        s.busy = false;
-        cv_done.notify_all();
+        if (q != hipErrorNotReady) {
+            s.reqs.clear();
+            s.busy = false;
+            any = true;
+        }
     }
+    if (any) cv_done.notify_all();
 }
 
 void sbs_server::admit() {
@@ -185,10 +219,14 @@ bool sbs_server::launch(Slot &s) {
 
     // Group tiles by (kind, precision); inside a group, longest systems first.
     std::vector<Tile> grp[kGroups];
-    for (Req *r : take) {
+    int *left = reinterpret_cast<int *>(s.host + left_offset());
+    for (size_t k = 0; k < take.size(); ++k) {
+        Req *r = take[k];
         const sbs_lhs *h = lhs[r->lhs];
         const int fp32 = r->dtype == SBS_F32;
         const int g = (h->kind == SBS_PENTA ? 2 : 0) + fp32;
+        left[k] = (int)((r->m + kWave - 1) / kWave);
+        s.flag_host[k] = 0;  // the slot's previous launch has completed: nothing writes it now
         for (int64_t c = 0; c < r->m; c += kWave) {
             Tile t;
             t.fac = fp32 ? h->fac32 : h->fac64;
@@ -201,12 +239,13 @@ bool sbs_server::launch(Slot &s) {
             t.col0 = c;
             t.kind = h->kind;
             t.fp32 = fp32;
+            t.req = (int32_t)k;
+            t.pad = 0;
             grp[g].push_back(t);
         }
         r->state = RUNNING;
     }
-    // Staging layout: kGroups counters (one 64-byte line each), then the tiles.
-    size_t at = kGroups * 64;
+    size_t at = tiles_offset(max_batch);
     size_t offs[kGroups];
     for (int g = 0; g < kGroups; ++g) {
         std::stable_sort(grp[g].begin(), grp[g].end(), [](const Tile &a, const Tile &b) { return a.n > b.n; });
@@ -220,24 +259,25 @@ bool sbs_server::launch(Slot &s) {
         if (grp[g].empty()) continue;
         const int kind = g >= 2 ? SBS_PENTA : SBS_TRI;
         e = launch_tiles(kind, g & 1, reinterpret_cast<const Tile *>(s.dev + offs[g]), (int)grp[g].size(),
-                         reinterpret_cast<int *>(s.dev + g * 64), kPersistentWaves, s.stream);
+                         reinterpret_cast<int *>(s.dev + g * 64), reinterpret_cast<int *>(s.dev + left_offset()),
+                         s.flag_dev, kPersistentWaves, s.stream);
     }
     if (e == hipSuccess) e = hipEventRecord(s.done, s.stream);
     s.reqs = std::move(take);
     s.busy = true;
     ++launches;
     if (e != hipSuccess) {
-        // Nothing will signal these requests: fail them now.
+        // Nothing will signal these requests: fail them now.  The slot
+        // stays busy until its stream has drained whatever was queued.
         const auto now = Clock::now();
-        for (Req *r : s.reqs) {
-            r->state = DONE;
-            r->status = SBS_ERR_DEVICE;
-            r->t_done = now;
-            ++completed;
-            --in_flight;
+        for (Req *&r : s.reqs) {
+            finish(r, SBS_ERR_DEVICE, now);
+            r = nullptr;
         }
-        s.reqs.clear();
-        s.busy = false;
+        if (hipStreamSynchronize(s.stream) == hipSuccess) {
+            s.reqs.clear();
+            s.busy = false;
+        }
         cv_done.notify_all();
     }
     return true;
@@ -282,7 +322,7 @@ sbs_status sbs_server_create(size_t budget_bytes, int32_t max_streams, int32_t m
     if (hipGetDevice(&s->device) != hipSuccess) st = SBS_ERR_DEVICE;
     if (st == SBS_OK && hipMalloc(reinterpret_cast<void **>(&s->arena_base), s->budget) != hipSuccess)
         st = SBS_ERR_NO_MEMORY;
-    const size_t table = kGroups * 64 + (size_t)kMaxTilesPerLaunch * sizeof(Tile);
+    const size_t table = tiles_offset(s->max_batch) + (size_t)kMaxTilesPerLaunch * sizeof(Tile);
     s->slots.resize(ns);
     for (Slot &sl : s->slots) {
         if (st != SBS_OK) break;
@@ -290,13 +330,18 @@ sbs_status sbs_server_create(size_t budget_bytes, int32_t max_streams, int32_t m
             hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) != hipSuccess)
             st = SBS_ERR_DEVICE;
         else if (hipHostMalloc(reinterpret_cast<void **>(&sl.host), table, hipHostMallocDefault) != hipSuccess ||
-                 hipMalloc(reinterpret_cast<void **>(&sl.dev), table) != hipSuccess)
+                 hipMalloc(reinterpret_cast<void **>(&sl.dev), table) != hipSuccess ||
+                 hipHostMalloc(reinterpret_cast<void **>(&sl.flag_host), (size_t)s->max_batch * sizeof(int),
+                               hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess)
             st = SBS_ERR_NO_MEMORY;
+        else if (hipHostGetDevicePointer(reinterpret_cast<void **>(&sl.flag_dev), sl.flag_host, 0) != hipSuccess)
+            st = SBS_ERR_DEVICE;
     }
     if (st != SBS_OK) {
         for (Slot &sl : s->slots) {
             if (sl.dev) (void)hipFree(sl.dev);
             if (sl.host) (void)hipHostFree(sl.host);
+            if (sl.flag_host) (void)hipHostFree(sl.flag_host);
             if (sl.done) (void)hipEventDestroy(sl.done);
             if (sl.stream) (void)hipStreamDestroy(sl.stream);
         }
@@ -453,6 +498,7 @@ sbs_status sbs_server_destroy(sbs_server *srv) {
         if (sl.stream && hipStreamSynchronize(sl.stream) != hipSuccess) st = SBS_ERR_DEVICE;
         if (sl.dev) (void)hipFree(sl.dev);
         if (sl.host) (void)hipHostFree(sl.host);
+        if (sl.flag_host) (void)hipHostFree(sl.flag_host);
         if (sl.done) (void)hipEventDestroy(sl.done);
         if (sl.stream) (void)hipStreamDestroy(sl.stream);
     }

@@ -74,6 +74,10 @@ hipError_t hipFree(void *p) {
     return hipSuccess;
 }
 hipError_t hipHostMalloc(void **p, size_t n, unsigned int) { return hipMalloc(p, n); }
+hipError_t hipHostGetDevicePointer(void **d, void *h, unsigned int) {
+    *d = h;  // one address space on the CPU
+    return hipSuccess;
+}
 hipError_t hipHostFree(void *p) { return hipFree(p); }
 hipError_t hipStreamCreateWithFlags(hipStream_t *s, unsigned int) {
     *s = new ihipStream_t();
@@ -122,7 +126,12 @@ hipError_t hipMemcpyAsync(void *dst, const void *src, size_t n, hipMemcpyKind, h
 }  // extern "C"
 
 namespace sbs {
-hipError_t launch_tiles(int kind, int fp32, const Tile *tiles, int ntiles, int *counter, int, hipStream_t s) {
+// The tile kernel's completion protocol as the device runs it: after its
+// tile a "wave" takes one from the request's count of tiles left (acquire and
+// release), and the one that takes the last raises the request's flag with a
+// release store; the host reads the flag with an acquire load.
+hipError_t launch_tiles(int kind, int fp32, const Tile *tiles, int ntiles, int *counter, int *left, int *done, int,
+                        hipStream_t s) {
     s->push([=] {
         for (int t = 0; t < ntiles; ++t) {
             const Tile &tl = tiles[t];
@@ -135,6 +144,9 @@ hipError_t launch_tiles(int kind, int fp32, const Tile *tiles, int ntiles, int *
                     tl.x[k] = tl.fp32 ? (double)static_cast<const float *>(tl.in)[k]
                                       : static_cast<const double *>(tl.in)[k];
                 }
+            const int before = __atomic_fetch_sub(&left[tl.req], 1, __ATOMIC_ACQ_REL);
+            if (before < 1) std::abort();  // more tiles than the request was given
+            if (before == 1) __atomic_store_n(&done[tl.req], 1, __ATOMIC_RELEASE);
         }
         *counter = ntiles;
     });

@@ -1,6 +1,7 @@
 // Scenarios for the serving loop's host logic, run against the CPU stand-in
 // for the device.  Usage: scenarios <mix|budget|errors|shutdown>; exit 0 on
 // success, otherwise prints what failed.
+#include <algorithm>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -184,6 +185,88 @@ void shutdown() {
     std::printf("shutdown: ok\n");
 }
 
+// Per-request completion: one launch holds a long pentadiagonal request
+// and short tridiagonal ones (the tridiagonal tiles run first); each short
+// request is reported done, fetched and released while the long one is still
+// running in the same launch, and its arena bytes are reused by a request
+// admitted after it.
+void early() {
+    sbs_server *srv = nullptr;
+    CHECK(sbs_server_create(64u << 20, 1, 0, &srv) == SBS_OK);
+    Lhs L(srv, {64, 300});  // id 0 tridiagonal, id 1 pentadiagonal
+    std::mt19937_64 g(11);
+    Input big = make_input(g, 300, 64 * 400, SBS_F64);  // 400 tiles: about 8 ms
+    std::vector<Input> small;
+    for (int r = 0; r < 4; ++r) small.push_back(make_input(g, 64, 5 + r, r % 2 ? SBS_F32 : SBS_F64));
+    uint64_t tb = 0;
+    std::vector<uint64_t> ts(small.size());
+    CHECK(sbs_server_submit(srv, L.id[1], big.ptr(), big.m, SBS_F64, &tb) == SBS_OK);
+    for (size_t r = 0; r < small.size(); ++r)
+        CHECK(sbs_server_submit(srv, L.id[0], small[r].ptr(), small[r].m, small[r].dtype, &ts[r]) == SBS_OK);
+    const double *x;
+    double lat;
+    int early_done = 0;
+    for (size_t r = 0; r < small.size(); ++r) {
+        CHECK(sbs_server_wait(srv, ts[r], 20000000, &x, &lat) == SBS_OK);
+        CHECK(result_matches(x, small[r]));
+        if (sbs_server_wait(srv, tb, 0, &x, &lat) == SBS_ERR_TIMEOUT) ++early_done;
+        CHECK(sbs_server_release(srv, ts[r]) == SBS_OK);
+    }
+    sbs_server_stats st;
+    CHECK(sbs_server_stats_get(srv, &st) == SBS_OK);
+    // all of them in the first launch (one slot, submitted together) ...
+    CHECK(st.launches <= 2);
+    // ... and finished while the long request still ran
+    CHECK(early_done == (int)small.size());
+    // a request admitted now reuses the released bytes and runs next
+    Input again = make_input(g, 64, 9, SBS_F64);
+    uint64_t ta = 0;
+    CHECK(sbs_server_submit(srv, L.id[0], again.ptr(), again.m, SBS_F64, &ta) == SBS_OK);
+    CHECK(sbs_server_wait(srv, tb, 20000000, &x, &lat) == SBS_OK);
+    CHECK(result_matches(x, big));
+    CHECK(sbs_server_wait(srv, ta, 20000000, &x, &lat) == SBS_OK);
+    CHECK(result_matches(x, again));
+    CHECK(sbs_server_release(srv, tb) == SBS_OK);
+    CHECK(sbs_server_release(srv, ta) == SBS_OK);
+    CHECK(sbs_server_destroy(srv) == SBS_OK);
+    std::printf("early: %d short requests done while the long one ran\n", early_done);
+}
+
+// Many launches on several slots with requests released the moment each
+// completes, in random order of completion checks: every request completes
+// exactly once with its own columns, and nothing is touched after release.
+void churn() {
+    sbs_server *srv = nullptr;
+    // the budget holds every request at once: results are waited for in a
+    // shuffled order, so a request may be held (done, unreleased) while a
+    // later one waits for admission
+    CHECK(sbs_server_create(256u << 20, 3, 7, &srv) == SBS_OK);
+    Lhs L(srv, {40, 90, 130, 260});
+    std::mt19937_64 g(13);
+    const int count = 400;
+    std::vector<Input> in;
+    std::vector<uint64_t> tk(count);
+    for (int r = 0; r < count; ++r)
+        in.push_back(make_input(g, L.h[r % 4].n, 1 + (int64_t)(g() % 200), g() % 2 ? SBS_F64 : SBS_F32));
+    for (int r = 0; r < count; ++r)
+        CHECK(sbs_server_submit(srv, L.id[r % 4], in[r].ptr(), in[r].m, in[r].dtype, &tk[r]) == SBS_OK);
+    std::vector<int> order(count);
+    for (int r = 0; r < count; ++r) order[r] = r;
+    std::shuffle(order.begin(), order.end(), g);
+    for (int r : order) {
+        const double *x;
+        double lat;
+        CHECK(sbs_server_wait(srv, tk[r], 20000000, &x, &lat) == SBS_OK);
+        CHECK(result_matches(x, in[r]));
+        CHECK(sbs_server_release(srv, tk[r]) == SBS_OK);
+    }
+    sbs_server_stats st;
+    CHECK(sbs_server_stats_get(srv, &st) == SBS_OK);
+    CHECK(st.completed == (uint64_t)count && st.in_flight == 0 && st.bytes_reserved == 0);
+    CHECK(sbs_server_destroy(srv) == SBS_OK);
+    std::printf("churn: %d requests in %lu launches\n", count, (unsigned long)st.launches);
+}
+
 }  // namespace
 
 int main(int argc, char **argv) {
@@ -192,6 +275,8 @@ int main(int argc, char **argv) {
     else if (s == "budget") budget();
     else if (s == "errors") errors();
     else if (s == "shutdown") shutdown();
+    else if (s == "early") early();
+    else if (s == "churn") churn();
     else {
         std::fprintf(stderr, "unknown scenario '%s'\n", s.c_str());
         return 2;

@@ -229,10 +229,6 @@ def test_arrivals_during_running_work_are_admitted_and_overlap():
     hs.close()
 
 
-@pytest.mark.skip(reason="per-request completion is switched off: in its tile kernel the compiler let lanes "
-                  "1-63 go round the persistent loop without lane 0 after the lane-0 completion step, so "
-                  "readfirstlane gave those lanes tile 0 again and the kernel never ended; requests complete "
-                  "when their launch does")
 def test_small_request_completes_before_its_launch_ends():
     # One launch holding a large and a small request: with per-request
     # completion the small one is reported done before the large one.
