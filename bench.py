@@ -25,7 +25,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-KERNEL_SOURCE = os.path.join(ROOT, "paper_1909_04539_amd", "csrc", "kernels.hip")
+CSRC = os.path.join(ROOT, "paper_1909_04539_amd", "csrc")
+# source file of each kernel the headline may run
+KERNEL_SOURCE = {"k_sep": os.path.join(CSRC, "sep.hip"), "k_part": os.path.join(CSRC, "kernels.hip"),
+                 "k_sweep": os.path.join(CSRC, "kernels.hip")}
 VARIANTS = {"auto": 0, "resident": 1, "chunked": 2, "stream": 3, "partition": 4}
 # kernel that runs each variant of the headline solve
 KERNEL_OF = {1: "k_sweep", 2: "k_sweep", 3: "k_sweep", 4: "k_part"}
@@ -42,7 +45,7 @@ def measured_traffic(kernel):
     import hashlib
     try:
         rec = json.load(open(traffic_file(kernel)))
-        sha = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
+        sha = hashlib.sha256(open(KERNEL_SOURCE[kernel], "rb").read()).hexdigest()
     except OSError:
         return None
     if rec.get("kernel_source_sha256") != sha:
@@ -164,6 +167,10 @@ def bench_headline(args, torch, sbs, W):
     variant = VARIANTS[args.variant]
     ran = variant if variant else sbs.sbs_auto_variant(lhs.handle, m)
     kernel = KERNEL_OF[ran]
+    shape = None
+    if ran == VARIANTS["partition"]:
+        shape = sbs.sbs_partition_shape(lhs.handle, rhs)       # (form, lb, vec, S)
+        kernel = "k_sep" if shape and shape[0] == 1 else "k_part"
     step = lambda: lhs.solve(rhs, variant)
     wall, dev = timed_steps(step, args.steps, args.warmup, torch)
     # the kernel alone: median of 20 launches, each bracketed by its own
@@ -177,6 +184,8 @@ def bench_headline(args, torch, sbs, W):
     res = {
         "wall_s": wall, "dev_s": dev, "unknowns": unknowns,
         "variant": {v: k for k, v in VARIANTS.items()}[ran], "kernel": kernel,
+        "shape": None if shape is None else {"form": ["pair", "separator"][shape[0]], "lb": shape[1],
+                                             "systems_per_lane": shape[2], "systems_per_workgroup": shape[3]},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(kernel),
                      "kernel": kernel, "kernel_us_median": round(med * 1e6, 2), "kernel_us_min": round(mn * 1e6, 2),
@@ -674,7 +683,8 @@ def main():
         "dtype": "f64",
         "data": "synthetic (seeded): rhs = A x_true, x_true ~ N(0,1)",
         "config": {"workload": "penta_f64_n1024_m65536_shared_lhs", "n": 1024, "m": 65536,
-                   "matrix": "I + s(1,-4,6,-4,1), s=0.5, truncated ends", "variant": h["variant"]},
+                   "matrix": "I + s(1,-4,6,-4,1), s=0.5, truncated ends", "variant": h["variant"],
+                   "shape": h["shape"]},
         "roofline": h["roofline"],
         "cpu_baseline": cpu,
         "kernel_ms": h["dev_s"] * 1e3,

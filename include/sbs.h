@@ -163,6 +163,36 @@ sbs_status sbs_solve_batch(sbs_handle h, void *rhs, int64_t m, int32_t dtype,
 sbs_status sbs_solve_batch_variant(sbs_handle h, void *rhs, int64_t m,
                                    int32_t dtype, int32_t variant, void *stream);
 
+/*
+ * The partitioned variant with an explicit shape (tests check every shape
+ * against the oracle; benchmarks compare shapes).  Two forms:
+ *  form 0  pair form: each block's first and last h unknowns are the
+ *          interface (2h per block boundary); lb in {16, 32, 64}, S systems
+ *          per workgroup, vec = 1, flags = 0.
+ *  form 1  separator form: the last h rows of each block are separator rows,
+ *          solved through the Schur complement of the interior rows (h per
+ *          block boundary); lb in {16, 32, 64}, vec 1 or 2 adjacent systems
+ *          per lane (2: one 16-byte FP64 access per row; needs m even and
+ *          rhs aligned to 2 elements), S systems per workgroup (a multiple
+ *          of vec), flags bit 0: workgroups of one chiplet take adjacent
+ *          groups, bit 1: the next group's loads are issued while the
+ *          current group is stored.
+ * Same arguments and results as sbs_solve_batch otherwise.  A shape that has
+ * no plan, exceeds 1024 threads, the register budget or the LDS returns
+ * SBS_ERR_INVALID_ARG.
+ */
+sbs_status sbs_solve_batch_partition(sbs_handle h, void *rhs, int64_t m,
+                                     int32_t dtype, int32_t form, int32_t lb,
+                                     int32_t vec, int32_t S, int32_t flags,
+                                     void *stream);
+
+/* The partitioned shape AUTO runs for m systems of this dtype at rhs (host
+ * only, rhs is not read: its alignment decides vec).  Returns
+ * SBS_ERR_NOT_FOUND (outputs 0) if AUTO runs the sweeps. */
+sbs_status sbs_partition_shape(sbs_handle h, int64_t m, int32_t dtype,
+                               const void *rhs, int32_t *form, int32_t *lb,
+                               int32_t *vec, int32_t *S);
+
 /* The variant SBS_VARIANT_AUTO runs for m systems of this dtype: the
  * partitioned variant when a plan exists and fits, otherwise resident
  * (n <= 64), chunked (checkpoints fit 160 KiB of LDS) or stream.  Host only,

@@ -253,21 +253,83 @@ sbs_status sbs_solve_batch_variant(sbs_handle h, void *rhs, int64_t m, int32_t d
         return SBS_ERR_INVALID_ARG;
     const int t = dtype == SBS_F64 ? 0 : 1;
     hipError_t e;
-    PartChoice pc;
-    const bool part = choose_partition(h, t, m, &pc);
-    if (variant == SBS_VARIANT_PARTITION && !part) return SBS_ERR_INVALID_ARG;
-    if (variant == SBS_VARIANT_PARTITION || (variant == SBS_VARIANT_AUTO && part))
-        e = launch_partition(h, pc, t, t, t, rhs, rhs, m, static_cast<hipStream_t>(stream));
-    else
-        e = launch_sweep(h, variant, t, t, t, rhs, rhs, m, static_cast<hipStream_t>(stream));
+    if (variant == SBS_VARIANT_AUTO || variant == SBS_VARIANT_PARTITION) {
+        // Partitioned forms: the separator kernel when it fills the GPU with
+        // whole row runs, else the pair kernel, else any separator shape.
+        SepChoice sc;
+        PartChoice pc;
+        const bool sep = choose_sep(h, t, m, rhs, &sc);
+        const bool part = choose_partition(h, t, m, &pc);
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        if (sep && (sep_fills(h, t, m, sc) || !part))
+            e = launch_sep(h, sc, t, rhs, m, s);
+        else if (part)
+            e = launch_partition(h, pc, t, t, t, rhs, rhs, m, s);
+        else if (variant == SBS_VARIANT_PARTITION)
+            return SBS_ERR_INVALID_ARG;
+        else
+            e = launch_sweep(h, variant, t, t, t, rhs, rhs, m, s);
+        return e == hipSuccess ? SBS_OK : SBS_ERR_DEVICE;
+    }
+    e = launch_sweep(h, variant, t, t, t, rhs, rhs, m, static_cast<hipStream_t>(stream));
     return e == hipSuccess ? SBS_OK : SBS_ERR_DEVICE;
+}
+
+sbs_status sbs_solve_batch_partition(sbs_handle h, void *rhs, int64_t m, int32_t dtype, int32_t form, int32_t lb,
+                                     int32_t vec, int32_t S, int32_t flags, void *stream) {
+    if (!h || m < 0 || (dtype != SBS_F64 && dtype != SBS_F32) || (form != 0 && form != 1)) return SBS_ERR_INVALID_ARG;
+    if (m == 0) return SBS_OK;
+    if (!rhs || !aligned(rhs, dtype == SBS_F64 ? 8 : 4) || m > (int64_t)0x7fffffff * kWave) return SBS_ERR_INVALID_ARG;
+    const int t = dtype == SBS_F64 ? 0 : 1;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipError_t e;
+    if (form == 1) {
+        SepChoice sc;
+        if (flags < 0 || flags > 3 || !sep_shape(h, t, m, rhs, lb, vec, S, flags, &sc)) return SBS_ERR_INVALID_ARG;
+        e = launch_sep(h, sc, t, rhs, m, s);
+    } else {
+        PartChoice pc;
+        if (vec != 1 || flags != 0 || !part_shape(h, t, m, lb, S, &pc)) return SBS_ERR_INVALID_ARG;
+        e = launch_partition(h, pc, t, t, t, rhs, rhs, m, s);
+    }
+    return e == hipSuccess ? SBS_OK : SBS_ERR_DEVICE;
+}
+
+sbs_status sbs_partition_shape(sbs_handle h, int64_t m, int32_t dtype, const void *rhs, int32_t *form, int32_t *lb,
+                               int32_t *vec, int32_t *S) {
+    if (!h || m < 1 || (dtype != SBS_F64 && dtype != SBS_F32) || !form || !lb || !vec || !S)
+        return SBS_ERR_INVALID_ARG;
+    const int t = dtype == SBS_F64 ? 0 : 1;
+    SepChoice sc;
+    PartChoice pc;
+    const bool sep = choose_sep(h, t, m, rhs, &sc);
+    const bool part = choose_partition(h, t, m, &pc);
+    if (sep && (sep_fills(h, t, m, sc) || !part)) {
+        *form = 1;
+        *lb = h->sep[sc.plan].lb;
+        *vec = sc.vec;
+        *S = sc.S;
+    } else if (part) {
+        *form = 0;
+        *lb = h->part[pc.plan].lb;
+        *vec = 1;
+        *S = pc.S;
+    } else {
+        *form = *lb = *vec = *S = 0;
+        return SBS_ERR_NOT_FOUND;
+    }
+    return SBS_OK;
 }
 
 sbs_status sbs_auto_variant(sbs_handle h, int64_t m, int32_t dtype, int32_t *variant) {
     if (!h || !variant || m < 1 || (dtype != SBS_F64 && dtype != SBS_F32)) return SBS_ERR_INVALID_ARG;
     const int t = dtype == SBS_F64 ? 0 : 1;
     PartChoice pc;
-    *variant = choose_partition(h, t, m, &pc) ? SBS_VARIANT_PARTITION : choose_variant(h, t);
+    SepChoice sc;
+    // a separator shape exists for some alignment of the right-hand sides
+    // whenever one exists for 8-byte alignment (pairs need 16)
+    const bool part = choose_partition(h, t, m, &pc) || choose_sep(h, t, m, nullptr, &sc);
+    *variant = part ? SBS_VARIANT_PARTITION : choose_variant(h, t);
     return SBS_OK;
 }
 

@@ -94,6 +94,41 @@ struct PartPlan {
 };
 constexpr int kPartLbs[3] = {16, 32, 64};
 
+// Separator partition of the shared matrix (several lanes per system, the
+// form the plain partitioned solve runs).  Rows are cut into P blocks of lb
+// rows; the last h rows of every block but the last (of every block when the
+// matrix is periodic) are separator rows, the others interior rows.  With
+// the separators z known, the interior rows of block p decouple:
+//   x_I(p) = g_p - V_p z_p - W_p z_{p-1},   g_p = A_II(p)^{-1} f_I(p),
+// V_p / W_p = A_II(p)^{-1} times the columns of its own / the previous
+// separator.  Substituting into the separator rows gives the Schur
+// complement system S z = yhat, yhat_p = f_sep(p) - (separator rows' couplings
+// to the neighbouring interior rows) . g, with h(P-1) unknowns (hP periodic),
+// half the interface of the pair form above.  Everything but g and yhat
+// depends on the matrix only and is computed once, in FP64.
+struct SepPlan {
+    int lb = 0, P = 0, Nr = 0;
+    int D = 0;  // distinct blocks stored
+    bool ok = false;
+    bool periodic = false;
+    // Device arrays, each [fac | spk | scf | sinv | map] contiguous, 16-byte aligned:
+    //   fac: D*lb factor rows (interior factor; identity on separator rows)
+    //   spk: D*lb rows of {V[0..h), W[0..h)} (0 on separator rows)
+    //   scf: D*h rows of 2h+1 coefficients: band row of each separator row,
+    //        0 on separator columns and outside the matrix
+    //   sinv: Nr*Nr, row-major (inverse of S)
+    //   map: P ints
+    void *blob64 = nullptr, *blob32 = nullptr;
+    size_t fac_bytes64 = 0, spk_bytes64 = 0, scf_bytes64 = 0, sinv_bytes64 = 0;
+    size_t fac_bytes32 = 0, spk_bytes32 = 0, scf_bytes32 = 0, sinv_bytes32 = 0;
+    size_t map_bytes = 0;
+    size_t blob_bytes(int tc) const {
+        return (tc == 0 ? fac_bytes64 + spk_bytes64 + scf_bytes64 + sinv_bytes64
+                        : fac_bytes32 + spk_bytes32 + scf_bytes32 + sinv_bytes32) +
+               map_bytes;
+    }
+};
+
 }  // namespace sbs
 
 struct sbs_lhs {
@@ -106,6 +141,7 @@ struct sbs_lhs {
     sbs::BandRow *bands = nullptr;  // BandRow[rows]
     void *pdev = nullptr;       // partition data (one allocation for all plans)
     sbs::PartPlan part[3];      // block lengths 16, 32, 64
+    sbs::SepPlan sep[3];        // block lengths 16, 32, 64
     // every band constant over the rows where it lies inside the matrix
     // (every row for a periodic matrix): the coefficients themselves
     bool constant_bands = false;
@@ -160,6 +196,8 @@ struct PartChoice {
 // bands (coefficients passed by value, nothing staged).
 // rows: the systems are rows of a row-major grid (launch_partition_rows).
 bool choose_partition(const sbs_lhs *h, int tc, int64_t m, PartChoice *out, int cn = 0, bool rows = false);
+// A given pair-partition shape for a plain solve (block length lb, S).
+bool part_shape(const sbs_lhs *h, int tc, int64_t m, int lb, int S, PartChoice *out);
 hipError_t launch_partition(const sbs_lhs *h, const PartChoice &c, int tc, int tin, int tout, const void *in,
                             void *out, int64_t m, hipStream_t stream, int cn = 0);
 // FP64 solve of m systems stored one after another (system j at x + j*n),
@@ -169,6 +207,25 @@ sbs_status build_partitions(sbs_lhs *h, const double *bands);
 bool choose_partition_refine(const sbs_lhs *h, int64_t m, PartChoice *out);
 hipError_t launch_partition_refine(const sbs_lhs *h, const PartChoice &c, const float *b, double *x, int64_t m,
                                    int sweeps, hipStream_t stream);
+
+// Separator-partitioned solve (plain solves of interleaved right-hand sides):
+// plan, values per lane (VEC adjacent systems, one access per row), systems
+// per workgroup, launch options (bit 0: XCD-grouped group order, bit 1: the
+// next group's loads issued during the current group's stores).
+struct SepChoice {
+    int plan = -1, vec = 1, S = 0, threads = 0, flags = 0;
+    size_t lds = 0;
+    int wgs = 1;  // workgroups resident per CU at this size
+};
+// The shape AUTO runs for m systems at x (the alignment of x decides whether
+// pairs of systems can move as one access); false if no plan fits.
+bool choose_sep(const sbs_lhs *h, int tc, int64_t m, const void *x, SepChoice *out);
+// A given shape (block length lb, VEC, S, flags); false if it cannot run.
+bool sep_shape(const sbs_lhs *h, int tc, int64_t m, const void *x, int lb, int vec, int S, int flags, SepChoice *out);
+// In place on the interleaved (n, m) array x (tc: 0 f64, 1 f32).
+hipError_t launch_sep(const sbs_lhs *h, const SepChoice &c, int tc, void *x, int64_t m, hipStream_t stream);
+// Whether the separator shape fills the GPU with whole 256-byte row runs.
+bool sep_fills(const sbs_lhs *h, int tc, int64_t m, const SepChoice &c);
 
 // Mixed-precision solve (sbs_solve_batch_refined): argument checks, whether
 // the fused kernel serves m systems (then no scratch is used), and the run

@@ -1819,6 +1819,30 @@ bool choose_partition(const sbs_lhs *h, int tc, int64_t m, PartChoice *out, int 
     return true;
 }
 
+bool part_shape(const sbs_lhs *h, int tc, int64_t m, int lb, int S, PartChoice *out) {
+    const size_t elem = tc == 0 ? 8 : 4;
+    const int H = part_kind(h->kind) / 2;
+    for (int q = 0; q < 3; ++q) {
+        const PartPlan &pp = h->part[q];
+        if (!pp.ok || pp.lb != lb || m < 1 || S < 1 || S > 64) continue;
+        const int maxt = (pp.lb == 64 && elem == 8) ? 512 : 1024;
+        const int threads = S * pp.P;
+        if (threads > maxt) return false;
+        const bool mma = tc == 0 && H == 2;
+        const size_t lds = pp.blob_bytes(tc) + ((size_t)S * (pp.Nr + 1) * elem + 15) / 16 * 16 * (mma ? 2 : 1);
+        if (lds > kMaxPartLdsBytes) return false;
+        const int wgs = part_wgs_per_cu(h->kind, tc, pp.lb, threads, lds, 0);
+        if (wgs < 1) return false;
+        out->plan = q;
+        out->S = S;
+        out->threads = threads;
+        out->lds = lds;
+        out->wgs = wgs;
+        return true;
+    }
+    return false;
+}
+
 template <int KIND, typename T>
 hipError_t go_part_cn(const sbs_lhs *h, const PartChoice &c, const void *in, void *out, int64_t m, hipStream_t s,
                       int cn) {

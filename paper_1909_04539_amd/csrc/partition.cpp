@@ -286,6 +286,227 @@ bool build_plan(int kind, bool periodic, int64_t n, const double *bands, int lb,
     return dev <= kPlanTolerance;
 }
 
+// ---------------------------------------------------------------------------
+// Separator partition (SepPlan).
+
+constexpr int kMaxSepInterface = 96;  // separator unknowns: the FP64 inverse stays under 72 KB of LDS
+
+struct SepHostPlan {
+    int lb = 0, P = 0, Nr = 0, D = 0;
+    std::vector<unsigned char> fac;  // D*lb FP64 rows
+    std::vector<double> spk;         // D*lb*2h: V (own separator), W (previous separator)
+    std::vector<double> scf;         // D*h*(2h+1)
+    std::vector<double> sinv;        // Nr*Nr
+    std::vector<int> map;
+};
+
+// The separator plan's own solve of one column, as the kernel runs it:
+// block sweeps (separator rows pass through unchanged), separator
+// right-hand sides yhat, separators z = S^{-1} yhat, interior correction.
+template <typename Row, typename SolveFn>
+void sep_plan_solve(const SepHostPlan &hp, int h, bool periodic, int64_t n, SolveFn solve, std::vector<double> &x) {
+    const int lb = hp.lb, P = hp.P, Nr = hp.Nr, nb = 2 * h + 1;
+    const Row *fac = reinterpret_cast<const Row *>(hp.fac.data());
+    auto has_sep = [&](int p) { return periodic || p < P - 1; };
+    auto has_prev = [&](int p) { return periodic || p >= 1; };
+    auto prev = [&](int p) { return p == 0 ? P - 1 : p - 1; };
+    auto next = [&](int p) { return p == P - 1 ? 0 : p + 1; };
+    std::vector<double> g((size_t)P * lb, 0.0), f = g, yh(Nr > 0 ? Nr : 1, 0.0), z = yh;
+    for (int64_t i = 0; i < n; ++i) f[i] = g[i] = x[i];
+    for (int p = 0; p < P; ++p) solve(lb, fac + (int64_t)hp.map[p] * lb, g.data() + (int64_t)p * lb);
+    for (int p = 0; p < P; ++p) {
+        if (!has_sep(p)) continue;
+        const double *cf = hp.scf.data() + (size_t)hp.map[p] * h * nb;
+        for (int c = 0; c < h; ++c) {
+            double v = f[(int64_t)p * lb + lb - h + c];
+            for (int d = 0; d < nb; ++d) {
+                const int t = lb - h + c + d - h;  // column, relative to the block's first row
+                double val = 0.0;
+                if (t < lb - h) val = g[(int64_t)p * lb + t];
+                else if (t >= lb) val = g[(int64_t)next(p) * lb + t - lb];
+                v -= cf[c * nb + d] * val;
+            }
+            yh[h * p + c] = v;
+        }
+    }
+    for (int r = 0; r < Nr; ++r) {
+        double v = 0.0;
+        for (int k = 0; k < Nr; ++k) v += hp.sinv[(size_t)r * Nr + k] * yh[k];
+        z[r] = v;
+    }
+    for (int p = 0; p < P; ++p) {
+        const double *sp = hp.spk.data() + (size_t)hp.map[p] * lb * 2 * h;
+        for (int t = 0; t < lb; ++t) {
+            const int64_t i = (int64_t)p * lb + t;
+            if (i >= n) break;
+            double v;
+            if (has_sep(p) && t >= lb - h) {
+                v = z[h * p + t - (lb - h)];
+            } else {
+                v = g[i];
+                for (int c = 0; c < h; ++c) {
+                    if (has_sep(p)) v -= sp[t * 2 * h + c] * z[h * p + c];
+                    if (has_prev(p)) v -= sp[t * 2 * h + h + c] * z[h * prev(p) + c];
+                }
+            }
+            x[i] = v;
+        }
+    }
+}
+
+template <typename Row, typename SolveFn>
+double sep_plan_deviation(const SepHostPlan &hp, int kind, bool periodic, int64_t n, const double *bands,
+                          SolveFn solve) {
+    const int h = kind / 2;
+    uint64_t st = 0x9e3779b97f4a7c15ull;  // xorshift64, fixed seed
+    double worst = 0.0;
+    std::vector<double> d(n), a, b;
+    for (int q = 0; q < kPlanChecks; ++q) {
+        for (int64_t i = 0; i < n; ++i) {
+            st ^= st << 13;
+            st ^= st >> 7;
+            st ^= st << 17;
+            d[i] = (double)(st >> 11) * 0x1.0p-52 - 1.0;  // U[-1, 1)
+        }
+        a = d;
+        b = d;
+        reference_solve(kind, periodic, n, bands, a);
+        sep_plan_solve<Row>(hp, h, periodic, n, solve, b);
+        double num = 0.0, den = 0.0;
+        for (int64_t i = 0; i < n; ++i) {
+            num = std::max(num, std::fabs(b[i] - a[i]));
+            den = std::max(den, std::fabs(a[i]));
+        }
+        const double e = den > 0.0 ? num / den : num;
+        if (!(e <= worst)) worst = e;  // a NaN stays
+    }
+    return worst;
+}
+
+// kind 3 or 5; `periodic` wraps a tridiagonal matrix round (needs n a whole
+// number P >= 2 of blocks; every block then has a separator).
+template <typename Row, typename FactorFn, typename SolveFn>
+bool build_sep_plan(int kind, bool periodic, int64_t n, const double *bands, int lb, FactorFn factor, SolveFn solve,
+                    SepHostPlan &hp) {
+    const int h = kind / 2, nb = 2 * h + 1;
+    const int P = (int)((n + lb - 1) / lb);
+    if (periodic && (n % lb != 0 || P < 2)) return false;
+    const int nsep = periodic ? P : P - 1;
+    if (P > kMaxBlocks || lb < 2 * h + 1 || h * nsep > kMaxSepInterface) return false;
+    const int64_t npad = (int64_t)P * lb;
+    auto has_sep = [&](int p) { return periodic || p < P - 1; };
+    auto has_prev = [&](int p) { return periodic || p >= 1; };
+    auto prev = [&](int p) { return p == 0 ? P - 1 : p - 1; };
+    auto next = [&](int p) { return p == P - 1 ? 0 : p + 1; };
+    auto interior = [&](int p) { return has_sep(p) ? lb - h : lb; };
+    // Entry of row i < n in column col (any index; wrapped when periodic).
+    auto entry = [&](int64_t i, int64_t col) -> double {
+        if (i >= n) return 0.0;
+        int64_t d = col - i;
+        if (periodic) {
+            d = ((d % n) + n) % n;
+            if (d > n / 2) d -= n;
+        } else if (col < 0 || col >= n) {
+            return 0.0;
+        }
+        return (d >= -h && d <= h) ? bands[(int64_t)(d + h) * n + i] : 0.0;
+    };
+    std::vector<Row> rows(npad);
+    std::vector<double> spk((size_t)npad * 2 * h, 0.0), scf((size_t)P * h * nb, 0.0);
+    std::vector<double> v(lb);
+    for (int p = 0; p < P; ++p) {
+        const int64_t r0 = (int64_t)p * lb;
+        const int ni = interior(p);
+        // the interior block: coefficients among its own interior columns,
+        // identity on separator rows and past the end
+        auto local = [&](int k, int64_t t) -> double {
+            const int64_t i = r0 + t;
+            if (i >= n || t >= ni) return k == h ? 1.0 : 0.0;
+            const int64_t ct = t + k - h;
+            if (ct < 0 || ct >= ni || r0 + ct >= n) return 0.0;
+            return bands[(int64_t)k * n + i];
+        };
+        int64_t bad = -1;
+        if (!factor(lb, local, rows.data() + r0, &bad)) return false;
+        for (int c = 0; c < h; ++c) {
+            // V: the block's own separator rows r0 + ni + c
+            for (int t = 0; t < lb; ++t) v[t] = (has_sep(p) && t < ni) ? entry(r0 + t, r0 + ni + c) : 0.0;
+            solve(lb, rows.data() + r0, v.data());
+            for (int t = 0; t < lb; ++t) spk[(size_t)(r0 + t) * 2 * h + c] = t < ni ? v[t] : 0.0;
+            // W: the previous separator, rows r0 - h + c (wrapped for block 0)
+            const int64_t pc = p == 0 ? n - h + c : r0 - h + c;
+            for (int t = 0; t < lb; ++t) v[t] = (has_prev(p) && t < ni) ? entry(r0 + t, pc) : 0.0;
+            solve(lb, rows.data() + r0, v.data());
+            for (int t = 0; t < lb; ++t) spk[(size_t)(r0 + t) * 2 * h + h + c] = t < ni ? v[t] : 0.0;
+        }
+        if (!has_sep(p)) continue;
+        // band rows of the separator rows, without the separator columns
+        for (int c = 0; c < h; ++c)
+            for (int d = 0; d < nb; ++d) {
+                const int t = ni + c + d - h;
+                if (t >= ni && t < lb) continue;
+                scf[((size_t)p * h + c) * nb + d] = entry(r0 + ni + c, r0 + t);
+            }
+    }
+    // S: separator s (of block s), row c.  Unknown order h * s + c.
+    const int Nr = h * nsep;
+    std::vector<double> S((size_t)Nr * Nr, 0.0);
+    auto V = [&](int p, int t, int c) { return spk[(size_t)((int64_t)p * lb + t) * 2 * h + c]; };
+    auto W = [&](int p, int t, int c) { return spk[(size_t)((int64_t)p * lb + t) * 2 * h + h + c]; };
+    for (int s = 0; s < nsep; ++s) {
+        const int64_t r0 = (int64_t)s * lb;
+        const int ni = lb - h, nx = next(s);
+        for (int c = 0; c < h; ++c) {
+            const int row = h * s + c;
+            for (int c2 = 0; c2 < h; ++c2) S[(size_t)row * Nr + h * s + c2] += entry(r0 + ni + c, r0 + ni + c2);
+            for (int d = 0; d < nb; ++d) {
+                const int t = ni + c + d - h;
+                const double cf = scf[((size_t)s * h + c) * nb + d];
+                if (cf == 0.0) continue;
+                if (t < ni) {  // interior row t of block s
+                    for (int c2 = 0; c2 < h; ++c2) {
+                        S[(size_t)row * Nr + h * s + c2] -= cf * V(s, t, c2);
+                        if (has_prev(s)) S[(size_t)row * Nr + h * prev(s) + c2] -= cf * W(s, t, c2);
+                    }
+                } else {  // interior row t - lb of the next block
+                    const int u = t - lb;
+                    for (int c2 = 0; c2 < h; ++c2) {
+                        S[(size_t)row * Nr + h * s + c2] -= cf * W(nx, u, c2);
+                        if (has_sep(nx)) S[(size_t)row * Nr + h * nx + c2] -= cf * V(nx, u, c2);
+                    }
+                }
+            }
+        }
+    }
+    if (Nr > 0 && !invert(S, Nr)) return false;
+    hp.lb = lb;
+    hp.P = P;
+    hp.Nr = Nr;
+    hp.D = 0;
+    const size_t rb = sizeof(Row) * lb, sb = sizeof(double) * lb * 2 * h, cb = sizeof(double) * h * nb;
+    hp.map.assign(P, -1);
+    hp.fac.clear();
+    hp.spk.clear();
+    hp.scf.clear();
+    for (int p = 0; p < P; ++p) {
+        const unsigned char *rp = reinterpret_cast<const unsigned char *>(rows.data() + (int64_t)p * lb);
+        const double *sp = spk.data() + (size_t)p * lb * 2 * h;
+        const double *cp = scf.data() + (size_t)p * h * nb;
+        for (int q = 0; q < hp.D && hp.map[p] < 0; ++q)
+            if (!std::memcmp(hp.fac.data() + q * rb, rp, rb) && !std::memcmp(hp.spk.data() + q * lb * 2 * h, sp, sb) &&
+                !std::memcmp(hp.scf.data() + (size_t)q * h * nb, cp, cb))
+                hp.map[p] = q;
+        if (hp.map[p] < 0) {
+            hp.map[p] = hp.D++;
+            hp.fac.insert(hp.fac.end(), rp, rp + rb);
+            hp.spk.insert(hp.spk.end(), sp, sp + (size_t)lb * 2 * h);
+            hp.scf.insert(hp.scf.end(), cp, cp + (size_t)h * nb);
+        }
+    }
+    hp.sinv.swap(S);
+    return sep_plan_deviation<Row>(hp, kind, periodic, n, bands, solve) <= kPlanTolerance;
+}
+
 template <typename Row32, typename Row64>
 Row32 narrow_row(const Row64 &r);
 template <>
@@ -333,13 +554,54 @@ void serialise(const HostPlan &hp, std::vector<unsigned char> &b64, std::vector<
     pp.D = hp.D;
 }
 
+// Serialise one separator plan as [fac | spk | scf | sinv | map] in FP64 and FP32.
+template <typename Row64, typename Row32>
+void serialise_sep(const SepHostPlan &hp, std::vector<unsigned char> &b64, std::vector<unsigned char> &b32,
+                   SepPlan &pp) {
+    const size_t nrow = hp.fac.size() / sizeof(Row64);
+    const size_t map_bytes = align16(hp.map.size() * sizeof(int));
+    pp.fac_bytes64 = align16(hp.fac.size());
+    pp.spk_bytes64 = align16(hp.spk.size() * 8);
+    pp.scf_bytes64 = align16(hp.scf.size() * 8);
+    pp.sinv_bytes64 = align16(hp.sinv.size() * 8);
+    b64.assign(pp.fac_bytes64 + pp.spk_bytes64 + pp.scf_bytes64 + pp.sinv_bytes64 + map_bytes, 0);
+    unsigned char *at = b64.data();
+    copy_bytes(at, hp.fac.data(), hp.fac.size());
+    copy_bytes(at += pp.fac_bytes64, hp.spk.data(), hp.spk.size() * 8);
+    copy_bytes(at += pp.spk_bytes64, hp.scf.data(), hp.scf.size() * 8);
+    copy_bytes(at += pp.scf_bytes64, hp.sinv.data(), hp.sinv.size() * 8);
+    copy_bytes(at += pp.sinv_bytes64, hp.map.data(), hp.map.size() * sizeof(int));
+    pp.fac_bytes32 = align16(nrow * sizeof(Row32));
+    pp.spk_bytes32 = align16(hp.spk.size() * 4);
+    pp.scf_bytes32 = align16(hp.scf.size() * 4);
+    pp.sinv_bytes32 = align16(hp.sinv.size() * 4);
+    b32.assign(pp.fac_bytes32 + pp.spk_bytes32 + pp.scf_bytes32 + pp.sinv_bytes32 + map_bytes, 0);
+    const Row64 *r64 = reinterpret_cast<const Row64 *>(hp.fac.data());
+    Row32 *r32 = reinterpret_cast<Row32 *>(b32.data());
+    for (size_t i = 0; i < nrow; ++i) r32[i] = narrow_row<Row32>(r64[i]);
+    auto put = [](unsigned char *dst, const std::vector<double> &src) {
+        float *f = reinterpret_cast<float *>(dst);
+        for (size_t i = 0; i < src.size(); ++i) f[i] = (float)src[i];
+    };
+    unsigned char *q = b32.data() + pp.fac_bytes32;
+    put(q, hp.spk);
+    put(q += pp.spk_bytes32, hp.scf);
+    put(q += pp.scf_bytes32, hp.sinv);
+    copy_bytes(q += pp.sinv_bytes32, hp.map.data(), hp.map.size() * sizeof(int));
+    pp.map_bytes = map_bytes;
+    pp.D = hp.D;
+    pp.lb = hp.lb;
+    pp.P = hp.P;
+    pp.Nr = hp.Nr;
+}
+
 }  // namespace
 
 // Builds every plan that exists for this matrix.  A plan that does not exist
 // (too many blocks, a zero pivot inside a block, a singular interface
 // system) only disables the partitioned variant for that block length.
 sbs_status build_partitions(sbs_lhs *h, const double *bands) {
-    std::vector<unsigned char> b64[3], b32[3];
+    std::vector<unsigned char> b64[3], b32[3], s64[3], s32[3];
     size_t total = 0;
     // A periodic tridiagonal matrix is partitioned directly (the blocks are
     // plain tridiagonal; the wrap is one more interface pair).
@@ -368,6 +630,28 @@ sbs_status build_partitions(sbs_lhs *h, const double *bands) {
         pp.ok = true;
         total += align256(b64[q].size()) + align256(b32[q].size());
     }
+    for (int q = 0; q < 3; ++q) {
+        SepHostPlan hp;
+        const int lb = kPartLbs[q];
+        bool ok;
+        if (tri)
+            ok = build_sep_plan<TriRow<double>>(SBS_TRI, periodic, h->n, bands, lb,
+                                                factor_tri_rows<std::function<double(int, int64_t)>>, solve_tri_rows,
+                                                hp);
+        else
+            ok = build_sep_plan<PentaRow<double>>(SBS_PENTA, false, h->n, bands, lb,
+                                                  factor_penta_rows<std::function<double(int, int64_t)>>,
+                                                  solve_penta_rows, hp);
+        if (!ok) continue;
+        SepPlan &sp = h->sep[q];
+        sp.periodic = periodic;
+        if (tri)
+            serialise_sep<TriRow<double>, TriRow<float>>(hp, s64[q], s32[q], sp);
+        else
+            serialise_sep<PentaRow<double>, PentaRow<float>>(hp, s64[q], s32[q], sp);
+        sp.ok = true;
+        total += align256(s64[q].size()) + align256(s32[q].size());
+    }
     if (total == 0) return SBS_OK;
     void *dev = nullptr;
     if (hipMalloc(&dev, total) != hipSuccess) return SBS_ERR_NO_MEMORY;
@@ -385,6 +669,19 @@ sbs_status build_partitions(sbs_lhs *h, const double *bands) {
             return SBS_ERR_DEVICE;
         pp.blob32 = base + at;
         at += align256(b32[q].size());
+    }
+    for (int q = 0; q < 3; ++q) {
+        SepPlan &sp = h->sep[q];
+        if (!sp.ok) continue;
+        unsigned char *base = static_cast<unsigned char *>(dev);
+        if (hipMemcpy(base + at, s64[q].data(), s64[q].size(), hipMemcpyHostToDevice) != hipSuccess)
+            return SBS_ERR_DEVICE;
+        sp.blob64 = base + at;
+        at += align256(s64[q].size());
+        if (hipMemcpy(base + at, s32[q].data(), s32[q].size(), hipMemcpyHostToDevice) != hipSuccess)
+            return SBS_ERR_DEVICE;
+        sp.blob32 = base + at;
+        at += align256(s32[q].size());
     }
     h->device_bytes += (int64_t)total;
     return SBS_OK;

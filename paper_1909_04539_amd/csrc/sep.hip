@@ -1,0 +1,620 @@
+// Separator-partitioned solve (several lanes per system) for plain solves of
+// interleaved right-hand sides.
+//
+// The rows of every system are cut into P blocks of LB rows.  The last H rows
+// of each block (but the last, unless the matrix is periodic) are separator
+// rows; the others are interior rows.  A workgroup holds S systems x P
+// blocks: lane (p, s) loads rows [p*LB, (p+1)*LB) of VEC adjacent systems
+// (VEC = 2: one 16-byte access per FP64 row), and then, per group of S
+// systems:
+//   1. runs the Section 3.1 / 4.1 recurrences over its block with the
+//      block's interior factor (separator rows are identity rows, so they pass
+//      through holding their right-hand sides);
+//   2. publishes the first H values of its block solution to LDS;
+//   3. forms its separator's right-hand side yhat = f_sep - (couplings of the
+//      separator rows to the interior rows on either side) . g, the right
+//      neighbour's values coming from LDS;
+//   4. the separators of all S systems follow as Z = S^{-1} Yhat, a dense
+//      (Nr x Nr)(Nr x S) product on the matrix cores in FP64 (per-lane dot
+//      products otherwise);
+//   5. corrects its interior rows x = g - V z_own - W z_prev, takes its
+//      separator rows from z, and stores every row once, non-temporally,
+//      loading the next group's rows into the registers it frees.
+// Each right-hand side crosses HBM once in and once out (16 bytes per FP64
+// unknown).  The block factors, spikes V / W, separator band rows and S^{-1}
+// depend only on the shared matrix; they are computed once on the host and
+// copied into LDS once per persistent workgroup.
+#include <algorithm>
+
+#include "internal.h"
+
+namespace sbs {
+namespace {
+
+typedef double D2 __attribute__((ext_vector_type(2)));
+typedef float F2 __attribute__((ext_vector_type(2)));
+typedef double D4 __attribute__((ext_vector_type(4)));
+
+template <int KIND, typename T>
+struct RowOf;
+template <typename T>
+struct RowOf<SBS_TRI, T> {
+    using type = TriRow<T>;
+};
+template <typename T>
+struct RowOf<SBS_PENTA, T> {
+    using type = PentaRow<T>;
+};
+
+template <typename T>
+struct Pair;
+template <>
+struct Pair<double> {
+    using type = D2;
+};
+template <>
+struct Pair<float> {
+    using type = F2;
+};
+
+// VEC adjacent values of one row (one 8/16-byte access for VEC = 2).
+template <typename T, int VEC>
+__device__ __forceinline__ void load_vec(const T *p, T (&v)[VEC]) {
+    if constexpr (VEC == 1) {
+        v[0] = *p;
+    } else {
+        const typename Pair<T>::type a = *reinterpret_cast<const typename Pair<T>::type *>(p);
+        v[0] = a.x;
+        v[1] = a.y;
+    }
+}
+
+template <typename T, int VEC>
+__device__ __forceinline__ void store_vec_nt(T *p, const T (&v)[VEC]) {
+    if constexpr (VEC == 1) {
+        __builtin_nontemporal_store(v[0], p);
+    } else {
+        typename Pair<T>::type a;
+        a.x = v[0];
+        a.y = v[1];
+        __builtin_nontemporal_store(a, reinterpret_cast<typename Pair<T>::type *>(p));
+    }
+}
+
+__device__ __forceinline__ int align16(int b) { return (b + 15) / 16 * 16; }
+
+// Copies the plan blob into LDS, eight 16-byte loads in flight per thread.
+__device__ __forceinline__ void stage(unsigned char *lds, const unsigned char *blob, int bytes) {
+    typedef unsigned int U4 __attribute__((ext_vector_type(4)));
+    constexpr int U = 8;
+    const U4 *src = reinterpret_cast<const U4 *>(blob);
+    U4 *dst = reinterpret_cast<U4 *>(lds);
+    const int total = bytes / 16, step = blockDim.x;
+    int i = threadIdx.x;
+    for (; i + (U - 1) * step < total; i += U * step) {
+        U4 v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) v[u] = src[i + u * step];
+#pragma unroll
+        for (int u = 0; u < U; ++u) dst[i + u * step] = v[u];
+    }
+    for (; i < total; i += step) dst[i] = src[i];
+}
+
+struct SepArgs {
+    int fac_bytes, spk_bytes, scf_bytes, sinv_bytes, map_bytes;
+    int n, P, Nr, S, ngroups, periodic, flags;
+    int64_t m;
+};
+
+// Z = S^{-1} Yhat for the group on the matrix cores: 16 x 16 output tiles of
+// v_mfma_f64_16x16x4f64 shared out over the waves (lane l holds
+// A[l % 16][l / 16] and B[l / 16][l % 16]; item r of the result is
+// D[4 r + l / 16][l % 16]).  Column s of Yhat / Z is at red / z + s * ldr.
+__device__ __forceinline__ void sep_mma(const double *sinv, const double *red, double *z, int Nr, int S, int ldr) {
+    const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave, nwaves = blockDim.x / kWave;
+    const int mt = (Nr + 15) / 16, ntiles = mt * ((S + 15) / 16);
+    const int lr = lane % 16, lk = lane / 16;
+    for (int tile = wave; tile < ntiles; tile += nwaves) {
+        const int i0 = (tile % mt) * 16, j0 = (tile / mt) * 16;
+        const int i = i0 + lr, j = j0 + lr;
+        const double *arow = sinv + (size_t)min(i, Nr - 1) * Nr;
+        const double *bcol = red + min(j, S - 1) * ldr;
+        D4 acc = {0.0, 0.0, 0.0, 0.0};
+        for (int k0 = 0; k0 < Nr; k0 += 4) {
+            const int k = k0 + lk, kc = min(k, Nr - 1);
+            const bool kin = k < Nr;
+            const double a = (kin && i < Nr) ? arow[kc] : 0.0;
+            const double b = (kin && j < S) ? bcol[kc] : 0.0;
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int row = i0 + 4 * r + lk;
+            if (row < Nr && j < S) z[j * ldr + row] = acc[r];
+        }
+    }
+}
+
+// LDS layout after the blob: tops [S][P][H], red [S][ldr], z [S][ldr].
+template <typename T, int H>
+__host__ __device__ __forceinline__ int sep_top_bytes(int S, int P) {
+    return (S * P * H * (int)sizeof(T) + 15) / 16 * 16;
+}
+template <typename T>
+__host__ __device__ __forceinline__ int sep_red_bytes(int S, int Nr) {
+    return (S * (Nr + 1) * (int)sizeof(T) + 15) / 16 * 16;
+}
+
+// Compiler-only fence: `v` must be computed here, and no memory access moves
+// across (emits no instruction).  Keeps the coefficient reads of later rows
+// from being hoisted to the start of a loop, where they would hold every
+// row's coefficients in registers at once.
+template <typename T>
+__device__ __forceinline__ void pin(T &v) {
+    asm volatile("" : "+v"(v) : : "memory");
+}
+
+constexpr int G = 4;  // rows per coefficient group
+
+// The block's forward and backward sweeps (Sections 3.1 / 4.1) over VEC
+// systems in registers, with the block's factor rows from LDS.
+template <int KIND, typename T, int LB, int VEC>
+__device__ __forceinline__ void block_sweeps(const typename RowOf<KIND, T>::type *fr, T (&x)[LB][VEC]) {
+    constexpr int NG = LB / G;
+    if constexpr (KIND == SBS_TRI) {
+        T cf[2][G][2];
+        T y1[VEC];
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) y1[v] = T(0);
+#pragma unroll
+        for (int u = 0; u < G; ++u) cf[0][u][0] = fr[u].a_s, cf[0][u][1] = fr[u].inv;
+#pragma unroll
+        for (int g = 0; g < NG; ++g) {
+            if (g + 1 < NG) {
+#pragma unroll
+                for (int u = 0; u < G; ++u)
+                    cf[(g + 1) & 1][u][0] = fr[(g + 1) * G + u].a_s, cf[(g + 1) & 1][u][1] = fr[(g + 1) * G + u].inv;
+            }
+#pragma unroll
+            for (int u = 0; u < G; ++u)
+#pragma unroll
+                for (int v = 0; v < VEC; ++v)  // y_i = d_i / den_i - (a_i / den_i) y_{i-1}
+                    y1[v] = x[g * G + u][v] = fma(-cf[g & 1][u][0], y1[v], x[g * G + u][v] * cf[g & 1][u][1]);
+            pin(y1[0]);
+        }
+        T ch[2][G];
+        T x1[VEC];
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) x1[v] = T(0);
+#pragma unroll
+        for (int u = 0; u < G; ++u) ch[(NG - 1) & 1][u] = fr[LB - 1 - u].chat;
+#pragma unroll
+        for (int g = NG - 1; g >= 0; --g) {
+            if (g > 0) {
+#pragma unroll
+                for (int u = 0; u < G; ++u) ch[(g - 1) & 1][u] = fr[g * G - 1 - u].chat;
+            }
+#pragma unroll
+            for (int u = 0; u < G; ++u) {
+                const int t = g * G + G - 1 - u;
+#pragma unroll
+                for (int v = 0; v < VEC; ++v)  // x_i = y_i - chat_i x_{i+1}
+                    x1[v] = x[t][v] = fma(-ch[g & 1][u], x1[v], x[t][v]);
+            }
+            pin(x1[0]);
+        }
+    } else {
+        T cf[2][G][3];
+        T g1[VEC], g2[VEC];
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) g1[v] = g2[v] = T(0);
+#pragma unroll
+        for (int u = 0; u < G; ++u) cf[0][u][0] = fr[u].eps_s, cf[0][u][1] = fr[u].beta_s, cf[0][u][2] = fr[u].inv;
+#pragma unroll
+        for (int g = 0; g < NG; ++g) {
+            if (g + 1 < NG) {
+#pragma unroll
+                for (int u = 0; u < G; ++u) {
+                    const int t = (g + 1) * G + u;
+                    cf[(g + 1) & 1][u][0] = fr[t].eps_s;
+                    cf[(g + 1) & 1][u][1] = fr[t].beta_s;
+                    cf[(g + 1) & 1][u][2] = fr[t].inv;
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < G; ++u)
+#pragma unroll
+                for (int v = 0; v < VEC; ++v) {  // g_i = (f_i - eps_i g_{i-2} - beta_i g_{i-1}) / alpha_i
+                    const T *c = cf[g & 1][u];
+                    const T gg = fma(-c[1], g1[v], fma(-c[0], g2[v], x[g * G + u][v] * c[2]));
+                    g2[v] = g1[v];
+                    g1[v] = gg;
+                    x[g * G + u][v] = gg;
+                }
+            pin(g1[0]);
+        }
+        T cb[2][G][2];
+        T x1[VEC], x2[VEC];
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) x1[v] = x2[v] = T(0);
+#pragma unroll
+        for (int u = 0; u < G; ++u) cb[(NG - 1) & 1][u][0] = fr[LB - 1 - u].gamma, cb[(NG - 1) & 1][u][1] = fr[LB - 1 - u].delta;
+#pragma unroll
+        for (int g = NG - 1; g >= 0; --g) {
+            if (g > 0) {
+#pragma unroll
+                for (int u = 0; u < G; ++u) {
+                    const int t = g * G - 1 - u;
+                    cb[(g - 1) & 1][u][0] = fr[t].gamma;
+                    cb[(g - 1) & 1][u][1] = fr[t].delta;
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < G; ++u) {
+                const int t = g * G + G - 1 - u;
+#pragma unroll
+                for (int v = 0; v < VEC; ++v) {  // x_i = g_i - gamma_i x_{i+1} - delta_i x_{i+2}
+                    const T xx = fma(-cb[g & 1][u][0], x1[v], fma(-cb[g & 1][u][1], x2[v], x[t][v]));
+                    x2[v] = x1[v];
+                    x1[v] = xx;
+                    x[t][v] = xx;
+                }
+            }
+            pin(x1[0]);
+        }
+    }
+}
+
+// flags: bit 0 XCD-grouped order of the groups (the workgroups a chiplet
+// runs at once take adjacent groups), bit 1 next-group loads issued during
+// the stores of the current one.
+template <int KIND, typename T, int LB, int VEC, int MAXT>
+__global__ __launch_bounds__(MAXT) void k_sep(const unsigned char *__restrict__ blob, SepArgs a, const T *in,
+                                              T *out) {
+    using Row = typename RowOf<KIND, T>::type;
+    constexpr int H = KIND / 2, NB = 2 * H + 1, NI = LB - H;
+    constexpr bool MMA = sizeof(T) == 8;
+    extern __shared__ __align__(16) unsigned char lds[];
+    const int P = a.P, Nr = a.Nr, S = a.S, n = a.n;
+    const int blob_bytes = a.fac_bytes + a.spk_bytes + a.scf_bytes + a.sinv_bytes + a.map_bytes;
+    stage(lds, blob, blob_bytes);
+    const Row *lfac = reinterpret_cast<const Row *>(lds);
+    const T *lspk = reinterpret_cast<const T *>(lds + a.fac_bytes);
+    const T *lscf = reinterpret_cast<const T *>(lds + a.fac_bytes + a.spk_bytes);
+    const T *lsinv = reinterpret_cast<const T *>(lds + a.fac_bytes + a.spk_bytes + a.scf_bytes);
+    const int *lmap = reinterpret_cast<const int *>(lds + a.fac_bytes + a.spk_bytes + a.scf_bytes + a.sinv_bytes);
+    const int ldr = Nr + 1;  // odd stride: the systems' columns fall in different banks
+    T *ltop = reinterpret_cast<T *>(lds + blob_bytes);
+    T *lred = reinterpret_cast<T *>(lds + blob_bytes + sep_top_bytes<T, H>(S, P));
+    T *lz = reinterpret_cast<T *>(lds + blob_bytes + sep_top_bytes<T, H>(S, P) + sep_red_bytes<T>(S, Nr));
+    __syncthreads();
+
+    const int Ls = S / VEC;  // lanes per block row
+    const int l = threadIdx.x, p = l / Ls, sl = l - p * Ls;
+    const int r0 = p * LB;
+    const int q = lmap[p];
+    const Row *fr = lfac + q * LB;
+    const T *sp = lspk + q * LB * 2 * H;
+    const T *cf = lscf + q * H * NB;
+    const bool has_sep = a.periodic || p < P - 1, has_prev = a.periodic || p > 0;
+    const int pn = p == P - 1 ? 0 : p + 1, pp = p == 0 ? P - 1 : p - 1;
+    const int s0 = sl * VEC;  // the lane's first system within the group
+    const int64_t m = a.m;
+    const bool full = r0 + LB <= n;
+    const bool prefetch = (a.flags & 2) != 0;
+    const int grid = gridDim.x;
+    int b = blockIdx.x;
+    if ((a.flags & 1) && grid % 8 == 0) b = (b % 8) * (grid / 8) + b / 8;
+
+    T x[LB][VEC];
+    // lanes past the last system take the last VEC systems: same values, same
+    // addresses, so their duplicate stores are harmless
+    auto col = [&](int g) { return min((int64_t)g * S + s0, m - VEC); };
+    auto load_group = [&](int g) {
+        const T *src = in + (int64_t)r0 * m + col(g);
+        if (full) {
+#pragma unroll
+            for (int t = 0; t < LB; ++t) load_vec<T, VEC>(src + (int64_t)t * m, x[t]);
+        } else {
+#pragma unroll
+            for (int t = 0; t < LB; ++t) {
+                if (r0 + t < n) {
+                    load_vec<T, VEC>(src + (int64_t)t * m, x[t]);
+                } else {
+#pragma unroll
+                    for (int v = 0; v < VEC; ++v) x[t][v] = T(0);
+                }
+            }
+        }
+    };
+
+    int g = b;
+    if (g < a.ngroups) load_group(g);
+    for (; g < a.ngroups; g += grid) {
+        T fsep[H][VEC];
+#pragma unroll
+        for (int c = 0; c < H; ++c)
+#pragma unroll
+            for (int v = 0; v < VEC; ++v) fsep[c][v] = x[NI + c][v];
+        // 1. block sweeps (Section 3.1 / 4.1 recurrences, block factor);
+        // each group of G rows reads its coefficients while the previous
+        // group computes
+        block_sweeps<KIND, T, LB, VEC>(fr, x);
+        // 2. first H values of the block solution, for the previous block's separator
+#pragma unroll
+        for (int v = 0; v < VEC; ++v)
+#pragma unroll
+            for (int c = 0; c < H; ++c) ltop[((s0 + v) * P + p) * H + c] = x[c][v];
+        __syncthreads();
+        // 3. separator right-hand sides
+        if (has_sep) {
+#pragma unroll
+            for (int v = 0; v < VEC; ++v)
+#pragma unroll
+                for (int c = 0; c < H; ++c) {
+                    T yh = fsep[c][v];
+#pragma unroll
+                    for (int d = 0; d < NB; ++d) {
+                        const int t = NI + c + d - H;  // column relative to the block (compile time)
+                        if (t < NI)
+                            yh = fma(-cf[c * NB + d], x[t < NI ? t : 0][v], yh);
+                        else if (t >= LB)
+                            yh = fma(-cf[c * NB + d], ltop[((s0 + v) * P + pn) * H + (t - LB)], yh);
+                    }
+                    lred[(s0 + v) * ldr + H * p + c] = yh;
+                }
+        }
+        __syncthreads();
+        // 4. separators
+        T zr[H][VEC], zl[H][VEC];
+        if (Nr == 0) {
+#pragma unroll
+            for (int c = 0; c < H; ++c)
+#pragma unroll
+                for (int v = 0; v < VEC; ++v) zr[c][v] = zl[c][v] = T(0);
+        } else if (MMA && blockDim.x % kWave == 0) {
+            if constexpr (MMA) sep_mma(lsinv, lred, lz, Nr, S, ldr);
+            __syncthreads();
+#pragma unroll
+            for (int c = 0; c < H; ++c)
+#pragma unroll
+                for (int v = 0; v < VEC; ++v) {
+                    // indices stay inside the separators even where unused
+                    const T zo = lz[(s0 + v) * ldr + (has_sep ? H * p + c : 0)];
+                    const T zp = lz[(s0 + v) * ldr + (has_prev ? H * pp + c : 0)];
+                    zr[c][v] = has_sep ? zo : T(0);
+                    zl[c][v] = has_prev ? zp : T(0);
+                }
+        } else {
+            // rows of S^{-1} for the own and the previous separator (a block
+            // without one reads the other's rows and discards the result)
+            const T *rr = lsinv + (size_t)H * (has_sep ? p : pp) * Nr;
+            const T *rl = lsinv + (size_t)H * (has_prev ? pp : p) * Nr;
+            T ar[H][VEC], al[H][VEC];
+#pragma unroll
+            for (int c = 0; c < H; ++c)
+#pragma unroll
+                for (int v = 0; v < VEC; ++v) ar[c][v] = al[c][v] = T(0);
+            for (int k = 0; k < Nr; ++k) {
+#pragma unroll
+                for (int v = 0; v < VEC; ++v) {
+                    const T y = lred[(s0 + v) * ldr + k];
+#pragma unroll
+                    for (int c = 0; c < H; ++c) {
+                        ar[c][v] = fma(rr[c * Nr + k], y, ar[c][v]);
+                        al[c][v] = fma(rl[c * Nr + k], y, al[c][v]);
+                    }
+                }
+            }
+#pragma unroll
+            for (int c = 0; c < H; ++c)
+#pragma unroll
+                for (int v = 0; v < VEC; ++v) {
+                    zr[c][v] = has_sep ? ar[c][v] : T(0);
+                    zl[c][v] = has_prev ? al[c][v] : T(0);
+                }
+        }
+        // 5. correction and stores; the next group's rows are loaded into the
+        // registers as they free up
+        const int gn = g + grid;
+        const bool more = gn < a.ngroups;
+        const bool early = prefetch && more;
+        T *dst = out + (int64_t)r0 * m + col(g);
+        const T *nsrc = in + (int64_t)r0 * m + col(more ? gn : g);
+#pragma unroll
+        for (int t = 0; t < LB; ++t) {
+            T spt[2 * H];
+#pragma unroll
+            for (int k = 0; k < 2 * H; ++k) spt[k] = sp[t * 2 * H + k];
+            T v2[VEC];
+#pragma unroll
+            for (int v = 0; v < VEC; ++v) {
+                T val = x[t][v];
+#pragma unroll
+                for (int c = 0; c < H; ++c) {
+                    val = fma(-spt[c], zr[c][v], val);
+                    val = fma(-spt[H + c], zl[c][v], val);
+                }
+                if (t >= NI) val = has_sep ? zr[t >= NI ? t - NI : 0][v] : val;
+                v2[v] = val;
+            }
+            if (full || r0 + t < n) store_vec_nt<T, VEC>(dst + (int64_t)t * m, v2);
+            if (early) {
+                if (full || r0 + t < n) {
+                    load_vec<T, VEC>(nsrc + (int64_t)t * m, x[t]);
+                } else {
+#pragma unroll
+                    for (int v = 0; v < VEC; ++v) x[t][v] = T(0);
+                }
+            }
+            if (t % 2 == 1) pin(zr[0][0]);
+        }
+        if (more && !prefetch) load_group(gn);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Launch side.
+
+// Threads a workgroup may have: the lane's LB * VEC values take
+// LB * VEC * sizeof(T) / 4 registers, and a CU's register file holds 512 per
+// lane of one wave per SIMD.
+template <typename T, int LB, int VEC>
+constexpr int sep_maxt() {
+    return LB * VEC * (int)sizeof(T) / 4 <= 64 ? 1024 : 512;
+}
+
+template <int KIND, typename T, int LB, int VEC>
+hipError_t sep_kernel(const void **fn) {
+    auto kern = k_sep<KIND, T, LB, VEC, sep_maxt<T, LB, VEC>()>;
+    // once per instantiation; thread-safe static initialisation, so that
+    // concurrent first launches from several host threads do not race
+    static const hipError_t attr = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
+                                                       hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                       (int)kMaxPartLdsBytes);
+    if (attr != hipSuccess) return attr;
+    *fn = reinterpret_cast<const void *>(kern);
+    return hipSuccess;
+}
+
+// The shapes built: (LB, VEC) with at most 128 registers of values per lane.
+template <int KIND, typename T>
+hipError_t sep_kernel_of(int lb, int vec, const void **fn, int *maxt) {
+    if (lb == 16 && vec == 1) return *maxt = sep_maxt<T, 16, 1>(), sep_kernel<KIND, T, 16, 1>(fn);
+    if (lb == 16 && vec == 2) return *maxt = sep_maxt<T, 16, 2>(), sep_kernel<KIND, T, 16, 2>(fn);
+    if (lb == 32 && vec == 1) return *maxt = sep_maxt<T, 32, 1>(), sep_kernel<KIND, T, 32, 1>(fn);
+    if (lb == 32 && vec == 2) return *maxt = sep_maxt<T, 32, 2>(), sep_kernel<KIND, T, 32, 2>(fn);
+    if (lb == 64 && vec == 1) return *maxt = sep_maxt<T, 64, 1>(), sep_kernel<KIND, T, 64, 1>(fn);
+    if constexpr (sizeof(T) == 4)
+        if (lb == 64 && vec == 2) return *maxt = sep_maxt<T, 64, 2>(), sep_kernel<KIND, T, 64, 2>(fn);
+    return hipErrorInvalidValue;
+}
+
+hipError_t sep_fn(int kind, int tc, int lb, int vec, const void **fn, int *maxt) {
+    const int k = kind == SBS_PENTA ? SBS_PENTA : SBS_TRI;  // periodic blocks are plain tridiagonal
+    if (k == SBS_TRI)
+        return tc == 0 ? sep_kernel_of<SBS_TRI, double>(lb, vec, fn, maxt)
+                       : sep_kernel_of<SBS_TRI, float>(lb, vec, fn, maxt);
+    return tc == 0 ? sep_kernel_of<SBS_PENTA, double>(lb, vec, fn, maxt)
+                   : sep_kernel_of<SBS_PENTA, float>(lb, vec, fn, maxt);
+}
+
+// LDS of one workgroup: the plan, the published block tops, the separator
+// right-hand sides and (FP64: the matrix-core product's output) the separators.
+size_t sep_lds(const SepPlan &sp, int tc, int H, int S) {
+    const int P = sp.P, Nr = sp.Nr;
+    const size_t top = tc == 0 ? (H == 1 ? sep_top_bytes<double, 1>(S, P) : sep_top_bytes<double, 2>(S, P))
+                               : (H == 1 ? sep_top_bytes<float, 1>(S, P) : sep_top_bytes<float, 2>(S, P));
+    const size_t red = tc == 0 ? sep_red_bytes<double>(S, Nr) : sep_red_bytes<float>(S, Nr);
+    return sp.blob_bytes(tc) + top + red * (tc == 0 ? 2 : 1);
+}
+
+int cu_count(int device) {
+    int cus = 256;
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device);
+    return cus;
+}
+
+// Checks one shape and fills in its launch figures; false if it cannot run.
+bool sep_fit(const sbs_lhs *h, int tc, int64_t m, const void *x, int q, int vec, int S, int flags, SepChoice *c) {
+    const SepPlan &sp = h->sep[q];
+    const size_t elem = tc == 0 ? 8 : 4;
+    const int H = h->kind == SBS_PENTA ? 2 : 1;
+    if (!sp.ok || m < vec || S < vec || S % vec) return false;
+    if (vec == 2 && (m % 2 || reinterpret_cast<uintptr_t>(x) % (2 * elem))) return false;
+    const void *fn = nullptr;
+    int maxt = 0;
+    if (sep_fn(h->kind, tc, sp.lb, vec, &fn, &maxt) != hipSuccess) return false;
+    const int threads = (S / vec) * sp.P;
+    if (threads > maxt) return false;
+    const size_t lds = sep_lds(sp, tc, H, S);
+    if (lds > kMaxPartLdsBytes) return false;
+    int wgs = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&wgs, fn, threads, lds) != hipSuccess || wgs < 1) return false;
+    c->plan = q;
+    c->vec = vec;
+    c->S = S;
+    c->threads = threads;
+    c->lds = lds;
+    c->wgs = wgs;
+    c->flags = flags;
+    return true;
+}
+
+}  // namespace
+
+// Default launch options: next-group loads during the stores.
+constexpr int kSepDefaultFlags = 2;
+
+bool choose_sep(const sbs_lhs *h, int tc, int64_t m, const void *x, SepChoice *out) {
+    const size_t elem = tc == 0 ? 8 : 4;
+    const int cus = cu_count(h->device);
+    SepChoice best;
+    int64_t best_key[4] = {-1, -1, -1, -1};
+    for (int q = 2; q >= 0; --q)
+        for (int vec = 2; vec >= 1; --vec)
+            for (int S = 64; S >= 1; S /= 2) {
+                SepChoice c;
+                if (!sep_fit(h, tc, m, x, q, vec, S, kSepDefaultFlags, &c)) continue;
+                const int64_t groups = (m + S - 1) / S;
+                const int64_t engaged = std::min<int64_t>(groups, (int64_t)cus * c.wgs);
+                // rows read in whole 256-byte runs, 16-byte accesses, then
+                // lanes at work (up to 8 waves per CU)
+                const int64_t run = std::min<int64_t>((int64_t)S * elem, 256);
+                const int64_t acc = (int64_t)vec * elem;
+                const int64_t lanes = std::min<int64_t>(engaged * c.threads, (int64_t)cus * 8 * kWave);
+                const int64_t key[4] = {std::min<int64_t>(engaged, cus), run, acc, lanes};
+                if (std::lexicographical_compare(best_key, best_key + 4, key, key + 4)) {
+                    std::copy(key, key + 4, best_key);
+                    best = c;
+                }
+            }
+    if (best.plan < 0) return false;
+    *out = best;
+    return true;
+}
+
+bool sep_fills(const sbs_lhs *h, int tc, int64_t m, const SepChoice &c) {
+    const size_t elem = tc == 0 ? 8 : 4;
+    const int64_t groups = (m + c.S - 1) / c.S;
+    return (size_t)c.S * elem >= 256 && groups >= cu_count(h->device);
+}
+
+bool sep_shape(const sbs_lhs *h, int tc, int64_t m, const void *x, int lb, int vec, int S, int flags, SepChoice *out) {
+    for (int q = 0; q < 3; ++q)
+        if (kPartLbs[q] == lb) return sep_fit(h, tc, m, x, q, vec, S, flags, out);
+    return false;
+}
+
+hipError_t launch_sep(const sbs_lhs *h, const SepChoice &c, int tc, void *x, int64_t m, hipStream_t s) {
+    if (m <= 0) return hipSuccess;
+    const SepPlan &sp = h->sep[c.plan];
+    const void *fn = nullptr;
+    int maxt = 0;
+    if (hipError_t e = sep_fn(h->kind, tc, sp.lb, c.vec, &fn, &maxt); e != hipSuccess) return e;
+    if (c.threads > maxt) return hipErrorInvalidValue;
+    const int64_t ngroups = (m + c.S - 1) / c.S;
+    if (ngroups > 0x7fffffff) return hipErrorInvalidValue;
+    SepArgs a;
+    const bool f64 = tc == 0;
+    a.fac_bytes = (int)(f64 ? sp.fac_bytes64 : sp.fac_bytes32);
+    a.spk_bytes = (int)(f64 ? sp.spk_bytes64 : sp.spk_bytes32);
+    a.scf_bytes = (int)(f64 ? sp.scf_bytes64 : sp.scf_bytes32);
+    a.sinv_bytes = (int)(f64 ? sp.sinv_bytes64 : sp.sinv_bytes32);
+    a.map_bytes = (int)sp.map_bytes;
+    a.n = (int)h->n;
+    a.P = sp.P;
+    a.Nr = sp.Nr;
+    a.S = c.S;
+    a.ngroups = (int)ngroups;
+    a.periodic = sp.periodic ? 1 : 0;
+    a.flags = c.flags;
+    a.m = m;
+    const int grid = (int)std::min<int64_t>(ngroups, (int64_t)cu_count(h->device) * std::max(1, c.wgs));
+    const unsigned char *blob = static_cast<const unsigned char *>(f64 ? sp.blob64 : sp.blob32);
+    void *args[] = {&blob, &a, &x, &x};
+    return hipLaunchKernel(fn, dim3(grid), dim3(c.threads), args, c.lds, s);
+}
+
+}  // namespace sbs

@@ -73,6 +73,8 @@ def lib() -> ctypes.CDLL:
         "sbs_solve_batch": ([vp, vp, i64, i32, vp], i32),
         "sbs_solve_batch_variant": ([vp, vp, i64, i32, i32, vp], i32),
         "sbs_auto_variant": ([vp, i64, i32, P(i32)], i32),
+        "sbs_solve_batch_partition": ([vp, vp, i64, i32, i32, i32, i32, i32, i32, vp], i32),
+        "sbs_partition_shape": ([vp, i64, i32, vp, P(i32), P(i32), P(i32), P(i32)], i32),
         "sbs_solve_batch_refined": ([vp, vp, vp, i64, i32, vp, sz, vp], i32),
         "sbs_refined_workspace_bytes": ([vp, i64], sz),
         "sbs_solve_batch_refined_noalloc": ([vp, vp, vp, i64, i32, vp], i32),
@@ -206,6 +208,27 @@ def sbs_auto_variant(h: int, m: int, dtype: int = SBS_F64) -> int:
     v = ctypes.c_int32()
     _check(lib().sbs_auto_variant(h, m, dtype, ctypes.byref(v)), "sbs_auto_variant")
     return v.value
+
+
+def sbs_solve_batch_partition(h: int, rhs: torch.Tensor, form: int, lb: int, vec: int, S: int, flags: int = 0,
+                              stream=None) -> torch.Tensor:
+    """In-place partitioned solve with an explicit shape (form 0 pair, 1 separator)."""
+    _, n, _ = sbs_handle_info(h)
+    p = _rhs(rhs, n)
+    _check(lib().sbs_solve_batch_partition(h, p, rhs.shape[1], _dtype_code(rhs), form, lb, vec, S, flags,
+                                           _stream(stream)), "sbs_solve_batch_partition")
+    return rhs
+
+
+def sbs_partition_shape(h: int, rhs: torch.Tensor):
+    """(form, lb, vec, S) of the partitioned shape AUTO runs for rhs, or None."""
+    _, n, _ = sbs_handle_info(h)
+    out = [ctypes.c_int32() for _ in range(4)]
+    st = lib().sbs_partition_shape(h, rhs.shape[1], _dtype_code(rhs), rhs.data_ptr(), *[ctypes.byref(o) for o in out])
+    if st == 7:
+        return None
+    _check(st, "sbs_partition_shape")
+    return tuple(o.value for o in out)
 
 
 def sbs_refined_workspace_bytes(h: int, m: int) -> int:

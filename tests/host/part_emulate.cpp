@@ -6,7 +6,8 @@
 //   part_emulate in.bin out.bin
 // in:  int32 kind, int64 n, int64 m, bands (3 or 5 x n doubles), rhs (n x m)
 // out: per block length 16, 32, 64: int32 lb (0 if no plan), P, D, Nr, then
-//      the n x m solution (only when the plan exists)
+//      the n x m solution (only when the plan exists); first for the pair
+//      plans, then for the separator plans
 #include <cstdio>
 #include <cstdlib>
 #include <vector>
@@ -60,6 +61,68 @@ void emulate(const sbs_lhs &h, const PartPlan &pp, const double *rhs, int64_t m,
     }
 }
 
+// The separator plan, step for step as its kernel runs it: block sweeps
+// (separator rows pass through), separator right-hand sides from the
+// separator rows' couplings, separators from the stored inverse of S,
+// interior correction with the spikes.
+template <typename Row, typename Solve>
+void emulate_sep(const sbs_lhs &h, const SepPlan &pp, const double *rhs, int64_t m, double *x, Solve solve) {
+    const int H = h.kind == SBS_PENTA ? 2 : 1, NB = 2 * H + 1, lb = pp.lb, P = pp.P, Nr = pp.Nr;
+    const unsigned char *blob = static_cast<const unsigned char *>(pp.blob64);
+    const Row *fac = reinterpret_cast<const Row *>(blob);
+    const double *spk = reinterpret_cast<const double *>(blob + pp.fac_bytes64);
+    const double *scf = reinterpret_cast<const double *>(blob + pp.fac_bytes64 + pp.spk_bytes64);
+    const double *sinv = reinterpret_cast<const double *>(blob + pp.fac_bytes64 + pp.spk_bytes64 + pp.scf_bytes64);
+    const int *map = reinterpret_cast<const int *>(blob + pp.fac_bytes64 + pp.spk_bytes64 + pp.scf_bytes64 +
+                                                   pp.sinv_bytes64);
+    const int64_t n = h.n;
+    auto has_sep = [&](int p) { return pp.periodic || p < P - 1; };
+    auto has_prev = [&](int p) { return pp.periodic || p >= 1; };
+    auto prev = [&](int p) { return p == 0 ? P - 1 : p - 1; };
+    auto next = [&](int p) { return p == P - 1 ? 0 : p + 1; };
+    std::vector<double> g((size_t)P * lb), f((size_t)P * lb), yh(Nr > 0 ? Nr : 1), z(Nr > 0 ? Nr : 1);
+    for (int64_t j = 0; j < m; ++j) {
+        for (int64_t i = 0; i < (int64_t)P * lb; ++i) f[i] = g[i] = i < n ? rhs[i * m + j] : 0.0;
+        for (int p = 0; p < P; ++p) solve(lb, fac + (int64_t)map[p] * lb, g.data() + (int64_t)p * lb);
+        for (int p = 0; p < P; ++p) {
+            if (!has_sep(p)) continue;
+            for (int c = 0; c < H; ++c) {
+                double v = f[(int64_t)p * lb + lb - H + c];
+                for (int d = 0; d < NB; ++d) {
+                    const int t = lb - H + c + d - H;
+                    const double cf = scf[((size_t)map[p] * H + c) * NB + d];
+                    if (t < lb - H) v -= cf * g[(int64_t)p * lb + t];
+                    else if (t >= lb) v -= cf * g[(int64_t)next(p) * lb + t - lb];
+                }
+                yh[H * p + c] = v;
+            }
+        }
+        for (int r = 0; r < Nr; ++r) {
+            double v = 0.0;
+            for (int k = 0; k < Nr; ++k) v += sinv[(size_t)r * Nr + k] * yh[k];
+            z[r] = v;
+        }
+        for (int p = 0; p < P; ++p) {
+            const double *sp = spk + (size_t)map[p] * lb * 2 * H;
+            for (int t = 0; t < lb; ++t) {
+                const int64_t i = (int64_t)p * lb + t;
+                if (i >= n) continue;
+                double v;
+                if (has_sep(p) && t >= lb - H) {
+                    v = z[H * p + t - (lb - H)];
+                } else {
+                    v = g[i];
+                    for (int c = 0; c < H; ++c) {
+                        if (has_sep(p)) v -= sp[t * 2 * H + c] * z[H * p + c];
+                        if (has_prev(p)) v -= sp[t * 2 * H + H + c] * z[H * prev(p) + c];
+                    }
+                }
+                x[i * m + j] = v;
+            }
+        }
+    }
+}
+
 int main(int argc, char **argv) {
     if (argc != 3) return 2;
     FILE *f = std::fopen(argv[1], "rb");
@@ -87,6 +150,17 @@ int main(int argc, char **argv) {
             emulate<TriRow<double>>(h, pp, rhs.data(), m, x.data(), solve_tri_rows);
         else
             emulate<PentaRow<double>>(h, pp, rhs.data(), m, x.data(), solve_penta_rows);
+        std::fwrite(x.data(), 8, x.size(), o);
+    }
+    for (int q = 0; q < 3; ++q) {
+        const SepPlan &pp = h.sep[q];
+        int32_t hdr[4] = {pp.ok ? pp.lb : 0, pp.P, pp.D, pp.Nr};
+        std::fwrite(hdr, 4, 4, o);
+        if (!pp.ok) continue;
+        if (kind != SBS_PENTA)
+            emulate_sep<TriRow<double>>(h, pp, rhs.data(), m, x.data(), solve_tri_rows);
+        else
+            emulate_sep<PentaRow<double>>(h, pp, rhs.data(), m, x.data(), solve_penta_rows);
         std::fwrite(x.data(), 8, x.size(), o);
     }
     std::fclose(o);

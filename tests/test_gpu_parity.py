@@ -72,6 +72,29 @@ def partition_available(kind, n, elem=8, m=1 << 20, cus=256):
     return False
 
 
+def separator_available(kind, n, elem=8, m=1 << 20):
+    """Mirror of the library's rule for the separator form (matrices whose
+    blocks all differ): some block length lb in (16, 32, 64) with
+    P = ceil(n/lb) <= 64 blocks and at most 96 separator unknowns h(P-1),
+    whose block factors + spikes + separator band rows + inverse of the
+    separator system + block map, with the published block tops and the
+    separator right-hand sides (and, in FP64, the separators) of one
+    system per workgroup, fit in 160 KiB of LDS."""
+    h = kind // 2
+    row = (4 if kind == 3 else 8) * elem
+    r16 = lambda v: -(-v // 16) * 16
+    for lb in (16, 32, 64):
+        P = -(-n // lb)
+        Nr = h * (P - 1)
+        if P > 64 or Nr > 96:
+            continue
+        blob = (r16(P * lb * row) + r16(P * lb * 2 * h * elem) + r16(P * h * (2 * h + 1) * elem)
+                + r16(Nr * Nr * elem) + r16(P * 4))
+        if blob + r16(P * h * elem) + r16((Nr + 1) * elem) * (2 if elem == 8 else 1) <= 160 * 1024:
+            return True
+    return False
+
+
 def gpu_solve(kind, B, rhs, variant=sbs.VARIANT_AUTO, dtype=torch.float64):
     with sbs.SharedLhs(kind, B) as lhs:
         x = torch.from_numpy(np.ascontiguousarray(rhs)).to(DEV, dtype)
@@ -95,7 +118,8 @@ def test_fp64_matches_oracle(kind, variant, n, m):
     B = bands_for(kind, n, 1000 * kind + n)
     rhs = np.random.default_rng(n * 7 + m).uniform(-1, 1, (n, m))
     if (variant == sbs.VARIANT_CHUNKED and not chunked_fits(kind, n)) or \
-            (variant == sbs.VARIANT_PARTITION and not partition_available(kind, n, m=m)):
+            (variant == sbs.VARIANT_PARTITION and not partition_available(kind, n, m=m)
+             and not separator_available(kind, n, m=m)):
         with pytest.raises(sbs.SbsError) as e:
             gpu_solve(kind, B, rhs, variant)
         assert e.value.status == 1
@@ -130,8 +154,12 @@ def test_penta_partition_tiny_batches(n, m):
 
 
 def test_partition_plan_rule():
-    # penta n = 2048 needs 31 blocks of 64 rows: 120 interface unknowns, over the limit
+    # penta n = 2048 needs 31 blocks of 64 rows: 120 interface unknowns, over the
+    # pair form's limit; the separator form has 62, but with every block
+    # different its 32 block factors and spikes exceed the LDS
     assert not partition_available(5, 2048) and partition_available(5, 1024) and partition_available(3, 2048)
+    assert not separator_available(5, 2048) and separator_available(5, 1024) and separator_available(3, 2048)
+    assert separator_available(3, 3000, elem=4) and not partition_available(3, 3000, elem=4)
 
 
 @pytest.mark.parametrize("kind", [3, 5])
@@ -140,7 +168,7 @@ def test_auto_variant_query(kind, n):
     # what AUTO runs: partitioned when a plan exists, else resident / chunked / stream
     with sbs.SharedLhs(kind, bands_for(kind, n, n)) as lhs:
         for dtype, elem in ((sbs.SBS_F64, 8), (sbs.SBS_F32, 4)):
-            if partition_available(kind, n, elem, m=1000):
+            if partition_available(kind, n, elem, m=1000) or separator_available(kind, n, elem, m=1000):
                 want = sbs.VARIANT_PARTITION
             elif n <= 64:
                 want = sbs.VARIANT_RESIDENT
@@ -154,7 +182,7 @@ def test_auto_variant_query(kind, n):
 @pytest.mark.parametrize("kind", [3, 5])
 @pytest.mark.parametrize("n,m", [(64, 4096), (65, 33), (129, 1000), (500, 17), (1024, 3000), (2048, 130)])
 def test_partition_fp32(kind, n, m):
-    if not partition_available(kind, n, elem=4, m=m):
+    if not partition_available(kind, n, elem=4, m=m) and not separator_available(kind, n, elem=4, m=m):
         pytest.skip("no partition plan")
     B = bands_for(kind, n, 9 + n)
     rhs = np.random.default_rng(n + m).uniform(-1, 1, (n, m)).astype(np.float32)

@@ -39,8 +39,21 @@ def chunked_fits(n, elem=8):
 
 def partition_available(n):
     """Periodic plans: n a whole number P >= 2 of blocks of 16, 32 or 64 rows,
-    at most 90 interface unknowns (2 per block: the wrap adds one pair)."""
-    return any(n % lb == 0 and 2 <= n // lb and 2 * (n // lb) <= 90 for lb in (16, 32, 64))
+    and either at most 90 interface unknowns in the pair form (2 per block:
+    the wrap adds one pair) or, in the separator form, at most 64 blocks
+    (one separator each) whose factors, spikes and separator inverse fit in
+    the LDS with room for one system (the ring bands here differ per row)."""
+    r16 = lambda v: -(-v // 16) * 16
+    for lb in (16, 32, 64):
+        P = n // lb
+        if n % lb or P < 2:
+            continue
+        if 2 * P <= 90:
+            return True
+        blob = r16(P * lb * 32) + r16(P * lb * 16) + r16(P * 3 * 8) + r16(P * P * 8) + r16(P * 4)
+        if P <= 64 and blob + r16(P * 8) + 2 * r16((P + 1) * 8) <= 160 * 1024:
+            return True
+    return False
 
 
 def gpu_solve(B, rhs, variant=sbs.VARIANT_AUTO, dtype=torch.float64):

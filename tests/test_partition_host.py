@@ -35,6 +35,16 @@ def exe(tmp_path_factory):
 
 
 def run(exe, tmp_path, kind, B, rhs):
+    """The pair plans (block lengths 16, 32, 64): (lb or 0, P, D, Nr, x)."""
+    return run_all(exe, tmp_path, kind, B, rhs)[0]
+
+
+def run_sep(exe, tmp_path, kind, B, rhs):
+    """The separator plans (block lengths 16, 32, 64): (lb or 0, P, D, Nr, x)."""
+    return run_all(exe, tmp_path, kind, B, rhs)[1]
+
+
+def run_all(exe, tmp_path, kind, B, rhs):
     n, m = rhs.shape
     src, dst = str(tmp_path / "in.bin"), str(tmp_path / "out.bin")
     with open(src, "wb") as f:
@@ -46,11 +56,11 @@ def run(exe, tmp_path, kind, B, rhs):
     assert r.returncode == 0, r.stderr
     plans = []
     with open(dst, "rb") as f:
-        for _ in range(3):
+        for _ in range(6):
             lb, P, D, Nr = struct.unpack("<4i", f.read(16))
             x = np.frombuffer(f.read(8 * n * m), dtype=np.float64).reshape(n, m) if lb else None
             plans.append((lb, P, D, Nr, x))
-    return plans
+    return plans[:3], plans[3:]
 
 
 def colrel(x, ref):
@@ -167,5 +177,78 @@ def test_ill_conditioned_plans_stay_within_the_parity_bar(exe, tmp_path, n):
     rhs = np.random.default_rng(3).uniform(-1, 1, (n, 4))
     ref = oracle.solve(3, B, rhs)
     for lb, P, D, Nr, x in run(exe, tmp_path, 3, B, rhs):
+        if lb:
+            assert colrel(x, ref) <= 1e-12, (lb, colrel(x, ref))
+
+
+# ---------------------------------------------------------------------------
+# Separator plans: interior blocks, Schur complement on the separator rows.
+
+@pytest.mark.parametrize("kind", [3, 5])
+@pytest.mark.parametrize("n", [1, 2, 3, 5, 16, 17, 31, 33, 64, 100, 256, 1000, 1024, 2047, 2048, 3000, 4096])
+def test_separator_plan_solves_like_the_oracle(exe, tmp_path, kind, n):
+    B = dominant(kind, n, 70 + n)
+    rhs = np.random.default_rng(n + 1).uniform(-1, 1, (n, 3))
+    ref = oracle.solve(kind, B, rhs)
+    h = kind // 2
+    found = 0
+    for want_lb, (lb, P, D, Nr, x) in zip((16, 32, 64), run_sep(exe, tmp_path, kind, B, rhs)):
+        if not lb:
+            continue
+        found += 1
+        assert lb == want_lb and P == -(-n // lb) and Nr == h * (P - 1)
+        assert 1 <= D <= P
+        assert colrel(x, ref) <= 1e-13, (lb, P, D, colrel(x, ref))
+    # half the interface of the pair form: 32-row pentadiagonal blocks up to
+    # n = 1536, 64-row blocks up to n = 3072
+    assert found >= 1 or n > 3072
+
+
+@pytest.mark.parametrize("kind,n,lb", [(5, 1024, 32), (5, 2048, 64), (3, 512, 16), (3, 1000, 32)])
+def test_separator_plan_of_constant_bands_stores_three_blocks(exe, tmp_path, kind, n, lb):
+    B = W.hyperdiffusion_bands(n, 0.5) if kind == 5 else W.diffusion_bands(n, 0.5)
+    rhs = np.random.default_rng(8).uniform(-1, 1, (n, 4))
+    ref = oracle.solve(kind, B, rhs)
+    plan = {p[0]: p for p in run_sep(exe, tmp_path, kind, B, rhs) if p[0]}
+    assert lb in plan
+    _, P, got_d, _, x = plan[lb]
+    assert P > 3 and got_d == 3, (P, got_d)
+    assert colrel(x, ref) <= 1e-13
+
+
+@pytest.mark.parametrize("n", [32, 64, 96, 512, 1024, 2048])
+def test_periodic_separator_plan_solves_like_the_periodic_oracle(exe, tmp_path, n):
+    rng = np.random.default_rng(n + 5)
+    a, c = rng.uniform(-1, 1, n), rng.uniform(-1, 1, n)
+    B = np.stack([a, np.abs(a) + np.abs(c) + rng.uniform(1, 2, n), c])
+    rhs = rng.uniform(-1, 1, (n, 3))
+    ref = oracle.solve(oracle.TRI_PERIODIC, B, rhs)
+    found = 0
+    for want_lb, (lb, P, D, Nr, x) in zip((16, 32, 64), run_sep(exe, tmp_path, 13, B, rhs)):
+        exists = n % want_lb == 0 and n // want_lb >= 2 and n // want_lb <= 64
+        assert lb == (want_lb if exists else 0)
+        if not lb:
+            continue
+        found += 1
+        assert Nr == P
+        assert colrel(x, ref) <= 1e-13, (lb, P)
+    assert found >= 1
+
+
+@pytest.mark.parametrize("n", [256, 1000, 2048])
+def test_separator_plans_with_tiny_block_pivots_are_dropped(exe, tmp_path, n):
+    B = tiny_block_pivot_bands(n)
+    rhs = np.random.default_rng(n).uniform(-1, 1, (n, 2))
+    for lb, P, D, Nr, x in run_sep(exe, tmp_path, 3, B, rhs):
+        if lb:  # a plan whose blocks avoid the tiny pivots may exist; it must be accurate
+            assert colrel(x, oracle.solve(3, B, rhs)) <= 1e-12, lb
+
+
+@pytest.mark.parametrize("n", [1024, 2048])
+def test_ill_conditioned_separator_plans_stay_within_the_parity_bar(exe, tmp_path, n):
+    B = W.zero_outside(np.stack([-np.ones(n), np.full(n, 2.0), -np.ones(n)]))
+    rhs = np.random.default_rng(4).uniform(-1, 1, (n, 4))
+    ref = oracle.solve(3, B, rhs)
+    for lb, P, D, Nr, x in run_sep(exe, tmp_path, 3, B, rhs):
         if lb:
             assert colrel(x, ref) <= 1e-12, (lb, colrel(x, ref))
