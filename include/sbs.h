@@ -175,8 +175,8 @@ sbs_status sbs_solve_batch_variant(sbs_handle h, void *rhs, int64_t m,
  *          per lane (2: one 16-byte FP64 access per row; needs m even and
  *          rhs aligned to 2 elements), S systems per workgroup (a multiple
  *          of vec), flags bit 0: workgroups of one chiplet take adjacent
- *          groups, bit 1: the next group's loads are issued while the
- *          current group is stored.
+ *          groups, bit 2: workgroups start out of step, workgroup b waiting
+ *          (b % 4) * k * 4096 cycles first, with k in bits 8..15.
  * Same arguments and results as sbs_solve_batch otherwise.  A shape that has
  * no plan, exceeds 1024 threads, the register budget or the LDS returns
  * SBS_ERR_INVALID_ARG.

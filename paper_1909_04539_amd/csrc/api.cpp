@@ -285,7 +285,7 @@ sbs_status sbs_solve_batch_partition(sbs_handle h, void *rhs, int64_t m, int32_t
     hipError_t e;
     if (form == 1) {
         SepChoice sc;
-        if (flags < 0 || flags > 3 || !sep_shape(h, t, m, rhs, lb, vec, S, flags, &sc)) return SBS_ERR_INVALID_ARG;
+        if (flags < 0 || flags > 0xffff || !sep_shape(h, t, m, rhs, lb, vec, S, flags, &sc)) return SBS_ERR_INVALID_ARG;
         e = launch_sep(h, sc, t, rhs, m, s);
     } else {
         PartChoice pc;

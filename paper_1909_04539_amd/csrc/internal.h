@@ -210,8 +210,8 @@ hipError_t launch_partition_refine(const sbs_lhs *h, const PartChoice &c, const 
 
 // Separator-partitioned solve (plain solves of interleaved right-hand sides):
 // plan, values per lane (VEC adjacent systems, one access per row), systems
-// per workgroup, launch options (bit 0: XCD-grouped group order, bit 1: the
-// next group's loads issued during the current group's stores).
+// per workgroup, launch options (bit 0: XCD-grouped group order, bit 2:
+// workgroups start out of step by bits 8.. sleeps of 4096 cycles per quarter).
 struct SepChoice {
     int plan = -1, vec = 1, S = 0, threads = 0, flags = 0;
     size_t lds = 0;

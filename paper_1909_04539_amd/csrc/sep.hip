@@ -107,25 +107,31 @@ struct SepArgs {
     int64_t m;
 };
 
-// Z = S^{-1} Yhat for the group on the matrix cores: 16 x 16 output tiles of
+// Z = S^{-1} Yhat for the group on the matrix cores (Yhat = redl + redr, the
+// two parts of the separator right-hand sides): 16 x 16 output tiles of
 // v_mfma_f64_16x16x4f64 shared out over the waves (lane l holds
 // A[l % 16][l / 16] and B[l / 16][l % 16]; item r of the result is
 // D[4 r + l / 16][l % 16]).  Column s of Yhat / Z is at red / z + s * ldr.
-__device__ __forceinline__ void sep_mma(const double *sinv, const double *red, double *z, int Nr, int S, int ldr) {
-    const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave, nwaves = blockDim.x / kWave;
+__device__ __forceinline__ void sep_mma(const double *sinv, const double *redl, const double *redr, double *z, int Nr,
+                                        int S, int ldr) {
+    // the thread's coordinates, made opaque at each call: the tile addresses
+    // below are formed per call rather than kept live across the group loop
+    int tid = threadIdx.x;
+    asm volatile("" : "+v"(tid));
+    const int lane = tid % kWave, wave = __builtin_amdgcn_readfirstlane(tid / kWave), nwaves = blockDim.x / kWave;
     const int mt = (Nr + 15) / 16, ntiles = mt * ((S + 15) / 16);
     const int lr = lane % 16, lk = lane / 16;
     for (int tile = wave; tile < ntiles; tile += nwaves) {
         const int i0 = (tile % mt) * 16, j0 = (tile / mt) * 16;
         const int i = i0 + lr, j = j0 + lr;
         const double *arow = sinv + (size_t)min(i, Nr - 1) * Nr;
-        const double *bcol = red + min(j, S - 1) * ldr;
+        const double *bl = redl + min(j, S - 1) * ldr, *br = redr + min(j, S - 1) * ldr;
         D4 acc = {0.0, 0.0, 0.0, 0.0};
         for (int k0 = 0; k0 < Nr; k0 += 4) {
             const int k = k0 + lk, kc = min(k, Nr - 1);
             const bool kin = k < Nr;
             const double a = (kin && i < Nr) ? arow[kc] : 0.0;
-            const double b = (kin && j < S) ? bcol[kc] : 0.0;
+            const double b = (kin && j < S) ? bl[kc] + br[kc] : 0.0;
             acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
         }
 #pragma unroll
@@ -136,11 +142,8 @@ __device__ __forceinline__ void sep_mma(const double *sinv, const double *red, d
     }
 }
 
-// LDS layout after the blob: tops [S][P][H], red [S][ldr], z [S][ldr].
-template <typename T, int H>
-__host__ __device__ __forceinline__ int sep_top_bytes(int S, int P) {
-    return (S * P * H * (int)sizeof(T) + 15) / 16 * 16;
-}
+// LDS layout after the blob: the two parts of the separator right-hand
+// sides, redL and redR [S][ldr], and (FP64) the separators z [S][ldr].
 template <typename T>
 __host__ __device__ __forceinline__ int sep_red_bytes(int S, int Nr) {
     return (S * (Nr + 1) * (int)sizeof(T) + 15) / 16 * 16;
@@ -155,12 +158,13 @@ __device__ __forceinline__ void pin(T &v) {
     asm volatile("" : "+v"(v) : : "memory");
 }
 
-constexpr int G = 4;  // rows per coefficient group
+constexpr int G = 4;  // rows per coefficient group (2 where registers are short)
 
 // The block's forward and backward sweeps (Sections 3.1 / 4.1) over VEC
 // systems in registers, with the block's factor rows from LDS.
 template <int KIND, typename T, int LB, int VEC>
 __device__ __forceinline__ void block_sweeps(const typename RowOf<KIND, T>::type *fr, T (&x)[LB][VEC]) {
+    // coefficient rows per group: fewer when the block's values fill the registers
     constexpr int NG = LB / G;
     if constexpr (KIND == SBS_TRI) {
         T cf[2][G][2];
@@ -267,8 +271,10 @@ __device__ __forceinline__ void block_sweeps(const typename RowOf<KIND, T>::type
 }
 
 // flags: bit 0 XCD-grouped order of the groups (the workgroups a chiplet
-// runs at once take adjacent groups), bit 1 next-group loads issued during
-// the stores of the current one.
+// runs at once take adjacent groups); bit 2 workgroups start out of step (see
+// below).  (Issuing the next group's loads into registers while the current
+// group is stored was measured slower: each wave's loads then queue behind
+// its stores.)
 template <int KIND, typename T, int LB, int VEC, int MAXT>
 __global__ __launch_bounds__(MAXT) void k_sep(const unsigned char *__restrict__ blob, SepArgs a, const T *in,
                                               T *out) {
@@ -278,31 +284,25 @@ __global__ __launch_bounds__(MAXT) void k_sep(const unsigned char *__restrict__ 
     extern __shared__ __align__(16) unsigned char lds[];
     const int P = a.P, Nr = a.Nr, S = a.S, n = a.n;
     const int blob_bytes = a.fac_bytes + a.spk_bytes + a.scf_bytes + a.sinv_bytes + a.map_bytes;
-    stage(lds, blob, blob_bytes);
     const Row *lfac = reinterpret_cast<const Row *>(lds);
     const T *lspk = reinterpret_cast<const T *>(lds + a.fac_bytes);
     const T *lscf = reinterpret_cast<const T *>(lds + a.fac_bytes + a.spk_bytes);
     const T *lsinv = reinterpret_cast<const T *>(lds + a.fac_bytes + a.spk_bytes + a.scf_bytes);
     const int *lmap = reinterpret_cast<const int *>(lds + a.fac_bytes + a.spk_bytes + a.scf_bytes + a.sinv_bytes);
     const int ldr = Nr + 1;  // odd stride: the systems' columns fall in different banks
-    T *ltop = reinterpret_cast<T *>(lds + blob_bytes);
-    T *lred = reinterpret_cast<T *>(lds + blob_bytes + sep_top_bytes<T, H>(S, P));
-    T *lz = reinterpret_cast<T *>(lds + blob_bytes + sep_top_bytes<T, H>(S, P) + sep_red_bytes<T>(S, Nr));
-    __syncthreads();
+    T *lredl = reinterpret_cast<T *>(lds + blob_bytes);
+    T *lredr = reinterpret_cast<T *>(lds + blob_bytes + sep_red_bytes<T>(S, Nr));
+    T *lz = reinterpret_cast<T *>(lds + blob_bytes + 2 * sep_red_bytes<T>(S, Nr));
+
 
     const int Ls = S / VEC;  // lanes per block row
     const int l = threadIdx.x, p = l / Ls, sl = l - p * Ls;
     const int r0 = p * LB;
-    const int q = lmap[p];
-    const Row *fr = lfac + q * LB;
-    const T *sp = lspk + q * LB * 2 * H;
-    const T *cf = lscf + q * H * NB;
     const bool has_sep = a.periodic || p < P - 1, has_prev = a.periodic || p > 0;
-    const int pn = p == P - 1 ? 0 : p + 1, pp = p == 0 ? P - 1 : p - 1;
+    const int pp = p == 0 ? P - 1 : p - 1;
     const int s0 = sl * VEC;  // the lane's first system within the group
     const int64_t m = a.m;
     const bool full = r0 + LB <= n;
-    const bool prefetch = (a.flags & 2) != 0;
     const int grid = gridDim.x;
     int b = blockIdx.x;
     if ((a.flags & 1) && grid % 8 == 0) b = (b % 8) * (grid / 8) + b / 8;
@@ -330,39 +330,74 @@ __global__ __launch_bounds__(MAXT) void k_sep(const unsigned char *__restrict__ 
     };
 
     int g = b;
+    stage(lds, blob, blob_bytes);
+    // flags bit 2: workgroups start out of step (b % 4 quarter steps of
+    // `stagger` sleeps of 4096 cycles each), so that while some compute their
+    // separators others stream, instead of every CU reaching its compute
+    // phase at the same time
+    if (a.flags & 4) {
+        const int steps = (b % 4) * (a.flags >> 8);
+        for (int i = 0; i < steps; ++i) __builtin_amdgcn_s_sleep(64);
+    }
+    __syncthreads();
     if (g < a.ngroups) load_group(g);
+    const int q = lmap[p];  // stored copy of this block's factor, spikes and separator rows
+    const Row *fr = lfac + q * LB;
+    const T *sp = lspk + q * LB * 2 * H;
+    const T *cf = lscf + q * H * NB;
+    const T *cfp = lscf + lmap[pp] * H * NB;  // the previous block's separator rows
+    // the separator rows' couplings to interior rows, the same for every
+    // group: the own separator's to this block's last rows (c + d < H) and
+    // the previous separator's to this block's first rows (c + d >= 2H)
+    T cl[H][H], cr[H][H];
+#pragma unroll
+    for (int c = 0; c < H; ++c)
+#pragma unroll
+        for (int d = 0; d < H; ++d) {
+            cl[c][d] = (c + d < H) ? cf[c * NB + d] : T(0);
+            cr[c][d] = (2 * H - c + d < NB) ? cfp[c * NB + 2 * H - c + d] : T(0);
+        }
     for (; g < a.ngroups; g += grid) {
-        T fsep[H][VEC];
-#pragma unroll
-        for (int c = 0; c < H; ++c)
-#pragma unroll
-            for (int v = 0; v < VEC; ++v) fsep[c][v] = x[NI + c][v];
+        // the lane's offsets into the separator buffers, made opaque each
+        // group so that the addresses derived from them are formed where they
+        // are used instead of being kept live (and spilled) across the loop
+        int o_own = s0 * ldr + H * p, o_prev = s0 * ldr + H * pp, o_col = s0 * ldr;
+        asm volatile("" : "+v"(o_own), "+v"(o_prev), "+v"(o_col));
+
         // 1. block sweeps (Section 3.1 / 4.1 recurrences, block factor);
         // each group of G rows reads its coefficients while the previous
         // group computes
         block_sweeps<KIND, T, LB, VEC>(fr, x);
-        // 2. first H values of the block solution, for the previous block's separator
+        // 2. the separator right-hand sides in two parts: the previous
+        // separator takes minus its couplings to this block's first rows
+        // (redr), the block's own separator takes f_sep minus its couplings to
+        // this block's last interior rows (redl); one barrier.  (In this order
+        // the first rows' values are dropped before the last rows' are used,
+        // which keeps the FP64 pentadiagonal kernel within its registers.)
+        if (has_prev) {
 #pragma unroll
-        for (int v = 0; v < VEC; ++v)
+            for (int v = 0; v < VEC; ++v)
 #pragma unroll
-            for (int c = 0; c < H; ++c) ltop[((s0 + v) * P + p) * H + c] = x[c][v];
-        __syncthreads();
-        // 3. separator right-hand sides
+                for (int c = 0; c < H; ++c) {
+                    // band d = 2H - c + e of separator row c meets this block's row e
+                    T yh = T(0);
+#pragma unroll
+                    for (int e = 0; e + 2 * H - c < NB; ++e) yh = fma(-cr[c][e], x[e][v], yh);
+                    lredr[o_prev + v * ldr + c] = yh;
+                }
+        }
         if (has_sep) {
 #pragma unroll
             for (int v = 0; v < VEC; ++v)
 #pragma unroll
                 for (int c = 0; c < H; ++c) {
-                    T yh = fsep[c][v];
+                    // separator rows are identity rows of the block factor: the
+                    // sweeps leave their right-hand sides in place
+                    T yh = x[NI + c][v];
+                    // band d < H - c of separator row c meets row NI + c + d - H
 #pragma unroll
-                    for (int d = 0; d < NB; ++d) {
-                        const int t = NI + c + d - H;  // column relative to the block (compile time)
-                        if (t < NI)
-                            yh = fma(-cf[c * NB + d], x[t < NI ? t : 0][v], yh);
-                        else if (t >= LB)
-                            yh = fma(-cf[c * NB + d], ltop[((s0 + v) * P + pn) * H + (t - LB)], yh);
-                    }
-                    lred[(s0 + v) * ldr + H * p + c] = yh;
+                    for (int d = 0; d + c < H; ++d) yh = fma(-cl[c][d], x[NI + c + d - H][v], yh);
+                    lredl[o_own + v * ldr + c] = yh;
                 }
         }
         __syncthreads();
@@ -374,15 +409,15 @@ __global__ __launch_bounds__(MAXT) void k_sep(const unsigned char *__restrict__ 
 #pragma unroll
                 for (int v = 0; v < VEC; ++v) zr[c][v] = zl[c][v] = T(0);
         } else if (MMA && blockDim.x % kWave == 0) {
-            if constexpr (MMA) sep_mma(lsinv, lred, lz, Nr, S, ldr);
+            if constexpr (MMA) sep_mma(lsinv, lredl, lredr, lz, Nr, S, ldr);
             __syncthreads();
 #pragma unroll
             for (int c = 0; c < H; ++c)
 #pragma unroll
                 for (int v = 0; v < VEC; ++v) {
                     // indices stay inside the separators even where unused
-                    const T zo = lz[(s0 + v) * ldr + (has_sep ? H * p + c : 0)];
-                    const T zp = lz[(s0 + v) * ldr + (has_prev ? H * pp + c : 0)];
+                    const T zo = lz[(has_sep ? o_own : o_col) + v * ldr + c];
+                    const T zp = lz[(has_prev ? o_prev : o_col) + v * ldr + c];
                     zr[c][v] = has_sep ? zo : T(0);
                     zl[c][v] = has_prev ? zp : T(0);
                 }
@@ -399,7 +434,7 @@ __global__ __launch_bounds__(MAXT) void k_sep(const unsigned char *__restrict__ 
             for (int k = 0; k < Nr; ++k) {
 #pragma unroll
                 for (int v = 0; v < VEC; ++v) {
-                    const T y = lred[(s0 + v) * ldr + k];
+                    const T y = lredl[o_col + v * ldr + k] + lredr[o_col + v * ldr + k];
 #pragma unroll
                     for (int c = 0; c < H; ++c) {
                         ar[c][v] = fma(rr[c * Nr + k], y, ar[c][v]);
@@ -415,42 +450,37 @@ __global__ __launch_bounds__(MAXT) void k_sep(const unsigned char *__restrict__ 
                     zl[c][v] = has_prev ? al[c][v] : T(0);
                 }
         }
-        // 5. correction and stores; the next group's rows are loaded into the
-        // registers as they free up
-        const int gn = g + grid;
-        const bool more = gn < a.ngroups;
-        const bool early = prefetch && more;
+        // 5. correction and stores
         T *dst = out + (int64_t)r0 * m + col(g);
-        const T *nsrc = in + (int64_t)r0 * m + col(more ? gn : g);
+        // the spikes of G rows per round trip to LDS
+        constexpr int GC = G;
 #pragma unroll
-        for (int t = 0; t < LB; ++t) {
-            T spt[2 * H];
+        for (int gr = 0; gr < LB / GC; ++gr) {
+            T spt[GC][2 * H];
 #pragma unroll
-            for (int k = 0; k < 2 * H; ++k) spt[k] = sp[t * 2 * H + k];
-            T v2[VEC];
+            for (int u = 0; u < GC; ++u)
 #pragma unroll
-            for (int v = 0; v < VEC; ++v) {
-                T val = x[t][v];
+                for (int k = 0; k < 2 * H; ++k) spt[u][k] = sp[(gr * GC + u) * 2 * H + k];
 #pragma unroll
-                for (int c = 0; c < H; ++c) {
-                    val = fma(-spt[c], zr[c][v], val);
-                    val = fma(-spt[H + c], zl[c][v], val);
+            for (int u = 0; u < GC; ++u) {
+                const int t = gr * GC + u;
+                T v2[VEC];
+#pragma unroll
+                for (int v = 0; v < VEC; ++v) {
+                    T val = x[t][v];
+#pragma unroll
+                    for (int c = 0; c < H; ++c) {
+                        val = fma(-spt[u][c], zr[c][v], val);
+                        val = fma(-spt[u][H + c], zl[c][v], val);
+                    }
+                    if (t >= NI) val = has_sep ? zr[t >= NI ? t - NI : 0][v] : val;
+                    v2[v] = val;
                 }
-                if (t >= NI) val = has_sep ? zr[t >= NI ? t - NI : 0][v] : val;
-                v2[v] = val;
+                if (full || r0 + t < n) store_vec_nt<T, VEC>(dst + (int64_t)t * m, v2);
             }
-            if (full || r0 + t < n) store_vec_nt<T, VEC>(dst + (int64_t)t * m, v2);
-            if (early) {
-                if (full || r0 + t < n) {
-                    load_vec<T, VEC>(nsrc + (int64_t)t * m, x[t]);
-                } else {
-#pragma unroll
-                    for (int v = 0; v < VEC; ++v) x[t][v] = T(0);
-                }
-            }
-            if (t % 2 == 1) pin(zr[0][0]);
+            pin(zr[0][0]);
         }
-        if (more && !prefetch) load_group(gn);
+        if (g + grid < a.ngroups) load_group(g + grid);
     }
 }
 
@@ -500,14 +530,11 @@ hipError_t sep_fn(int kind, int tc, int lb, int vec, const void **fn, int *maxt)
                    : sep_kernel_of<SBS_PENTA, float>(lb, vec, fn, maxt);
 }
 
-// LDS of one workgroup: the plan, the published block tops, the separator
-// right-hand sides and (FP64: the matrix-core product's output) the separators.
-size_t sep_lds(const SepPlan &sp, int tc, int H, int S) {
-    const int P = sp.P, Nr = sp.Nr;
-    const size_t top = tc == 0 ? (H == 1 ? sep_top_bytes<double, 1>(S, P) : sep_top_bytes<double, 2>(S, P))
-                               : (H == 1 ? sep_top_bytes<float, 1>(S, P) : sep_top_bytes<float, 2>(S, P));
-    const size_t red = tc == 0 ? sep_red_bytes<double>(S, Nr) : sep_red_bytes<float>(S, Nr);
-    return sp.blob_bytes(tc) + top + red * (tc == 0 ? 2 : 1);
+// LDS of one workgroup: the plan, the two parts of the separator right-hand
+// sides and (FP64: the matrix-core product's output) the separators.
+size_t sep_lds(const SepPlan &sp, int tc, int, int S) {
+    const size_t red = tc == 0 ? sep_red_bytes<double>(S, sp.Nr) : sep_red_bytes<float>(S, sp.Nr);
+    return sp.blob_bytes(tc) + red * (tc == 0 ? 3 : 2);
 }
 
 int cu_count(int device) {
@@ -544,8 +571,8 @@ bool sep_fit(const sbs_lhs *h, int tc, int64_t m, const void *x, int q, int vec,
 
 }  // namespace
 
-// Default launch options: next-group loads during the stores.
-constexpr int kSepDefaultFlags = 2;
+// Default launch options: groups in launch order.
+constexpr int kSepDefaultFlags = 0;
 
 bool choose_sep(const sbs_lhs *h, int tc, int64_t m, const void *x, SepChoice *out) {
     const size_t elem = tc == 0 ? 8 : 4;
