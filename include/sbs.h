@@ -176,7 +176,11 @@ sbs_status sbs_solve_batch_variant(sbs_handle h, void *rhs, int64_t m,
  *          rhs aligned to 2 elements), S systems per workgroup (a multiple
  *          of vec), flags bit 0: workgroups of one chiplet take adjacent
  *          groups, bit 2: workgroups start out of step, workgroup b waiting
- *          (b % 4) * k * 4096 cycles first, with k in bits 8..15.
+ *          (b % 4) * k * 4096 cycles first, with k in bits 8..15, bit 4:
+ *          read the plan's factor rows, spikes and separator rows from
+ *          global memory with only S^{-1} in LDS (taken anyway where the
+ *          whole plan does not fit the LDS; shapes (lb, vec) = (32, 2) and
+ *          (64, 1) only).  Bit 5 is ignored.
  * Same arguments and results as sbs_solve_batch otherwise.  A shape that has
  * no plan, exceeds 1024 threads, the register budget or the LDS returns
  * SBS_ERR_INVALID_ARG.

@@ -97,6 +97,22 @@ sbs_status upload(sbs_lhs *h, const std::vector<Row64> &r64, const double *B) {
 
 bool aligned(const void *p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
 
+// Which partitioned form runs: the separator kernel when it fills the GPU
+// with whole row runs; else the pair kernel; else a separator shape (for
+// AUTO only one whose plan sits in LDS or whose row runs are at least 128
+// bytes: a plan read from global memory with shorter runs loses to the
+// chunked sweep).  0: none (AUTO then runs the sweeps), 1: separator, 2: pair.
+int pick_partition(const sbs_lhs *h, int t, int64_t m, const void *rhs, bool for_auto, sbs::SepChoice *sc,
+                   sbs::PartChoice *pc) {
+    const bool sep = sbs::choose_sep(h, t, m, rhs, sc);
+    const bool part = sbs::choose_partition(h, t, m, pc);
+    if (sep && sbs::sep_fills(h, t, m, *sc)) return 1;
+    if (part) return 2;
+    const size_t elem = t == 0 ? 8 : 4;
+    if (sep && (!for_auto || !sc->gf || (size_t)sc->S * elem >= 128)) return 1;
+    return 0;
+}
+
 }  // namespace
 
 namespace sbs {
@@ -112,14 +128,19 @@ sbs_status refined_check(const sbs_lhs *h, const float *b, const double *x, int6
 }
 
 bool refined_fused(const sbs_lhs *h, int64_t m) {
+    RefwChoice rc;
     PartChoice pc;
-    return choose_partition_refine(h, m, &pc);
+    return choose_refine_wave(h, m, &rc) || choose_partition_refine(h, m, &pc);
 }
 
 sbs_status refined_run(const sbs_lhs *h, const float *b, double *x, int64_t m, int32_t sweeps, float *r,
                        hipStream_t s) {
-    // Fused path: one kernel keeps each block of b and x on chip through all
-    // passes (needs a partition plan); r is not touched.
+    // Fused paths: one kernel keeps each block of b and x on chip through all
+    // passes (needs a partition plan); r is not touched.  First the
+    // one-wave-per-block kernel on the separator plan, then the pair form.
+    RefwChoice rc;
+    if (choose_refine_wave(h, m, &rc))
+        return launch_refine_wave(h, rc, b, x, m, sweeps, s) == hipSuccess ? SBS_OK : SBS_ERR_DEVICE;
     PartChoice pc;
     if (choose_partition_refine(h, m, &pc))
         return launch_partition_refine(h, pc, b, x, m, sweeps, s) == hipSuccess ? SBS_OK : SBS_ERR_DEVICE;
@@ -254,16 +275,13 @@ sbs_status sbs_solve_batch_variant(sbs_handle h, void *rhs, int64_t m, int32_t d
     const int t = dtype == SBS_F64 ? 0 : 1;
     hipError_t e;
     if (variant == SBS_VARIANT_AUTO || variant == SBS_VARIANT_PARTITION) {
-        // Partitioned forms: the separator kernel when it fills the GPU with
-        // whole row runs, else the pair kernel, else any separator shape.
         SepChoice sc;
         PartChoice pc;
-        const bool sep = choose_sep(h, t, m, rhs, &sc);
-        const bool part = choose_partition(h, t, m, &pc);
+        const int form = pick_partition(h, t, m, rhs, variant == SBS_VARIANT_AUTO, &sc, &pc);
         hipStream_t s = static_cast<hipStream_t>(stream);
-        if (sep && (sep_fills(h, t, m, sc) || !part))
+        if (form == 1)
             e = launch_sep(h, sc, t, rhs, m, s);
-        else if (part)
+        else if (form == 2)
             e = launch_partition(h, pc, t, t, t, rhs, rhs, m, s);
         else if (variant == SBS_VARIANT_PARTITION)
             return SBS_ERR_INVALID_ARG;
@@ -302,14 +320,13 @@ sbs_status sbs_partition_shape(sbs_handle h, int64_t m, int32_t dtype, const voi
     const int t = dtype == SBS_F64 ? 0 : 1;
     SepChoice sc;
     PartChoice pc;
-    const bool sep = choose_sep(h, t, m, rhs, &sc);
-    const bool part = choose_partition(h, t, m, &pc);
-    if (sep && (sep_fills(h, t, m, sc) || !part)) {
+    const int pick = pick_partition(h, t, m, rhs, true, &sc, &pc);
+    if (pick == 1) {
         *form = 1;
         *lb = h->sep[sc.plan].lb;
         *vec = sc.vec;
         *S = sc.S;
-    } else if (part) {
+    } else if (pick == 2) {
         *form = 0;
         *lb = h->part[pc.plan].lb;
         *vec = 1;
@@ -326,10 +343,8 @@ sbs_status sbs_auto_variant(sbs_handle h, int64_t m, int32_t dtype, int32_t *var
     const int t = dtype == SBS_F64 ? 0 : 1;
     PartChoice pc;
     SepChoice sc;
-    // a separator shape exists for some alignment of the right-hand sides
-    // whenever one exists for 8-byte alignment (pairs need 16)
-    const bool part = choose_partition(h, t, m, &pc) || choose_sep(h, t, m, nullptr, &sc);
-    *variant = part ? SBS_VARIANT_PARTITION : choose_variant(h, t);
+    // (shapes for right-hand sides aligned to 16 bytes)
+    *variant = pick_partition(h, t, m, nullptr, true, &sc, &pc) ? SBS_VARIANT_PARTITION : choose_variant(h, t);
     return SBS_OK;
 }
 

@@ -106,6 +106,15 @@ constexpr int kPartLbs[3] = {16, 32, 64};
 // to the neighbouring interior rows) . g, with h(P-1) unknowns (hP periodic),
 // half the interface of the pair form above.  Everything but g and yhat
 // depends on the matrix only and is computed once, in FP64.
+// The separator plan rearranged for the one-wave-per-block mixed-precision
+// kernel (non-periodic plans of 32- and 64-row blocks): byte offsets from
+// `base` of the forward coefficients, backward coefficients and spikes
+// ([D][lb][..] FP32) and of the original band rows ([P][lb][2h+1] FP64).
+struct RefinePlan {
+    void *base = nullptr;
+    size_t fwd = 0, bwd = 0, spk = 0, band = 0;
+};
+
 struct SepPlan {
     int lb = 0, P = 0, Nr = 0;
     int D = 0;  // distinct blocks stored
@@ -122,6 +131,7 @@ struct SepPlan {
     size_t fac_bytes64 = 0, spk_bytes64 = 0, scf_bytes64 = 0, sinv_bytes64 = 0;
     size_t fac_bytes32 = 0, spk_bytes32 = 0, scf_bytes32 = 0, sinv_bytes32 = 0;
     size_t map_bytes = 0;
+    RefinePlan refine;
     size_t blob_bytes(int tc) const {
         return (tc == 0 ? fac_bytes64 + spk_bytes64 + scf_bytes64 + sinv_bytes64
                         : fac_bytes32 + spk_bytes32 + scf_bytes32 + sinv_bytes32) +
@@ -208,12 +218,24 @@ bool choose_partition_refine(const sbs_lhs *h, int64_t m, PartChoice *out);
 hipError_t launch_partition_refine(const sbs_lhs *h, const PartChoice &c, const float *b, double *x, int64_t m,
                                    int sweeps, hipStream_t stream);
 
+// Mixed-precision solve on a separator plan, one wave per block and 64
+// systems per group (coefficients wave-uniform, through scalar loads).
+struct RefwChoice {
+    int plan = -1;
+    size_t lds = 0;
+};
+bool choose_refine_wave(const sbs_lhs *h, int64_t m, RefwChoice *out);
+hipError_t launch_refine_wave(const sbs_lhs *h, const RefwChoice &c, const float *b, double *x, int64_t m,
+                              int sweeps, hipStream_t stream);
+
 // Separator-partitioned solve (plain solves of interleaved right-hand sides):
 // plan, values per lane (VEC adjacent systems, one access per row), systems
 // per workgroup, launch options (bit 0: XCD-grouped group order, bit 2:
-// workgroups start out of step by bits 8.. sleeps of 4096 cycles per quarter).
+// workgroups start out of step by bits 8.. sleeps of 4096 cycles per quarter,
+// bit 4: plan in global memory, bit 5: separators overwrite redL).
 struct SepChoice {
     int plan = -1, vec = 1, S = 0, threads = 0, flags = 0;
+    bool gf = false;  // plan read from global memory, S^{-1} alone in LDS
     size_t lds = 0;
     int wgs = 1;  // workgroups resident per CU at this size
 };

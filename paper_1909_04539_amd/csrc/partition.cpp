@@ -289,7 +289,7 @@ bool build_plan(int kind, bool periodic, int64_t n, const double *bands, int lb,
 // ---------------------------------------------------------------------------
 // Separator partition (SepPlan).
 
-constexpr int kMaxSepInterface = 96;  // separator unknowns: the FP64 inverse stays under 72 KB of LDS
+constexpr int kMaxSepInterface = 128;  // separator unknowns: the FP64 inverse stays within 128 KB of LDS
 
 struct SepHostPlan {
     int lb = 0, P = 0, Nr = 0, D = 0;
@@ -595,13 +595,55 @@ void serialise_sep(const SepHostPlan &hp, std::vector<unsigned char> &b64, std::
     pp.Nr = hp.Nr;
 }
 
+// The one-wave-per-block mixed-precision kernel's copy of a separator plan:
+// each pass's coefficients contiguous, so that a wave reads a run of rows
+// with a few wide scalar loads.  Per distinct block (FP32, from the plan):
+// forward coefficients (tri a/den, 1/den; penta eps/alpha, beta/alpha,
+// 1/alpha), backward coefficients (tri chat; penta gamma, delta), spikes;
+// per block (FP64): the original band rows, 0 outside the matrix.
+template <typename Row32>
+void serialise_refine(const SepHostPlan &hp, const std::vector<unsigned char> &b32, const SepPlan &sp, int kind,
+                      int64_t n, const double *bands, std::vector<unsigned char> &out, RefinePlan &rp) {
+    const int h = kind / 2, nb = 2 * h + 1, lb = hp.lb, D = hp.D, P = hp.P;
+    const int F = kind == SBS_TRI ? 2 : 3, Bk = kind == SBS_TRI ? 1 : 2;
+    rp.fwd = 0;
+    rp.bwd = align256(rp.fwd + (size_t)D * lb * F * 4);
+    rp.spk = align256(rp.bwd + (size_t)D * lb * Bk * 4);
+    rp.band = align256(rp.spk + (size_t)D * lb * 2 * h * 4);
+    const size_t total = align256(rp.band + (size_t)P * lb * nb * 8);
+    out.assign(total, 0);
+    const Row32 *rows = reinterpret_cast<const Row32 *>(b32.data());
+    float *fwd = reinterpret_cast<float *>(out.data() + rp.fwd);
+    float *bwd = reinterpret_cast<float *>(out.data() + rp.bwd);
+    for (size_t i = 0; i < (size_t)D * lb; ++i) {
+        if constexpr (sizeof(Row32) == sizeof(TriRow<float>)) {
+            fwd[2 * i] = rows[i].a_s;
+            fwd[2 * i + 1] = rows[i].inv;
+            bwd[i] = rows[i].chat;
+        } else {
+            fwd[3 * i] = rows[i].eps_s;
+            fwd[3 * i + 1] = rows[i].beta_s;
+            fwd[3 * i + 2] = rows[i].inv;
+            bwd[2 * i] = rows[i].gamma;
+            bwd[2 * i + 1] = rows[i].delta;
+        }
+    }
+    copy_bytes(out.data() + rp.spk, b32.data() + sp.fac_bytes32, (size_t)D * lb * 2 * h * 4);
+    double *band = reinterpret_cast<double *>(out.data() + rp.band);
+    for (int64_t i = 0; i < std::min<int64_t>(n, (int64_t)P * lb); ++i)
+        for (int k = 0; k < nb; ++k) {
+            const int64_t col = i + k - h;
+            band[i * nb + k] = (col >= 0 && col < n) ? bands[(int64_t)k * n + i] : 0.0;
+        }
+}
+
 }  // namespace
 
 // Builds every plan that exists for this matrix.  A plan that does not exist
 // (too many blocks, a zero pivot inside a block, a singular interface
 // system) only disables the partitioned variant for that block length.
 sbs_status build_partitions(sbs_lhs *h, const double *bands) {
-    std::vector<unsigned char> b64[3], b32[3], s64[3], s32[3];
+    std::vector<unsigned char> b64[3], b32[3], s64[3], s32[3], r32[3];
     size_t total = 0;
     // A periodic tridiagonal matrix is partitioned directly (the blocks are
     // plain tridiagonal; the wrap is one more interface pair).
@@ -651,6 +693,13 @@ sbs_status build_partitions(sbs_lhs *h, const double *bands) {
             serialise_sep<PentaRow<double>, PentaRow<float>>(hp, s64[q], s32[q], sp);
         sp.ok = true;
         total += align256(s64[q].size()) + align256(s32[q].size());
+        if (!periodic && lb >= 32) {
+            if (tri)
+                serialise_refine<TriRow<float>>(hp, s32[q], sp, SBS_TRI, h->n, bands, r32[q], sp.refine);
+            else
+                serialise_refine<PentaRow<float>>(hp, s32[q], sp, SBS_PENTA, h->n, bands, r32[q], sp.refine);
+            total += r32[q].size();
+        }
     }
     if (total == 0) return SBS_OK;
     void *dev = nullptr;
@@ -682,6 +731,12 @@ sbs_status build_partitions(sbs_lhs *h, const double *bands) {
             return SBS_ERR_DEVICE;
         sp.blob32 = base + at;
         at += align256(s32[q].size());
+        if (!r32[q].empty()) {
+            if (hipMemcpy(base + at, r32[q].data(), r32[q].size(), hipMemcpyHostToDevice) != hipSuccess)
+                return SBS_ERR_DEVICE;
+            sp.refine.base = base + at;
+            at += r32[q].size();
+        }
     }
     h->device_bytes += (int64_t)total;
     return SBS_OK;

@@ -112,6 +112,10 @@ struct SepArgs {
 // v_mfma_f64_16x16x4f64 shared out over the waves (lane l holds
 // A[l % 16][l / 16] and B[l / 16][l % 16]; item r of the result is
 // D[4 r + l / 16][l % 16]).  Column s of Yhat / Z is at red / z + s * ldr.
+//
+// ALIAS: z is redl's storage (the LDS holds no third buffer); each wave has
+// at most one tile, and writes it only after every wave has read Yhat.
+template <bool ALIAS>
 __device__ __forceinline__ void sep_mma(const double *sinv, const double *redl, const double *redr, double *z, int Nr,
                                         int S, int ldr) {
     // the thread's coordinates, made opaque at each call: the tile addresses
@@ -121,6 +125,32 @@ __device__ __forceinline__ void sep_mma(const double *sinv, const double *redl, 
     const int lane = tid % kWave, wave = __builtin_amdgcn_readfirstlane(tid / kWave), nwaves = blockDim.x / kWave;
     const int mt = (Nr + 15) / 16, ntiles = mt * ((S + 15) / 16);
     const int lr = lane % 16, lk = lane / 16;
+    if constexpr (ALIAS) {
+        const bool have = wave < ntiles;
+        const int i0 = (wave % mt) * 16, j0 = (wave / mt) * 16;
+        const int i = i0 + lr, j = j0 + lr;
+        D4 acc = {0.0, 0.0, 0.0, 0.0};
+        if (have) {
+            const double *arow = sinv + (size_t)min(i, Nr - 1) * Nr;
+            const double *bl = redl + min(j, S - 1) * ldr, *br = redr + min(j, S - 1) * ldr;
+            for (int k0 = 0; k0 < Nr; k0 += 4) {
+                const int k = k0 + lk, kc = min(k, Nr - 1);
+                const bool kin = k < Nr;
+                const double a = (kin && i < Nr) ? arow[kc] : 0.0;
+                const double b = (kin && j < S) ? bl[kc] + br[kc] : 0.0;
+                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+            }
+        }
+        __syncthreads();
+        if (have) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = i0 + 4 * r + lk;
+                if (row < Nr && j < S) z[j * ldr + row] = acc[r];
+            }
+        }
+        return;
+    }
     for (int tile = wave; tile < ntiles; tile += nwaves) {
         const int i0 = (tile % mt) * 16, j0 = (tile / mt) * 16;
         const int i = i0 + lr, j = j0 + lr;
@@ -162,7 +192,11 @@ constexpr int G = 4;  // rows per coefficient group (2 where registers are short
 
 // The block's forward and backward sweeps (Sections 3.1 / 4.1) over VEC
 // systems in registers, with the block's factor rows from LDS.
-template <int KIND, typename T, int LB, int VEC>
+// OPQ (rows in global memory): the row pointer is made opaque before each
+// group of rows is read, so that the read-only loads are not all hoisted to
+// the start (the fences below do not hold back loads of memory that nothing
+// in the kernel writes).
+template <int KIND, typename T, int LB, int VEC, bool OPQ>
 __device__ __forceinline__ void block_sweeps(const typename RowOf<KIND, T>::type *fr, T (&x)[LB][VEC]) {
     // coefficient rows per group: fewer when the block's values fill the registers
     constexpr int NG = LB / G;
@@ -171,11 +205,13 @@ __device__ __forceinline__ void block_sweeps(const typename RowOf<KIND, T>::type
         T y1[VEC];
 #pragma unroll
         for (int v = 0; v < VEC; ++v) y1[v] = T(0);
+        if constexpr (OPQ) asm volatile("" : "+v"(fr));
 #pragma unroll
         for (int u = 0; u < G; ++u) cf[0][u][0] = fr[u].a_s, cf[0][u][1] = fr[u].inv;
 #pragma unroll
         for (int g = 0; g < NG; ++g) {
             if (g + 1 < NG) {
+                if constexpr (OPQ) asm volatile("" : "+v"(fr));
 #pragma unroll
                 for (int u = 0; u < G; ++u)
                     cf[(g + 1) & 1][u][0] = fr[(g + 1) * G + u].a_s, cf[(g + 1) & 1][u][1] = fr[(g + 1) * G + u].inv;
@@ -191,11 +227,13 @@ __device__ __forceinline__ void block_sweeps(const typename RowOf<KIND, T>::type
         T x1[VEC];
 #pragma unroll
         for (int v = 0; v < VEC; ++v) x1[v] = T(0);
+        if constexpr (OPQ) asm volatile("" : "+v"(fr));
 #pragma unroll
         for (int u = 0; u < G; ++u) ch[(NG - 1) & 1][u] = fr[LB - 1 - u].chat;
 #pragma unroll
         for (int g = NG - 1; g >= 0; --g) {
             if (g > 0) {
+                if constexpr (OPQ) asm volatile("" : "+v"(fr));
 #pragma unroll
                 for (int u = 0; u < G; ++u) ch[(g - 1) & 1][u] = fr[g * G - 1 - u].chat;
             }
@@ -213,11 +251,13 @@ __device__ __forceinline__ void block_sweeps(const typename RowOf<KIND, T>::type
         T g1[VEC], g2[VEC];
 #pragma unroll
         for (int v = 0; v < VEC; ++v) g1[v] = g2[v] = T(0);
+        if constexpr (OPQ) asm volatile("" : "+v"(fr));
 #pragma unroll
         for (int u = 0; u < G; ++u) cf[0][u][0] = fr[u].eps_s, cf[0][u][1] = fr[u].beta_s, cf[0][u][2] = fr[u].inv;
 #pragma unroll
         for (int g = 0; g < NG; ++g) {
             if (g + 1 < NG) {
+                if constexpr (OPQ) asm volatile("" : "+v"(fr));
 #pragma unroll
                 for (int u = 0; u < G; ++u) {
                     const int t = (g + 1) * G + u;
@@ -242,11 +282,13 @@ __device__ __forceinline__ void block_sweeps(const typename RowOf<KIND, T>::type
         T x1[VEC], x2[VEC];
 #pragma unroll
         for (int v = 0; v < VEC; ++v) x1[v] = x2[v] = T(0);
+        if constexpr (OPQ) asm volatile("" : "+v"(fr));
 #pragma unroll
         for (int u = 0; u < G; ++u) cb[(NG - 1) & 1][u][0] = fr[LB - 1 - u].gamma, cb[(NG - 1) & 1][u][1] = fr[LB - 1 - u].delta;
 #pragma unroll
         for (int g = NG - 1; g >= 0; --g) {
             if (g > 0) {
+                if constexpr (OPQ) asm volatile("" : "+v"(fr));
 #pragma unroll
                 for (int u = 0; u < G; ++u) {
                     const int t = g * G - 1 - u;
@@ -275,7 +317,14 @@ __device__ __forceinline__ void block_sweeps(const typename RowOf<KIND, T>::type
 // below).  (Issuing the next group's loads into registers while the current
 // group is stored was measured slower: each wave's loads then queue behind
 // its stores.)
-template <int KIND, typename T, int LB, int VEC, int MAXT>
+//
+// GF: the plan does not fit the LDS with the group's buffers; only S^{-1}
+// is copied there, and the factor rows, spikes, separator rows and block map
+// are read from global memory (the caches hold them: every group reads the
+// same plan).  The separators then overwrite redL, and the corrected rows
+// are stored after all of them are computed (a spike load issued after a
+// store would wait for that store).
+template <int KIND, typename T, int LB, int VEC, int MAXT, bool GF>
 __global__ __launch_bounds__(MAXT) void k_sep(const unsigned char *__restrict__ blob, SepArgs a, const T *in,
                                               T *out) {
     using Row = typename RowOf<KIND, T>::type;
@@ -284,15 +333,31 @@ __global__ __launch_bounds__(MAXT) void k_sep(const unsigned char *__restrict__ 
     extern __shared__ __align__(16) unsigned char lds[];
     const int P = a.P, Nr = a.Nr, S = a.S, n = a.n;
     const int blob_bytes = a.fac_bytes + a.spk_bytes + a.scf_bytes + a.sinv_bytes + a.map_bytes;
-    const Row *lfac = reinterpret_cast<const Row *>(lds);
-    const T *lspk = reinterpret_cast<const T *>(lds + a.fac_bytes);
-    const T *lscf = reinterpret_cast<const T *>(lds + a.fac_bytes + a.spk_bytes);
-    const T *lsinv = reinterpret_cast<const T *>(lds + a.fac_bytes + a.spk_bytes + a.scf_bytes);
-    const int *lmap = reinterpret_cast<const int *>(lds + a.fac_bytes + a.spk_bytes + a.scf_bytes + a.sinv_bytes);
+    const int sinv_at = a.fac_bytes + a.spk_bytes + a.scf_bytes;
+    const Row *lfac;
+    const T *lspk, *lscf, *lsinv;
+    const int *lmap;
+    if constexpr (GF) {
+        lfac = reinterpret_cast<const Row *>(blob);
+        lspk = reinterpret_cast<const T *>(blob + a.fac_bytes);
+        lscf = reinterpret_cast<const T *>(blob + a.fac_bytes + a.spk_bytes);
+        lmap = reinterpret_cast<const int *>(blob + sinv_at + a.sinv_bytes);
+        lsinv = reinterpret_cast<const T *>(lds);
+    } else {
+        lfac = reinterpret_cast<const Row *>(lds);
+        lspk = reinterpret_cast<const T *>(lds + a.fac_bytes);
+        lscf = reinterpret_cast<const T *>(lds + a.fac_bytes + a.spk_bytes);
+        lsinv = reinterpret_cast<const T *>(lds + sinv_at);
+        lmap = reinterpret_cast<const int *>(lds + sinv_at + a.sinv_bytes);
+    }
+    const int plan_lds = GF ? a.sinv_bytes : blob_bytes;
     const int ldr = Nr + 1;  // odd stride: the systems' columns fall in different banks
-    T *lredl = reinterpret_cast<T *>(lds + blob_bytes);
-    T *lredr = reinterpret_cast<T *>(lds + blob_bytes + sep_red_bytes<T>(S, Nr));
-    T *lz = reinterpret_cast<T *>(lds + blob_bytes + 2 * sep_red_bytes<T>(S, Nr));
+    T *lredl = reinterpret_cast<T *>(lds + plan_lds);
+    T *lredr = reinterpret_cast<T *>(lds + plan_lds + sep_red_bytes<T>(S, Nr));
+    // flags bit 5 (GF only, set by the launch when the LDS has no room for a
+    // third buffer): the separators overwrite redL
+    const bool alias = GF && (a.flags & 32);
+    T *lz = alias ? lredl : reinterpret_cast<T *>(lds + plan_lds + 2 * sep_red_bytes<T>(S, Nr));
 
 
     const int Ls = S / VEC;  // lanes per block row
@@ -330,7 +395,10 @@ __global__ __launch_bounds__(MAXT) void k_sep(const unsigned char *__restrict__ 
     };
 
     int g = b;
-    stage(lds, blob, blob_bytes);
+    if constexpr (GF)
+        stage(lds, blob + sinv_at, a.sinv_bytes);
+    else
+        stage(lds, blob, blob_bytes);
     // flags bit 2: workgroups start out of step (b % 4 quarter steps of
     // `stagger` sleeps of 4096 cycles each), so that while some compute their
     // separators others stream, instead of every CU reaching its compute
@@ -342,8 +410,8 @@ __global__ __launch_bounds__(MAXT) void k_sep(const unsigned char *__restrict__ 
     __syncthreads();
     if (g < a.ngroups) load_group(g);
     const int q = lmap[p];  // stored copy of this block's factor, spikes and separator rows
-    const Row *fr = lfac + q * LB;
-    const T *sp = lspk + q * LB * 2 * H;
+    const Row *fr0 = lfac + q * LB;
+    const T *sp0 = lspk + q * LB * 2 * H;
     const T *cf = lscf + q * H * NB;
     const T *cfp = lscf + lmap[pp] * H * NB;  // the previous block's separator rows
     // the separator rows' couplings to interior rows, the same for every
@@ -363,11 +431,17 @@ __global__ __launch_bounds__(MAXT) void k_sep(const unsigned char *__restrict__ 
         // are used instead of being kept live (and spilled) across the loop
         int o_own = s0 * ldr + H * p, o_prev = s0 * ldr + H * pp, o_col = s0 * ldr;
         asm volatile("" : "+v"(o_own), "+v"(o_prev), "+v"(o_col));
+        // GF: the plan is read-only global memory, and its loads would be
+        // hoisted out of the loop (every row's coefficients live at once)
+        // unless its addresses are opaque here too
+        const Row *fr = fr0;
+        const T *sp = sp0;
+        if constexpr (GF) asm volatile("" : "+v"(fr), "+v"(sp));
 
         // 1. block sweeps (Section 3.1 / 4.1 recurrences, block factor);
         // each group of G rows reads its coefficients while the previous
         // group computes
-        block_sweeps<KIND, T, LB, VEC>(fr, x);
+        block_sweeps<KIND, T, LB, VEC, GF>(fr, x);
         // 2. the separator right-hand sides in two parts: the previous
         // separator takes minus its couplings to this block's first rows
         // (redr), the block's own separator takes f_sep minus its couplings to
@@ -408,8 +482,14 @@ __global__ __launch_bounds__(MAXT) void k_sep(const unsigned char *__restrict__ 
             for (int c = 0; c < H; ++c)
 #pragma unroll
                 for (int v = 0; v < VEC; ++v) zr[c][v] = zl[c][v] = T(0);
-        } else if (MMA && blockDim.x % kWave == 0) {
-            if constexpr (MMA) sep_mma(lsinv, lredl, lredr, lz, Nr, S, ldr);
+        } else if (MMA && blockDim.x % kWave == 0 &&
+                   (!alias || ((Nr + 15) / 16) * ((S + 15) / 16) <= (int)(blockDim.x / kWave))) {
+            if constexpr (MMA) {
+                if (alias)
+                    sep_mma<true>(lsinv, lredl, lredr, lz, Nr, S, ldr);
+                else
+                    sep_mma<false>(lsinv, lredl, lredr, lz, Nr, S, ldr);
+            }
             __syncthreads();
 #pragma unroll
             for (int c = 0; c < H; ++c)
@@ -421,6 +501,9 @@ __global__ __launch_bounds__(MAXT) void k_sep(const unsigned char *__restrict__ 
                     zr[c][v] = has_sep ? zo : T(0);
                     zl[c][v] = has_prev ? zp : T(0);
                 }
+            // the separators are redL's storage: the next group writes redL
+            // only after every lane has read them
+            if (alias) __syncthreads();
         } else {
             // rows of S^{-1} for the own and the previous separator (a block
             // without one reads the other's rows and discards the result)
@@ -449,18 +532,32 @@ __global__ __launch_bounds__(MAXT) void k_sep(const unsigned char *__restrict__ 
                     zr[c][v] = has_sep ? ar[c][v] : T(0);
                     zl[c][v] = has_prev ? al[c][v] : T(0);
                 }
+            // every lane has read redL / redR before the next group writes them
+            __syncthreads();
         }
         // 5. correction and stores
         T *dst = out + (int64_t)r0 * m + col(g);
-        // the spikes of G rows per round trip to LDS
-        constexpr int GC = G;
-#pragma unroll
-        for (int gr = 0; gr < LB / GC; ++gr) {
-            T spt[GC][2 * H];
+        // the spikes of GC rows per round trip; from global memory (GF) the
+        // next rows' spikes are loaded before the current rows are stored,
+        // since a load issued after a store waits for that store
+        constexpr int GC = GF ? 2 : G, NS = GF ? 2 : 1;
+        T spt[NS][GC][2 * H];
+        auto spikes = [&](int gr, T(&dstk)[GC][2 * H]) {
+            if constexpr (GF) asm volatile("" : "+v"(sp));
 #pragma unroll
             for (int u = 0; u < GC; ++u)
 #pragma unroll
-                for (int k = 0; k < 2 * H; ++k) spt[u][k] = sp[(gr * GC + u) * 2 * H + k];
+                for (int k = 0; k < 2 * H; ++k) dstk[u][k] = sp[(gr * GC + u) * 2 * H + k];
+        };
+        if constexpr (GF) spikes(0, spt[0]);
+#pragma unroll
+        for (int gr = 0; gr < LB / GC; ++gr) {
+            T(&cur)[GC][2 * H] = spt[GF ? gr & 1 : 0];
+            if constexpr (GF) {
+                if (gr + 1 < LB / GC) spikes(gr + 1, spt[(gr + 1) & 1]);
+            } else {
+                spikes(gr, cur);
+            }
 #pragma unroll
             for (int u = 0; u < GC; ++u) {
                 const int t = gr * GC + u;
@@ -470,8 +567,8 @@ __global__ __launch_bounds__(MAXT) void k_sep(const unsigned char *__restrict__ 
                     T val = x[t][v];
 #pragma unroll
                     for (int c = 0; c < H; ++c) {
-                        val = fma(-spt[u][c], zr[c][v], val);
-                        val = fma(-spt[u][H + c], zl[c][v], val);
+                        val = fma(-cur[u][c], zr[c][v], val);
+                        val = fma(-cur[u][H + c], zl[c][v], val);
                     }
                     if (t >= NI) val = has_sep ? zr[t >= NI ? t - NI : 0][v] : val;
                     v2[v] = val;
@@ -495,9 +592,9 @@ constexpr int sep_maxt() {
     return LB * VEC * (int)sizeof(T) / 4 <= 64 ? 1024 : 512;
 }
 
-template <int KIND, typename T, int LB, int VEC>
+template <int KIND, typename T, int LB, int VEC, bool GF>
 hipError_t sep_kernel(const void **fn) {
-    auto kern = k_sep<KIND, T, LB, VEC, sep_maxt<T, LB, VEC>()>;
+    auto kern = k_sep<KIND, T, LB, VEC, sep_maxt<T, LB, VEC>(), GF>;
     // once per instantiation; thread-safe static initialisation, so that
     // concurrent first launches from several host threads do not race
     static const hipError_t attr = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
@@ -508,33 +605,41 @@ hipError_t sep_kernel(const void **fn) {
     return hipSuccess;
 }
 
-// The shapes built: (LB, VEC) with at most 128 registers of values per lane.
+// The shapes built: (LB, VEC) with at most 128 registers of values per lane;
+// with the plan in global memory (GF) the two longest, (32, 2) and (64, 1).
 template <int KIND, typename T>
-hipError_t sep_kernel_of(int lb, int vec, const void **fn, int *maxt) {
-    if (lb == 16 && vec == 1) return *maxt = sep_maxt<T, 16, 1>(), sep_kernel<KIND, T, 16, 1>(fn);
-    if (lb == 16 && vec == 2) return *maxt = sep_maxt<T, 16, 2>(), sep_kernel<KIND, T, 16, 2>(fn);
-    if (lb == 32 && vec == 1) return *maxt = sep_maxt<T, 32, 1>(), sep_kernel<KIND, T, 32, 1>(fn);
-    if (lb == 32 && vec == 2) return *maxt = sep_maxt<T, 32, 2>(), sep_kernel<KIND, T, 32, 2>(fn);
-    if (lb == 64 && vec == 1) return *maxt = sep_maxt<T, 64, 1>(), sep_kernel<KIND, T, 64, 1>(fn);
+hipError_t sep_kernel_of(int lb, int vec, bool gf, const void **fn, int *maxt) {
+    if (gf) {
+        if (lb == 32 && vec == 2) return *maxt = sep_maxt<T, 32, 2>(), sep_kernel<KIND, T, 32, 2, true>(fn);
+        if (lb == 64 && vec == 1) return *maxt = sep_maxt<T, 64, 1>(), sep_kernel<KIND, T, 64, 1, true>(fn);
+        return hipErrorInvalidValue;
+    }
+    if (lb == 16 && vec == 1) return *maxt = sep_maxt<T, 16, 1>(), sep_kernel<KIND, T, 16, 1, false>(fn);
+    if (lb == 16 && vec == 2) return *maxt = sep_maxt<T, 16, 2>(), sep_kernel<KIND, T, 16, 2, false>(fn);
+    if (lb == 32 && vec == 1) return *maxt = sep_maxt<T, 32, 1>(), sep_kernel<KIND, T, 32, 1, false>(fn);
+    if (lb == 32 && vec == 2) return *maxt = sep_maxt<T, 32, 2>(), sep_kernel<KIND, T, 32, 2, false>(fn);
+    if (lb == 64 && vec == 1) return *maxt = sep_maxt<T, 64, 1>(), sep_kernel<KIND, T, 64, 1, false>(fn);
     if constexpr (sizeof(T) == 4)
-        if (lb == 64 && vec == 2) return *maxt = sep_maxt<T, 64, 2>(), sep_kernel<KIND, T, 64, 2>(fn);
+        if (lb == 64 && vec == 2) return *maxt = sep_maxt<T, 64, 2>(), sep_kernel<KIND, T, 64, 2, false>(fn);
     return hipErrorInvalidValue;
 }
 
-hipError_t sep_fn(int kind, int tc, int lb, int vec, const void **fn, int *maxt) {
+hipError_t sep_fn(int kind, int tc, int lb, int vec, bool gf, const void **fn, int *maxt) {
     const int k = kind == SBS_PENTA ? SBS_PENTA : SBS_TRI;  // periodic blocks are plain tridiagonal
     if (k == SBS_TRI)
-        return tc == 0 ? sep_kernel_of<SBS_TRI, double>(lb, vec, fn, maxt)
-                       : sep_kernel_of<SBS_TRI, float>(lb, vec, fn, maxt);
-    return tc == 0 ? sep_kernel_of<SBS_PENTA, double>(lb, vec, fn, maxt)
-                   : sep_kernel_of<SBS_PENTA, float>(lb, vec, fn, maxt);
+        return tc == 0 ? sep_kernel_of<SBS_TRI, double>(lb, vec, gf, fn, maxt)
+                       : sep_kernel_of<SBS_TRI, float>(lb, vec, gf, fn, maxt);
+    return tc == 0 ? sep_kernel_of<SBS_PENTA, double>(lb, vec, gf, fn, maxt)
+                   : sep_kernel_of<SBS_PENTA, float>(lb, vec, gf, fn, maxt);
 }
 
-// LDS of one workgroup: the plan, the two parts of the separator right-hand
-// sides and (FP64: the matrix-core product's output) the separators.
-size_t sep_lds(const SepPlan &sp, int tc, int, int S) {
+// LDS of one workgroup: the plan (GF: S^{-1} only), the two parts of the
+// separator right-hand sides and (FP64: the matrix-core product's output)
+// the separators, unless `alias` puts them in redL's storage.
+size_t sep_lds(const SepPlan &sp, int tc, int S, bool gf, bool alias) {
     const size_t red = tc == 0 ? sep_red_bytes<double>(S, sp.Nr) : sep_red_bytes<float>(S, sp.Nr);
-    return sp.blob_bytes(tc) + red * (tc == 0 ? 3 : 2);
+    const size_t plan = gf ? (tc == 0 ? sp.sinv_bytes64 : sp.sinv_bytes32) : sp.blob_bytes(tc);
+    return plan + red * (tc == 0 && !alias ? 3 : 2);
 }
 
 int cu_count(int device) {
@@ -544,19 +649,28 @@ int cu_count(int device) {
 }
 
 // Checks one shape and fills in its launch figures; false if it cannot run.
+// The plan goes to LDS whole where it fits with the group's buffers, else
+// (or with flags bit 4) only S^{-1} does (GF), and where even that leaves no
+// room for a third FP64 buffer the separators overwrite redL (flags bit 5,
+// which only this function sets).
 bool sep_fit(const sbs_lhs *h, int tc, int64_t m, const void *x, int q, int vec, int S, int flags, SepChoice *c) {
     const SepPlan &sp = h->sep[q];
     const size_t elem = tc == 0 ? 8 : 4;
-    const int H = h->kind == SBS_PENTA ? 2 : 1;
     if (!sp.ok || m < vec || S < vec || S % vec) return false;
     if (vec == 2 && (m % 2 || reinterpret_cast<uintptr_t>(x) % (2 * elem))) return false;
+    flags &= ~32;
+    bool gf = (flags & 16) != 0, alias = false;
+    if (!gf && sep_lds(sp, tc, S, false, false) > kMaxPartLdsBytes) gf = true;
+    if (gf && sep_lds(sp, tc, S, true, false) > kMaxPartLdsBytes) alias = tc == 0;
+    const size_t lds = sep_lds(sp, tc, S, gf, alias);
+    if (lds > kMaxPartLdsBytes) return false;
     const void *fn = nullptr;
     int maxt = 0;
-    if (sep_fn(h->kind, tc, sp.lb, vec, &fn, &maxt) != hipSuccess) return false;
+    if (sep_fn(h->kind, tc, sp.lb, vec, gf, &fn, &maxt) != hipSuccess) return false;
     const int threads = (S / vec) * sp.P;
     if (threads > maxt) return false;
-    const size_t lds = sep_lds(sp, tc, H, S);
-    if (lds > kMaxPartLdsBytes) return false;
+    // the separators in redL: one matrix-core tile per wave
+    if (alias && (threads % kWave || ((sp.Nr + 15) / 16) * ((S + 15) / 16) > threads / kWave)) return false;
     int wgs = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&wgs, fn, threads, lds) != hipSuccess || wgs < 1) return false;
     c->plan = q;
@@ -565,7 +679,8 @@ bool sep_fit(const sbs_lhs *h, int tc, int64_t m, const void *x, int q, int vec,
     c->threads = threads;
     c->lds = lds;
     c->wgs = wgs;
-    c->flags = flags;
+    c->flags = flags | (gf ? 16 : 0) | (alias ? 32 : 0);
+    c->gf = gf;
     return true;
 }
 
@@ -619,7 +734,7 @@ hipError_t launch_sep(const sbs_lhs *h, const SepChoice &c, int tc, void *x, int
     const SepPlan &sp = h->sep[c.plan];
     const void *fn = nullptr;
     int maxt = 0;
-    if (hipError_t e = sep_fn(h->kind, tc, sp.lb, c.vec, &fn, &maxt); e != hipSuccess) return e;
+    if (hipError_t e = sep_fn(h->kind, tc, sp.lb, c.vec, c.gf, &fn, &maxt); e != hipSuccess) return e;
     if (c.threads > maxt) return hipErrorInvalidValue;
     const int64_t ngroups = (m + c.S - 1) / c.S;
     if (ngroups > 0x7fffffff) return hipErrorInvalidValue;

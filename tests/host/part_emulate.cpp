@@ -7,7 +7,11 @@
 // in:  int32 kind, int64 n, int64 m, bands (3 or 5 x n doubles), rhs (n x m)
 // out: per block length 16, 32, 64: int32 lb (0 if no plan), P, D, Nr, then
 //      the n x m solution (only when the plan exists); first for the pair
-//      plans, then for the separator plans
+//      plans, then for the separator plans; then, for block lengths 32 and
+//      64, the mixed-precision form run from the separator plan's copy for
+//      the one-wave-per-block kernel (the right-hand sides rounded to FP32,
+//      two correction rounds): int32 lb (0 if there is no copy), then x
+#include <cmath>
 #include <cstdio>
 #include <cstdlib>
 #include <vector>
@@ -123,6 +127,104 @@ void emulate_sep(const sbs_lhs &h, const SepPlan &pp, const double *rhs, int64_t
     }
 }
 
+// The one-wave-per-block mixed-precision kernel's steps, from its copy of
+// the separator plan (FP32 coefficients pass by pass, FP64 band rows) and
+// the FP32 plan's separator rows, S^{-1} and map: x = fl64(solve32(b)), then
+// twice r = fl32(b - A x) (FP64), x += fl64(solve32(r)).
+void emulate_refine(const sbs_lhs &h, const SepPlan &pp, const double *rhs, int64_t m, double *x) {
+    const int H = h.kind == SBS_PENTA ? 2 : 1, NB = 2 * H + 1, lb = pp.lb, P = pp.P, Nr = pp.Nr;
+    const int F = H == 1 ? 2 : 3, Bk = H == 1 ? 1 : 2;
+    const unsigned char *blob = static_cast<const unsigned char *>(pp.blob32);
+    const float *scf = reinterpret_cast<const float *>(blob + pp.fac_bytes32 + pp.spk_bytes32);
+    const float *sinv = reinterpret_cast<const float *>(blob + pp.fac_bytes32 + pp.spk_bytes32 + pp.scf_bytes32);
+    const int *map = reinterpret_cast<const int *>(blob + pp.fac_bytes32 + pp.spk_bytes32 + pp.scf_bytes32 +
+                                                   pp.sinv_bytes32);
+    const unsigned char *rec = static_cast<const unsigned char *>(pp.refine.base);
+    const float *fwd = reinterpret_cast<const float *>(rec + pp.refine.fwd);
+    const float *bwd = reinterpret_cast<const float *>(rec + pp.refine.bwd);
+    const float *spk = reinterpret_cast<const float *>(rec + pp.refine.spk);
+    const double *band = reinterpret_cast<const double *>(rec + pp.refine.band);
+    const int64_t n = h.n, np = (int64_t)P * lb;
+    auto solve32 = [&](std::vector<float> &w) {
+        for (int p = 0; p < P; ++p) {
+            const int q = map[p];
+            float *v = w.data() + (int64_t)p * lb;
+            const float *fr = fwd + (size_t)q * lb * F, *br = bwd + (size_t)q * lb * Bk;
+            if (H == 1) {
+                float y = 0.0f;
+                for (int t = 0; t < lb; ++t) y = v[t] = std::fma(-fr[2 * t], y, v[t] * fr[2 * t + 1]);
+                float x1 = 0.0f;
+                for (int t = lb - 1; t >= 0; --t) x1 = v[t] = std::fma(-br[t], x1, v[t]);
+            } else {
+                float g1 = 0.0f, g2 = 0.0f;
+                for (int t = 0; t < lb; ++t) {
+                    const float gg = std::fma(-fr[3 * t + 1], g1, std::fma(-fr[3 * t], g2, v[t] * fr[3 * t + 2]));
+                    g2 = g1;
+                    g1 = v[t] = gg;
+                }
+                float x1 = 0.0f, x2 = 0.0f;
+                for (int t = lb - 1; t >= 0; --t) {
+                    const float xx = std::fma(-br[2 * t], x1, std::fma(-br[2 * t + 1], x2, v[t]));
+                    x2 = x1;
+                    x1 = v[t] = xx;
+                }
+            }
+        }
+        std::vector<float> yh(Nr > 0 ? Nr : 1, 0.0f), z(Nr > 0 ? Nr : 1, 0.0f);
+        for (int p = 0; p + 1 < P; ++p) {
+            const float *cl = scf + (size_t)map[p] * H * NB, *cr = cl;  // separator p's band rows
+            for (int c = 0; c < H; ++c) {
+                // own block's last interior rows, then the next block's first rows
+                float v = w[(int64_t)p * lb + lb - H + c];
+                for (int d = 0; d + c < H; ++d) v = std::fma(-cl[c * NB + d], w[(int64_t)p * lb + lb - 2 * H + c + d], v);
+                float r = 0.0f;
+                for (int e = 0; e + 2 * H - c < NB; ++e) r = std::fma(-cr[c * NB + 2 * H - c + e], w[(int64_t)(p + 1) * lb + e], r);
+                yh[H * p + c] = v + r;
+            }
+        }
+        for (int r = 0; r < Nr; ++r) {
+            float v = 0.0f;
+            for (int k = 0; k < Nr; ++k) v = std::fma(sinv[(size_t)r * Nr + k], yh[k], v);
+            z[r] = v;
+        }
+        for (int p = 0; p < P; ++p) {
+            const float *sp = spk + (size_t)map[p] * lb * 2 * H;
+            for (int t = 0; t < lb; ++t) {
+                float &v = w[(int64_t)p * lb + t];
+                if (p < P - 1 && t >= lb - H) {
+                    v = z[H * p + t - (lb - H)];
+                    continue;
+                }
+                for (int c = 0; c < H; ++c) {
+                    if (p < P - 1) v = std::fma(-sp[t * 2 * H + c], z[H * p + c], v);
+                    if (p > 0) v = std::fma(-sp[t * 2 * H + H + c], z[H * (p - 1) + c], v);
+                }
+            }
+        }
+    };
+    std::vector<float> b(np), w(np);
+    std::vector<double> xc(np);
+    for (int64_t j = 0; j < m; ++j) {
+        for (int64_t i = 0; i < np; ++i) w[i] = b[i] = i < n ? (float)rhs[i * m + j] : 0.0f;
+        solve32(w);
+        for (int64_t i = 0; i < np; ++i) xc[i] = (double)w[i];
+        for (int k = 0; k < 2; ++k) {
+            for (int64_t i = 0; i < np; ++i) {
+                double ax = 0.0;
+                for (int e = 0; e < NB; ++e) {
+                    const int64_t c = i - H + e;
+                    const double xv = (c >= 0 && c < np) ? xc[c] : 0.0;
+                    ax = e == 0 ? band[i * NB] * xv : std::fma(band[i * NB + e], xv, ax);
+                }
+                w[i] = (float)((double)b[i] - ax);
+            }
+            solve32(w);
+            for (int64_t i = 0; i < np; ++i) xc[i] += (double)w[i];
+        }
+        for (int64_t i = 0; i < n; ++i) x[i * m + j] = xc[i];
+    }
+}
+
 int main(int argc, char **argv) {
     if (argc != 3) return 2;
     FILE *f = std::fopen(argv[1], "rb");
@@ -161,6 +263,14 @@ int main(int argc, char **argv) {
             emulate_sep<TriRow<double>>(h, pp, rhs.data(), m, x.data(), solve_tri_rows);
         else
             emulate_sep<PentaRow<double>>(h, pp, rhs.data(), m, x.data(), solve_penta_rows);
+        std::fwrite(x.data(), 8, x.size(), o);
+    }
+    for (int q = 1; q < 3; ++q) {
+        const SepPlan &pp = h.sep[q];
+        const int32_t lb = pp.ok && pp.refine.base ? pp.lb : 0;
+        std::fwrite(&lb, 4, 1, o);
+        if (!lb) continue;
+        emulate_refine(h, pp, rhs.data(), m, x.data());
         std::fwrite(x.data(), 8, x.size(), o);
     }
     std::fclose(o);

@@ -1,7 +1,8 @@
 """GPU parity of the separator-partitioned solve (the partitioned variant's
 form for plain solves of interleaved right-hand sides): every shape the
 library builds -- block length, one or two systems per lane, systems per
-workgroup, group order and next-group loads -- against the oracle, on
+workgroup, group order, staggered starts and the plan read from global
+memory -- against the oracle, on
 matrices whose blocks all differ, with ragged last blocks, partial last
 groups and odd batch sizes; periodic matrices; FP32; and the choice AUTO
 makes for the benchmark's shapes."""
@@ -57,11 +58,14 @@ def test_every_shape_matches_oracle(kind, n, m):
     ran = 0
     with sbs.SharedLhs(kind, B) as h:
         for lb, vec, S in SHAPES:
-            for flags in (0, 1, 4 | (1 << 8)):
+            # flags: chiplet order, staggered start, plan read from global memory
+            for flags in (0, 1, 4 | (1 << 8), 16):
                 print(f"case kind={kind} n={n} m={m} lb={lb} vec={vec} S={S} flags={flags}", flush=True)
                 got = shape_run(h, rhs, lb, vec, S, flags)
                 if got is None:
-                    break  # the flags do not change whether a shape exists
+                    if flags == 0:
+                        break  # no such shape (the other flags add none but 16's)
+                    continue
                 assert colrel(got, ref) <= TOL64, (lb, vec, S, flags, colrel(got, ref))
                 ran += 1
     assert ran > 0
@@ -142,3 +146,29 @@ def test_constant_bands_full_size_sampled():
     assert colrel(got, ref) <= TOL64
     # manufactured solution: the right-hand side is A x_true
     assert colrel(got, wl.extra["x_true"][:, cols]) <= 1e-13
+
+
+@pytest.mark.parametrize("kind,n,m", [(5, 2048, 640), (5, 3000, 130), (3, 4000, 96), (5, 1500, 64)])
+def test_long_systems_read_the_plan_from_memory(kind, n, m):
+    # systems whose plan (random bands: every block distinct) does not fit
+    # the LDS: the factor rows, spikes and separator rows are read from
+    # global memory, S^{-1} alone is in LDS (and, for the longest S^{-1},
+    # the separators overwrite their right-hand sides)
+    B = bands_for(kind, n, 77 + n)
+    rhs = np.random.default_rng(n).uniform(-1, 1, (n, m))
+    ref = oracle.solve(kind, B, rhs)
+    ran = 0
+    with sbs.SharedLhs(kind, B) as h:
+        for lb, vec, S in [(32, 2, 16), (32, 2, 8), (64, 1, 16), (64, 1, 8), (64, 1, 4)]:
+            print(f"case kind={kind} n={n} m={m} lb={lb} vec={vec} S={S}", flush=True)
+            got = shape_run(h, rhs, lb, vec, S, 0)
+            if got is not None:
+                assert colrel(got, ref) <= TOL64, (lb, vec, S, colrel(got, ref))
+                ran += 1
+        # and whatever AUTO takes
+        x = torch.from_numpy(rhs).to(DEV)
+        print(f"AUTO shape: {sbs.sbs_partition_shape(h.handle, x)}", flush=True)
+        h.solve(x)
+        torch.cuda.synchronize()
+        assert colrel(x.cpu().numpy(), ref) <= TOL64
+    assert ran > 0

@@ -54,13 +54,24 @@ def run_all(exe, tmp_path, kind, B, rhs):
     r = subprocess.run([exe, src, dst], capture_output=True, text=True, timeout=120,
                        env=dict(os.environ, ASAN_OPTIONS="detect_leaks=1", UBSAN_OPTIONS="halt_on_error=1"))
     assert r.returncode == 0, r.stderr
-    plans = []
+    plans, refined = [], []
     with open(dst, "rb") as f:
         for _ in range(6):
             lb, P, D, Nr = struct.unpack("<4i", f.read(16))
             x = np.frombuffer(f.read(8 * n * m), dtype=np.float64).reshape(n, m) if lb else None
             plans.append((lb, P, D, Nr, x))
+        for _ in range(2):
+            (lb,) = struct.unpack("<i", f.read(4))
+            refined.append((lb, np.frombuffer(f.read(8 * n * m), dtype=np.float64).reshape(n, m) if lb else None))
+    run_all.refined = refined
     return plans[:3], plans[3:]
+
+
+def run_refine(exe, tmp_path, kind, B, rhs):
+    """The mixed-precision form from the one-wave-per-block kernel's copy of
+    the separator plans (block lengths 32, 64): (lb or 0, x)."""
+    run_all(exe, tmp_path, kind, B, rhs)
+    return run_all.refined
 
 
 def colrel(x, ref):
@@ -250,5 +261,24 @@ def test_ill_conditioned_separator_plans_stay_within_the_parity_bar(exe, tmp_pat
     rhs = np.random.default_rng(4).uniform(-1, 1, (n, 4))
     ref = oracle.solve(3, B, rhs)
     for lb, P, D, Nr, x in run_sep(exe, tmp_path, 3, B, rhs):
+        if lb:
+            assert colrel(x, ref) <= 1e-12, (lb, colrel(x, ref))
+
+
+@pytest.mark.parametrize("kind,n", [(3, 512), (3, 100), (3, 33), (5, 512), (5, 300), (3, 1000), (5, 64)])
+def test_refine_copy_of_the_plan_solves_like_the_oracle(exe, tmp_path, kind, n):
+    # the pass-by-pass copy of the separator plan (FP32 coefficients, FP64
+    # band rows): the refined form run from it reaches the FP64 solve of the
+    # FP32-rounded right-hand sides, which a mistake in any of its arrays
+    # (a wrong offset, a transposed pair, a band row off by one) would not
+    if kind == 3:
+        B = W.config3(n=n, m=1).bands
+    else:
+        B = dominant(kind, n, n)
+    rhs = np.random.default_rng(n).uniform(-1, 1, (n, 7)).astype(np.float32).astype(np.float64)
+    ref = oracle.refine_reference(kind, B, rhs.astype(np.float32))
+    got = run_refine(exe, tmp_path, kind, B, rhs)
+    assert any(lb for lb, _ in got)
+    for lb, x in got:
         if lb:
             assert colrel(x, ref) <= 1e-12, (lb, colrel(x, ref))
