@@ -109,10 +109,12 @@ constexpr int kPartLbs[3] = {16, 32, 64};
 // The separator plan rearranged for the one-wave-per-block mixed-precision
 // kernel (non-periodic plans of 32- and 64-row blocks): byte offsets from
 // `base` of the forward coefficients, backward coefficients and spikes
-// ([D][lb][..] FP32) and of the original band rows ([P][lb][2h+1] FP64).
+// ([D][lb][..] FP32), of the original band rows ([P][lb][2h+1] FP64) and of
+// S^{-1} ([Nr][ldsinv] FP32, rows padded with zeros to a multiple of 8).
 struct RefinePlan {
     void *base = nullptr;
-    size_t fwd = 0, bwd = 0, spk = 0, band = 0;
+    size_t fwd = 0, bwd = 0, spk = 0, band = 0, sinv = 0;
+    int ldsinv = 0;
 };
 
 struct SepPlan {

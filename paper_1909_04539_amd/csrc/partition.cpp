@@ -600,7 +600,8 @@ void serialise_sep(const SepHostPlan &hp, std::vector<unsigned char> &b64, std::
 // with a few wide scalar loads.  Per distinct block (FP32, from the plan):
 // forward coefficients (tri a/den, 1/den; penta eps/alpha, beta/alpha,
 // 1/alpha), backward coefficients (tri chat; penta gamma, delta), spikes;
-// per block (FP64): the original band rows, 0 outside the matrix.
+// per block (FP64): the original band rows, 0 outside the matrix; and S^{-1}
+// (FP32) with its rows padded with zeros to a multiple of 8 entries.
 template <typename Row32>
 void serialise_refine(const SepHostPlan &hp, const std::vector<unsigned char> &b32, const SepPlan &sp, int kind,
                       int64_t n, const double *bands, std::vector<unsigned char> &out, RefinePlan &rp) {
@@ -610,7 +611,9 @@ void serialise_refine(const SepHostPlan &hp, const std::vector<unsigned char> &b
     rp.bwd = align256(rp.fwd + (size_t)D * lb * F * 4);
     rp.spk = align256(rp.bwd + (size_t)D * lb * Bk * 4);
     rp.band = align256(rp.spk + (size_t)D * lb * 2 * h * 4);
-    const size_t total = align256(rp.band + (size_t)P * lb * nb * 8);
+    rp.ldsinv = (hp.Nr + 7) / 8 * 8;
+    rp.sinv = align256(rp.band + (size_t)P * lb * nb * 8);
+    const size_t total = align256(rp.sinv + (size_t)hp.Nr * rp.ldsinv * 4);
     out.assign(total, 0);
     const Row32 *rows = reinterpret_cast<const Row32 *>(b32.data());
     float *fwd = reinterpret_cast<float *>(out.data() + rp.fwd);
@@ -635,6 +638,9 @@ void serialise_refine(const SepHostPlan &hp, const std::vector<unsigned char> &b
             const int64_t col = i + k - h;
             band[i * nb + k] = (col >= 0 && col < n) ? bands[(int64_t)k * n + i] : 0.0;
         }
+    float *sinv = reinterpret_cast<float *>(out.data() + rp.sinv);
+    for (int r = 0; r < hp.Nr; ++r)
+        for (int k = 0; k < hp.Nr; ++k) sinv[(size_t)r * rp.ldsinv + k] = (float)hp.sinv[(size_t)r * hp.Nr + k];
 }
 
 }  // namespace

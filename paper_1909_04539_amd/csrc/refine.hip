@@ -40,7 +40,7 @@ struct R32<SBS_PENTA> {
 
 struct RefArgs {
     int fac_bytes, spk_bytes, scf_bytes, sinv_bytes;
-    int rec_fwd, rec_bwd, rec_spk, rec_band;  // offsets into the kernel's copy of the plan
+    int rec_fwd, rec_bwd, rec_spk, rec_band, rec_sinv, ldsinv;  // the kernel's copy of the plan
     int n, P, Nr, ngroups, sweeps;
     int64_t m;
 };
@@ -175,7 +175,6 @@ __global__ __launch_bounds__(MAXT) void k_refine_wave(const unsigned char *__res
     const int P = a.P, Nr = a.Nr, n = a.n, ldr = refw_ldr(Nr);
     const int64_t m = a.m;
     const float *__restrict__ scf = reinterpret_cast<const float *>(blob + a.fac_bytes + a.spk_bytes);
-    const float *__restrict__ sinv = reinterpret_cast<const float *>(blob + a.fac_bytes + a.spk_bytes + a.scf_bytes);
     const int *__restrict__ map =
         reinterpret_cast<const int *>(blob + a.fac_bytes + a.spk_bytes + a.scf_bytes + a.sinv_bytes);
 
@@ -191,8 +190,10 @@ __global__ __launch_bounds__(MAXT) void k_refine_wave(const unsigned char *__res
     const cptr<float> sk = (cptr<float>)(reinterpret_cast<const float *>(rec + a.rec_spk) + q * LB * 2 * H);
     // rows of S^{-1} of the own and the previous separator (a block without
     // one reads the other's and discards the result)
-    const cptr<float> rr = (cptr<float>)(sinv + (size_t)H * (has_sep ? p : pp) * Nr);
-    const cptr<float> rl = (cptr<float>)(sinv + (size_t)H * (has_prev ? pp : p) * Nr);
+    const int lsv = a.ldsinv;
+    const float *psinv = reinterpret_cast<const float *>(rec + a.rec_sinv);
+    const cptr<float> rr = (cptr<float>)(psinv + (size_t)H * (has_sep ? p : pp) * lsv);
+    const cptr<float> rl = (cptr<float>)(psinv + (size_t)H * (has_prev ? pp : p) * lsv);
     const cptr<double> br = (cptr<double>)(reinterpret_cast<const double *>(rec + a.rec_band) + (size_t)r0 * NB);
 
     float *lb32 = reinterpret_cast<float *>(lds) + (size_t)r0 * kWave + lane;  // [t * 64]
@@ -252,15 +253,14 @@ __global__ __launch_bounds__(MAXT) void k_refine_wave(const unsigned char *__res
                 y[u] = k0 + u < Nr ? v : 0.0f;
             }
             fence(y[KB - 1]);
+            // (rows padded with zeros to a multiple of KB)
             const cptr<float> a = here(rr, y[KB - 1]) + k0, b = here(rl, y[KB - 1]) + k0;
-            const int last = Nr - 1 - k0;  // the row's last entry (y is 0 past it)
 #pragma unroll
             for (int u = 0; u < KB; ++u)
 #pragma unroll
                 for (int c = 0; c < H; ++c) {
-                    const int e = c * Nr + min(u, last);
-                    zr[c] = fmaf(a[e], y[u], zr[c]);
-                    zl[c] = fmaf(b[e], y[u], zl[c]);
+                    zr[c] = fmaf(a[c * lsv + u], y[u], zr[c]);
+                    zl[c] = fmaf(b[c * lsv + u], y[u], zl[c]);
                 }
         }
 #pragma unroll
@@ -422,6 +422,8 @@ hipError_t go_refw(const sbs_lhs *h, const RefwChoice &c, const float *b, double
     a.rec_bwd = (int)sp.refine.bwd;
     a.rec_spk = (int)sp.refine.spk;
     a.rec_band = (int)sp.refine.band;
+    a.rec_sinv = (int)sp.refine.sinv;
+    a.ldsinv = sp.refine.ldsinv;
     a.n = (int)h->n;
     a.P = sp.P;
     a.Nr = sp.Nr;

@@ -136,7 +136,6 @@ void emulate_refine(const sbs_lhs &h, const SepPlan &pp, const double *rhs, int6
     const int F = H == 1 ? 2 : 3, Bk = H == 1 ? 1 : 2;
     const unsigned char *blob = static_cast<const unsigned char *>(pp.blob32);
     const float *scf = reinterpret_cast<const float *>(blob + pp.fac_bytes32 + pp.spk_bytes32);
-    const float *sinv = reinterpret_cast<const float *>(blob + pp.fac_bytes32 + pp.spk_bytes32 + pp.scf_bytes32);
     const int *map = reinterpret_cast<const int *>(blob + pp.fac_bytes32 + pp.spk_bytes32 + pp.scf_bytes32 +
                                                    pp.sinv_bytes32);
     const unsigned char *rec = static_cast<const unsigned char *>(pp.refine.base);
@@ -144,6 +143,8 @@ void emulate_refine(const sbs_lhs &h, const SepPlan &pp, const double *rhs, int6
     const float *bwd = reinterpret_cast<const float *>(rec + pp.refine.bwd);
     const float *spk = reinterpret_cast<const float *>(rec + pp.refine.spk);
     const double *band = reinterpret_cast<const double *>(rec + pp.refine.band);
+    const float *sinv = reinterpret_cast<const float *>(rec + pp.refine.sinv);
+    const int lds = pp.refine.ldsinv;
     const int64_t n = h.n, np = (int64_t)P * lb;
     auto solve32 = [&](std::vector<float> &w) {
         for (int p = 0; p < P; ++p) {
@@ -184,7 +185,9 @@ void emulate_refine(const sbs_lhs &h, const SepPlan &pp, const double *rhs, int6
         }
         for (int r = 0; r < Nr; ++r) {
             float v = 0.0f;
-            for (int k = 0; k < Nr; ++k) v = std::fma(sinv[(size_t)r * Nr + k], yh[k], v);
+            for (int k = 0; k < Nr; ++k) v = std::fma(sinv[(size_t)r * lds + k], yh[k], v);
+            for (int k = Nr; k < lds; ++k)
+                if (sinv[(size_t)r * lds + k] != 0.0f) v = NAN;  // the padding is zero
             z[r] = v;
         }
         for (int p = 0; p < P; ++p) {
