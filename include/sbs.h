@@ -212,7 +212,10 @@ sbs_status sbs_auto_variant(sbs_handle h, int64_t m, int32_t dtype,
  * The FP32 solves use the FP32 rounding of the FP64 factor.  When the
  * matrix has a partition plan (see SBS_VARIANT_PARTITION) all passes run in
  * one kernel that keeps each system's b and x on chip, so b is read once and
- * x written once; `work` is then not touched.
+ * x written once; `work` is then not touched.  That kernel holds 64 systems
+ * per workgroup with one wave per block of rows where the separator plan
+ * allows (at most 16 blocks of 32 rows or 8 of 64, and b of the 64 systems
+ * within the LDS: n up to about 560), else the pair-form plan's kernel.
  *
  *  b          device, n*m floats, interleaved, read only.
  *  x          device, n*m doubles, interleaved, written (may not alias b).

@@ -98,15 +98,18 @@ sbs_status upload(sbs_lhs *h, const std::vector<Row64> &r64, const double *B) {
 bool aligned(const void *p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
 
 // Which partitioned form runs: the separator kernel when it fills the GPU
-// with whole row runs; else the pair kernel; else a separator shape (for
-// AUTO only one whose plan sits in LDS or whose row runs are at least 128
-// bytes: a plan read from global memory with shorter runs loses to the
-// chunked sweep).  0: none (AUTO then runs the sweeps), 1: separator, 2: pair.
+// with whole row runs from a plan in LDS; else the pair kernel; else a
+// separator shape (for AUTO only one whose plan sits in LDS or whose row
+// runs are at least 128 bytes: a plan read from global memory with shorter
+// runs loses to the chunked sweep).  A plan read from global memory loses
+// to the pair form (random-band pentadiagonal n = 1024: 263.6 us against
+// 225.6 us), so it runs only where the pair form has no plan.
+// 0: none (AUTO then runs the sweeps), 1: separator, 2: pair.
 int pick_partition(const sbs_lhs *h, int t, int64_t m, const void *rhs, bool for_auto, sbs::SepChoice *sc,
                    sbs::PartChoice *pc) {
     const bool sep = sbs::choose_sep(h, t, m, rhs, sc);
     const bool part = sbs::choose_partition(h, t, m, pc);
-    if (sep && sbs::sep_fills(h, t, m, *sc)) return 1;
+    if (sep && !sc->gf && sbs::sep_fills(h, t, m, *sc)) return 1;
     if (part) return 2;
     const size_t elem = t == 0 ? 8 : 4;
     if (sep && (!for_auto || !sc->gf || (size_t)sc->S * elem >= 128)) return 1;

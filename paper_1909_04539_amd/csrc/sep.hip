@@ -10,20 +10,22 @@
 //   1. runs the Section 3.1 / 4.1 recurrences over its block with the
 //      block's interior factor (separator rows are identity rows, so they pass
 //      through holding their right-hand sides);
-//   2. publishes the first H values of its block solution to LDS;
-//   3. forms its separator's right-hand side yhat = f_sep - (couplings of the
-//      separator rows to the interior rows on either side) . g, the right
-//      neighbour's values coming from LDS;
-//   4. the separators of all S systems follow as Z = S^{-1} Yhat, a dense
+//   2. writes to LDS its two parts of the separator right-hand sides
+//      yhat = f_sep - (couplings of the separator rows to the interior rows
+//      on either side) . g: its own separator's f_sep less the couplings to
+//      the block's last interior rows (redL), and minus the previous
+//      separator's couplings to the block's first rows (redR); one barrier;
+//   3. the separators of all S systems follow as Z = S^{-1} Yhat, a dense
 //      (Nr x Nr)(Nr x S) product on the matrix cores in FP64 (per-lane dot
 //      products otherwise);
-//   5. corrects its interior rows x = g - V z_own - W z_prev, takes its
+//   4. corrects its interior rows x = g - V z_own - W z_prev, takes its
 //      separator rows from z, and stores every row once, non-temporally,
 //      loading the next group's rows into the registers it frees.
 // Each right-hand side crosses HBM once in and once out (16 bytes per FP64
 // unknown).  The block factors, spikes V / W, separator band rows and S^{-1}
 // depend only on the shared matrix; they are computed once on the host and
-// copied into LDS once per persistent workgroup.
+// copied into LDS once per persistent workgroup (where the whole plan does
+// not fit, only S^{-1} is, and the rest is read from global memory).
 #include <algorithm>
 
 #include "internal.h"
@@ -475,7 +477,7 @@ __global__ __launch_bounds__(MAXT) void k_sep(const unsigned char *__restrict__ 
                 }
         }
         __syncthreads();
-        // 4. separators
+        // 3. separators
         T zr[H][VEC], zl[H][VEC];
         if (Nr == 0) {
 #pragma unroll
@@ -535,7 +537,7 @@ __global__ __launch_bounds__(MAXT) void k_sep(const unsigned char *__restrict__ 
             // every lane has read redL / redR before the next group writes them
             __syncthreads();
         }
-        // 5. correction and stores
+        // 4. correction and stores
         T *dst = out + (int64_t)r0 * m + col(g);
         // the spikes of GC rows per round trip; from global memory (GF) the
         // next rows' spikes are loaded before the current rows are stored,
@@ -693,7 +695,7 @@ bool choose_sep(const sbs_lhs *h, int tc, int64_t m, const void *x, SepChoice *o
     const size_t elem = tc == 0 ? 8 : 4;
     const int cus = cu_count(h->device);
     SepChoice best;
-    int64_t best_key[4] = {-1, -1, -1, -1};
+    int64_t best_key[5] = {-1, -1, -1, -1, -1};
     for (int q = 2; q >= 0; --q)
         for (int vec = 2; vec >= 1; --vec)
             for (int S = 64; S >= 1; S /= 2) {
@@ -701,14 +703,15 @@ bool choose_sep(const sbs_lhs *h, int tc, int64_t m, const void *x, SepChoice *o
                 if (!sep_fit(h, tc, m, x, q, vec, S, kSepDefaultFlags, &c)) continue;
                 const int64_t groups = (m + S - 1) / S;
                 const int64_t engaged = std::min<int64_t>(groups, (int64_t)cus * c.wgs);
-                // rows read in whole 256-byte runs, 16-byte accesses, then
-                // lanes at work (up to 8 waves per CU)
+                // CUs engaged, the plan held in LDS, rows read in whole
+                // 256-byte runs, 16-byte accesses, then lanes at work (up to
+                // 8 waves per CU)
                 const int64_t run = std::min<int64_t>((int64_t)S * elem, 256);
                 const int64_t acc = (int64_t)vec * elem;
                 const int64_t lanes = std::min<int64_t>(engaged * c.threads, (int64_t)cus * 8 * kWave);
-                const int64_t key[4] = {std::min<int64_t>(engaged, cus), run, acc, lanes};
-                if (std::lexicographical_compare(best_key, best_key + 4, key, key + 4)) {
-                    std::copy(key, key + 4, best_key);
+                const int64_t key[5] = {std::min<int64_t>(engaged, cus), c.gf ? 0 : 1, run, acc, lanes};
+                if (std::lexicographical_compare(best_key, best_key + 5, key, key + 5)) {
+                    std::copy(key, key + 5, best_key);
                     best = c;
                 }
             }

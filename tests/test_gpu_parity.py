@@ -75,7 +75,7 @@ def partition_available(kind, n, elem=8, m=1 << 20, cus=256):
 def separator_available(kind, n, elem=8, m=1 << 20):
     """Mirror of the library's rule for the separator form (matrices whose
     blocks all differ): some block length lb in (16, 32, 64) with
-    P = ceil(n/lb) <= 64 blocks and at most 96 separator unknowns h(P-1),
+    P = ceil(n/lb) <= 64 blocks and at most 128 separator unknowns h(P-1),
     whose block factors + spikes + separator band rows + inverse of the
     separator system + block map, with the published block tops and the
     separator right-hand sides (and, in FP64, the separators) of one
@@ -86,12 +86,47 @@ def separator_available(kind, n, elem=8, m=1 << 20):
     for lb in (16, 32, 64):
         P = -(-n // lb)
         Nr = h * (P - 1)
-        if P > 64 or Nr > 96:
+        if P > 64 or Nr > 128:
             continue
         blob = (r16(P * lb * row) + r16(P * lb * 2 * h * elem) + r16(P * h * (2 * h + 1) * elem)
                 + r16(Nr * Nr * elem) + r16(P * 4))
         if blob + r16(P * h * elem) + r16((Nr + 1) * elem) * (2 if elem == 8 else 1) <= 160 * 1024:
             return True
+    return False
+
+
+def separator_in_memory_available(kind, n, elem=8, m=1 << 20):
+    """Mirror of the library's rule for the separator form with its plan
+    read from global memory (taken where the whole plan does not fit the
+    LDS): blocks of 32 rows with two systems per lane (m even) or of 64 rows
+    with one, P = ceil(n/lb) <= 64 blocks, at most 128 separator unknowns,
+    a workgroup of (S / vec) * P threads within the shape's limit (512 for
+    FP64, 1024 for FP32), and S^{-1} plus the separator buffers (two for
+    FP32; three for FP64, or two where the separators overwrite their
+    right-hand sides: whole waves, one matrix-core tile per wave) within
+    160 KiB of LDS."""
+    h = kind // 2
+    r16 = lambda v: -(-v // 16) * 16
+    maxt = 512 if elem == 8 else 1024
+    for lb, vec in ((32, 2), (64, 1)):
+        if vec == 2 and m % 2:
+            continue
+        P = -(-n // lb)
+        Nr = h * (P - 1)
+        if P > 64 or Nr > 128:
+            continue
+        for S in (64, 32, 16, 8, 4, 2, 1):
+            if S < vec or S % vec or S > m:
+                continue
+            threads = (S // vec) * P
+            if threads > maxt:
+                continue
+            sinv, red = r16(Nr * Nr * elem), r16(S * (Nr + 1) * elem)
+            if sinv + red * (3 if elem == 8 else 2) <= 160 * 1024:
+                return True
+            tiles = -(-Nr // 16) * -(-S // 16)
+            if elem == 8 and sinv + 2 * red <= 160 * 1024 and threads % 64 == 0 and tiles <= threads // 64:
+                return True
     return False
 
 
@@ -119,7 +154,7 @@ def test_fp64_matches_oracle(kind, variant, n, m):
     rhs = np.random.default_rng(n * 7 + m).uniform(-1, 1, (n, m))
     if (variant == sbs.VARIANT_CHUNKED and not chunked_fits(kind, n)) or \
             (variant == sbs.VARIANT_PARTITION and not partition_available(kind, n, m=m)
-             and not separator_available(kind, n, m=m)):
+             and not separator_available(kind, n, m=m) and not separator_in_memory_available(kind, n, m=m)):
         with pytest.raises(sbs.SbsError) as e:
             gpu_solve(kind, B, rhs, variant)
         assert e.value.status == 1
@@ -160,12 +195,18 @@ def test_partition_plan_rule():
     assert not partition_available(5, 2048) and partition_available(5, 1024) and partition_available(3, 2048)
     assert not separator_available(5, 2048) and separator_available(5, 1024) and separator_available(3, 2048)
     assert separator_available(3, 3000, elem=4) and not partition_available(3, 3000, elem=4)
+    # with the plan read from global memory the separator form reaches
+    # penta n = 2048 (and 3000 with 64-row blocks), not 5000
+    assert separator_in_memory_available(5, 2048) and separator_in_memory_available(5, 3000, m=33)
+    assert not separator_in_memory_available(5, 5000)
 
 
 @pytest.mark.parametrize("kind", [3, 5])
 @pytest.mark.parametrize("n", [1, 40, 64, 65, 700, 1024, 1500, 2048, 3000, 5000])
 def test_auto_variant_query(kind, n):
     # what AUTO runs: partitioned when a plan exists, else resident / chunked / stream
+    # (for 1000 systems AUTO never takes the separator form with its plan in
+    # memory: its shape with the most workgroups has runs of 16 or 32 bytes)
     with sbs.SharedLhs(kind, bands_for(kind, n, n)) as lhs:
         for dtype, elem in ((sbs.SBS_F64, 8), (sbs.SBS_F32, 4)):
             if partition_available(kind, n, elem, m=1000) or separator_available(kind, n, elem, m=1000):
@@ -182,7 +223,8 @@ def test_auto_variant_query(kind, n):
 @pytest.mark.parametrize("kind", [3, 5])
 @pytest.mark.parametrize("n,m", [(64, 4096), (65, 33), (129, 1000), (500, 17), (1024, 3000), (2048, 130)])
 def test_partition_fp32(kind, n, m):
-    if not partition_available(kind, n, elem=4, m=m) and not separator_available(kind, n, elem=4, m=m):
+    if not partition_available(kind, n, elem=4, m=m) and not separator_available(kind, n, elem=4, m=m) \
+            and not separator_in_memory_available(kind, n, elem=4, m=m):
         pytest.skip("no partition plan")
     B = bands_for(kind, n, 9 + n)
     rhs = np.random.default_rng(n + m).uniform(-1, 1, (n, m)).astype(np.float32)
@@ -261,11 +303,17 @@ def test_handle_storage_is_independent_of_batch_size():
             rows = (n + 63) // 64 * 64
             # FP64 factor + FP32 shadow + original bands, per padded row ...
             per_row = {3: 32 + 16 + 64, 5: 64 + 32 + 64}[kind]
-            # ... plus up to three partition plans (block factors and spikes in
-            # FP64 and FP32, an interface inverse of at most 90 x 90, a block
-            # map of at most 64 ints, each blob 256-byte aligned)
+            # ... plus up to three pair-form and three separator plans (block
+            # factors and spikes in FP64 and FP32, an interface inverse of at
+            # most 90 x 90 or 128 x 128 in both precisions, a block map of at
+            # most 64 ints, each blob 256-byte aligned) and, for the 32- and
+            # 64-row separator plans, the mixed-precision kernel's copy (FP32
+            # coefficients and spikes, FP64 band rows, FP32 inverse)
             plan_row = {3: (32 + 16) * 3 // 2, 5: (64 + 32) * 3 // 2}[kind]
-            assert rows * per_row <= lhs.device_bytes <= rows * per_row + 3 * (rows * plan_row + 90 * 90 * 12 + 2048)
+            rec_row = {3: 5 * 4 + 3 * 8, 5: 9 * 4 + 5 * 8}[kind]
+            bound = (rows * (per_row + 6 * plan_row + 2 * rec_row) + 3 * 90 * 90 * 12 + 3 * 128 * 128 * 12
+                     + 2 * 128 * 128 * 4 + 16 * 2048)
+            assert rows * per_row <= lhs.device_bytes <= bound, (kind, n, lhs.device_bytes, bound)
     # Shared LHS storage against one copy per system (the storage counts
     # closing Sections 3.1 and 4.1): 3N + MN vs 4MN, 5N + MN vs 6MN.
     M, N = 65536, 1024

@@ -37,12 +37,15 @@ def chunked_fits(n, elem=8):
     return ((n + 31) // 32) * 64 * elem + 2 * 32 * row <= 160 * 1024
 
 
-def partition_available(n):
+def partition_available(n, m=1):
     """Periodic plans: n a whole number P >= 2 of blocks of 16, 32 or 64 rows,
     and either at most 90 interface unknowns in the pair form (2 per block:
     the wrap adds one pair) or, in the separator form, at most 64 blocks
     (one separator each) whose factors, spikes and separator inverse fit in
-    the LDS with room for one system (the ring bands here differ per row)."""
+    the LDS with room for one system (the ring bands here differ per row), or
+    -- with the plan read from global memory, blocks of 32 rows with two
+    systems per lane (m even) or of 64 rows -- whose separator inverse and
+    buffers for one workgroup of at most 512 threads fit there."""
     r16 = lambda v: -(-v // 16) * 16
     for lb in (16, 32, 64):
         P = n // lb
@@ -53,6 +56,14 @@ def partition_available(n):
         blob = r16(P * lb * 32) + r16(P * lb * 16) + r16(P * 3 * 8) + r16(P * P * 8) + r16(P * 4)
         if P <= 64 and blob + r16(P * 8) + 2 * r16((P + 1) * 8) <= 160 * 1024:
             return True
+    for lb, vec in ((32, 2), (64, 1)):
+        P = n // lb
+        if n % lb or P < 2 or P > 64 or (vec == 2 and m % 2) or vec > m:
+            continue
+        for S in (64, 32, 16, 8, 4, 2, 1):
+            if S >= vec and S % vec == 0 and (S // vec) * P <= 512 and \
+                    r16(P * P * 8) + 3 * r16(S * (P + 1) * 8) <= 160 * 1024:
+                return True
     return False
 
 
@@ -78,7 +89,7 @@ def test_periodic_parity(n, m, variant):
         pytest.skip("checkpoints exceed the chunked variant's LDS")
     print(f"case periodic n={n} m={m} variant={variant}", flush=True)
     B = ring_bands(n, n + m)
-    if variant == sbs.VARIANT_PARTITION and not partition_available(n):
+    if variant == sbs.VARIANT_PARTITION and not partition_available(n, m):
         with pytest.raises(sbs.SbsError) as e:
             gpu_solve(B, np.zeros((n, m)), variant)
         assert e.value.status == 1
