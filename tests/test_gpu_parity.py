@@ -345,7 +345,11 @@ def test_factor_errors_on_gpu():
 
 
 # ----------------------------------------------------------------- mixed precision
-@pytest.mark.parametrize("kind,n,m", [(3, 512, 4096), (3, 1, 5), (3, 33, 70), (5, 700, 300), (5, 2, 64)])
+# n = 512 tri and 300 tri / penta: the one-wave-per-block kernel (32-row
+# blocks; 64-row blocks for penta 512, whose 32-row edges exceed the LDS);
+# 700 penta: the pair-form kernel; 1 and 2 rows: one block
+@pytest.mark.parametrize("kind,n,m", [(3, 512, 4096), (3, 1, 5), (3, 33, 70), (5, 700, 300), (5, 2, 64),
+                                      (5, 512, 256), (5, 300, 130), (3, 300, 65)])
 def test_refined_matches_fp64_oracle(kind, n, m):
     if kind == 3:
         wl = W.config3(n=n, m=m)
