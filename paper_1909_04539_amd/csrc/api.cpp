@@ -1,10 +1,14 @@
 // C-ABI entry points: argument checking, the host-side FP64 factorisation of
 // the shared matrix, its upload, and dispatch to the HIP kernels.
+#include <atomic>
 #include <climits>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <new>
+#include <tuple>
 #include <vector>
 
 #include "factor_rows.h"
@@ -105,8 +109,8 @@ bool aligned(const void *p, size_t a) { return (reinterpret_cast<uintptr_t>(p) %
 // to the pair form (random-band pentadiagonal n = 1024: 263.6 us against
 // 225.6 us), so it runs only where the pair form has no plan.
 // 0: none (AUTO then runs the sweeps), 1: separator, 2: pair.
-int pick_partition(const sbs_lhs *h, int t, int64_t m, const void *rhs, bool for_auto, sbs::SepChoice *sc,
-                   sbs::PartChoice *pc) {
+int pick_uncached(const sbs_lhs *h, int t, int64_t m, const void *rhs, bool for_auto, sbs::SepChoice *sc,
+                  sbs::PartChoice *pc) {
     const bool sep = sbs::choose_sep(h, t, m, rhs, sc);
     const bool part = sbs::choose_partition(h, t, m, pc);
     if (sep && !sc->gf && sbs::sep_fills(h, t, m, *sc)) return 1;
@@ -116,9 +120,70 @@ int pick_partition(const sbs_lhs *h, int t, int64_t m, const void *rhs, bool for
     return 0;
 }
 
+// The choice depends on the handle, the dtype, m, whether rhs is aligned for
+// two systems per lane and AUTO or not; it is made once and kept (weighing
+// every shape costs several microseconds, as much as a small solve).
+int pick_partition(const sbs_lhs *h, int t, int64_t m, const void *rhs, bool for_auto, sbs::SepChoice *sc,
+                   sbs::PartChoice *pc) {
+    struct Pick {
+        int form;
+        sbs::SepChoice sc;
+        sbs::PartChoice pc;
+    };
+    static std::mutex mu;
+    static std::map<std::tuple<uint64_t, int, int64_t, bool, bool>, Pick> known;
+    const bool al = reinterpret_cast<uintptr_t>(rhs) % (2 * (t == 0 ? 8 : 4)) == 0;
+    const auto key = std::make_tuple(h->id, t, m, al, for_auto);
+    {
+        std::lock_guard<std::mutex> g(mu);
+        auto it = known.find(key);
+        if (it != known.end()) {
+            *sc = it->second.sc;
+            *pc = it->second.pc;
+            return it->second.form;
+        }
+    }
+    const int form = pick_uncached(h, t, m, rhs, for_auto, sc, pc);
+    std::lock_guard<std::mutex> g(mu);
+    if (known.size() >= 4096) known.clear();  // bounded: many batch sizes only cost a new choice
+    known[key] = Pick{form, *sc, *pc};
+    return form;
+}
+
 }  // namespace
 
 namespace sbs {
+
+int device_cus(int device) {
+    static std::mutex mu;
+    static std::map<int, int> known;
+    std::lock_guard<std::mutex> g(mu);
+    auto it = known.find(device);
+    if (it != known.end()) return it->second;
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || cus < 1)
+        return 256;  // not kept: asked again next time
+    known[device] = cus;
+    return cus;
+}
+
+int occupancy(const void *fn, int threads, size_t lds) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    static std::mutex mu;
+    static std::map<std::tuple<const void *, int, size_t, int>, int> known;
+    const auto key = std::make_tuple(fn, threads, lds, dev);
+    {
+        std::lock_guard<std::mutex> g(mu);
+        auto it = known.find(key);
+        if (it != known.end()) return it->second;
+    }
+    int wgs = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&wgs, fn, threads, lds) != hipSuccess) return 0;
+    std::lock_guard<std::mutex> g(mu);
+    known[key] = wgs;
+    return wgs;
+}
 
 sbs_status refined_check(const sbs_lhs *h, const float *b, const double *x, int64_t m, int32_t sweeps) {
     if (!h || m < 0 || sweeps < 0 || sweeps > 8 || h->kind == SBS_TRI_PERIODIC) return SBS_ERR_INVALID_ARG;
@@ -198,6 +263,8 @@ sbs_status sbs_factor_shared_lhs(int32_t kind, int64_t n, const double *bands, s
             }
     sbs_lhs *h = new (std::nothrow) sbs_lhs();
     if (!h) return SBS_ERR_NO_MEMORY;
+    static std::atomic<uint64_t> next_id{1};
+    h->id = next_id++;
     h->kind = kind;
     h->n = n;
     h->rows = (n + kRowPad - 1) / kRowPad * kRowPad;

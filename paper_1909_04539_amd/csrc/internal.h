@@ -160,9 +160,18 @@ struct sbs_lhs {
     sbs::BandCoef coef{};
     int64_t device_bytes = 0;
     int device = 0;
+    uint64_t id = 0;  // unique per handle in the process (keys the host's cached launch choices)
 };
 
 namespace sbs {
+
+// Host-side launch figures, queried from the runtime once and then kept
+// (every solve chooses its shape, and the queries cost microseconds each):
+// compute units of a device, and workgroups of kernel `fn` resident per CU
+// at `threads` threads and `lds` bytes of dynamic LDS on the current device
+// (0 if the runtime reports an error).
+int device_cus(int device);
+int occupancy(const void *fn, int threads, size_t lds);
 
 struct SweepArgs {
     const sbs_lhs *h;

@@ -1552,10 +1552,7 @@ int part_wgs_lb(int lb, int threads, size_t lds) {
     const void *fn = nullptr;
     hipError_t e = lb == 16 ? part_kernel<KIND, T, 16, CN>(&fn)
                             : lb == 32 ? part_kernel<KIND, T, 32, CN>(&fn) : part_kernel<KIND, T, 64, CN>(&fn);
-    int wgs = 0;
-    if (e != hipSuccess || hipOccupancyMaxActiveBlocksPerMultiprocessor(&wgs, fn, threads, lds) != hipSuccess)
-        return 0;
-    return wgs;
+    return e != hipSuccess ? 0 : occupancy(fn, threads, lds);
 }
 
 // The blocks of a periodic tridiagonal matrix are plain tridiagonal.
@@ -1587,8 +1584,7 @@ hipError_t go_part(const sbs_lhs *h, const PartChoice &c, const void *in, void *
     if (hipError_t e = part_kernel<KIND, T, LB, CN>(&fn); e != hipSuccess) return e;
     if (c.threads > MAXT) return hipErrorInvalidValue;
     const int ngroups = (int)((m + c.S - 1) / c.S);
-    int cus = 256;
-    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, h->device);
+    const int cus = device_cus(h->device);
     const int per_cu = std::max(1, c.wgs);
     const int grid = (int)std::min<int64_t>(ngroups, (int64_t)cus * per_cu);
     hipLaunchKernelGGL(kern, dim3(grid), dim3(c.threads), c.lds, s,
@@ -1614,8 +1610,7 @@ hipError_t go_part_rows(const sbs_lhs *h, const PartChoice &c, double *x, int64_
     if (attr != hipSuccess) return attr;
     if (c.threads > MAXT) return hipErrorInvalidValue;
     const int ngroups = (int)((m + c.S - 1) / c.S);
-    int cus = 256;
-    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, h->device);
+    const int cus = device_cus(h->device);
     const int grid = (int)std::min<int64_t>(ngroups, (int64_t)cus * std::max(1, c.wgs));
     hipLaunchKernelGGL(kern, dim3(grid), dim3(c.threads), c.lds, s, static_cast<const unsigned char *>(pp.blob64),
                        (int)pp.fac_bytes64, (int)pp.spk_bytes64, (int)pp.rinv_bytes64, (int)h->n, pp.P, pp.Nr, c.S,
@@ -1655,10 +1650,7 @@ int refine_wgs_per_cu(int kind, int lb, int threads, size_t lds) {
         e = lb == 16 ? refine_kernel<SBS_TRI, 16>(&fn) : refine_kernel<SBS_TRI, 32>(&fn);
     else
         e = lb == 16 ? refine_kernel<SBS_PENTA, 16>(&fn) : refine_kernel<SBS_PENTA, 32>(&fn);
-    int wgs = 0;
-    if (e != hipSuccess || hipOccupancyMaxActiveBlocksPerMultiprocessor(&wgs, fn, threads, lds) != hipSuccess)
-        return 0;
-    return wgs;
+    return e != hipSuccess ? 0 : occupancy(fn, threads, lds);
 }
 
 template <int KIND, int LB>
@@ -1671,8 +1663,7 @@ hipError_t go_part_refine(const sbs_lhs *h, const PartChoice &c, const float *b,
     if (hipError_t e = refine_kernel<KIND, LB>(&fn); e != hipSuccess) return e;
     if (c.threads > MAXT) return hipErrorInvalidValue;
     const int ngroups = (int)((m + c.S - 1) / c.S);
-    int cus = 256;
-    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, h->device);
+    const int cus = device_cus(h->device);
     const int per_cu = std::max(1, c.wgs);
     const int grid = std::min(ngroups, cus * per_cu);
     hipLaunchKernelGGL(kern, dim3(grid), dim3(c.threads), c.lds, s, static_cast<const unsigned char *>(pp.blob32),
@@ -1693,8 +1684,7 @@ hipError_t go_part_refine(const sbs_lhs *h, const PartChoice &c, const float *b,
 // 3.54 ms).
 bool choose_partition_refine(const sbs_lhs *h, int64_t m, PartChoice *out) {
     const int H = h->kind / 2;
-    int cus = 256;
-    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, h->device);
+    const int cus = device_cus(h->device);
     PartChoice best;
     int64_t best_waves = -1;
     int best_wgs = 0;
@@ -1768,8 +1758,7 @@ hipError_t launch_partition_refine(const sbs_lhs *h, const PartChoice &c, const 
 bool choose_partition(const sbs_lhs *h, int tc, int64_t m, PartChoice *out, int cn, bool rows) {
     const size_t elem = tc == 0 ? 8 : 4;
     const int H = part_kind(h->kind) / 2;
-    int cus = 256;
-    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, h->device);
+    const int cus = device_cus(h->device);
     PartChoice best;
     int64_t best_lanes = -1, best_cus = -1;
     bool best_lines = false;

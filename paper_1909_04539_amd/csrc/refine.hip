@@ -430,8 +430,7 @@ hipError_t go_refw(const sbs_lhs *h, const RefwChoice &c, const float *b, double
     a.ngroups = (int)((m + kWave - 1) / kWave);
     a.sweeps = sweeps;
     a.m = m;
-    int cus = 256;
-    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, h->device);
+    const int cus = device_cus(h->device);
     const int grid = std::min(a.ngroups, cus);
     hipLaunchKernelGGL((k_refine_wave<KIND, LB, refw_maxt<KIND, LB>()>), dim3(grid), dim3(sp.P * kWave), c.lds, s,
                        static_cast<const unsigned char *>(sp.blob32), a,

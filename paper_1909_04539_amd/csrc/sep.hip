@@ -644,11 +644,7 @@ size_t sep_lds(const SepPlan &sp, int tc, int S, bool gf, bool alias) {
     return plan + red * (tc == 0 && !alias ? 3 : 2);
 }
 
-int cu_count(int device) {
-    int cus = 256;
-    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device);
-    return cus;
-}
+int cu_count(int device) { return device_cus(device); }
 
 // Checks one shape and fills in its launch figures; false if it cannot run.
 // The plan goes to LDS whole where it fits with the group's buffers, else
@@ -674,7 +670,7 @@ bool sep_fit(const sbs_lhs *h, int tc, int64_t m, const void *x, int q, int vec,
     // the separators in redL: one matrix-core tile per wave
     if (alias && (threads % kWave || ((sp.Nr + 15) / 16) * ((S + 15) / 16) > threads / kWave)) return false;
     int wgs = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&wgs, fn, threads, lds) != hipSuccess || wgs < 1) return false;
+    if ((wgs = occupancy(fn, threads, lds)) < 1) return false;
     c->plan = q;
     c->vec = vec;
     c->S = S;

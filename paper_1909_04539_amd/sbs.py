@@ -195,8 +195,10 @@ def sbs_solve_batch(h: int, rhs: torch.Tensor, stream=None) -> torch.Tensor:
     return rhs
 
 
-def sbs_solve_batch_variant(h: int, rhs: torch.Tensor, variant: int, stream=None) -> torch.Tensor:
-    _, n, _ = sbs_handle_info(h)
+def sbs_solve_batch_variant(h: int, rhs: torch.Tensor, variant: int, stream=None, n: int = None) -> torch.Tensor:
+    """`n`: the handle's row count when the caller knows it (saves a query)."""
+    if n is None:
+        _, n, _ = sbs_handle_info(h)
     p = _rhs(rhs, n)
     _check(lib().sbs_solve_batch_variant(h, p, rhs.shape[1], _dtype_code(rhs), variant, _stream(stream)),
            "sbs_solve_batch_variant")
@@ -312,7 +314,7 @@ class SharedLhs:
         _, self.n, self.device_bytes = sbs_handle_info(self.handle)
 
     def solve(self, rhs: torch.Tensor, variant: int = VARIANT_AUTO, stream=None) -> torch.Tensor:
-        return sbs_solve_batch_variant(self.handle, rhs, variant, stream)
+        return sbs_solve_batch_variant(self.handle, rhs, variant, stream, n=self.n)
 
     def cn_step(self, c: torch.Tensor, steps: int = 1, stream=None) -> torch.Tensor:
         return sbs_cn_step(self.handle, c, steps, stream)
