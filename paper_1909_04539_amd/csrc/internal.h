@@ -247,12 +247,14 @@ hipError_t launch_refine_wave(const sbs_lhs *h, const RefwChoice &c, const float
 struct SepChoice {
     int plan = -1, vec = 1, S = 0, threads = 0, flags = 0;
     bool gf = false;  // plan read from global memory, S^{-1} alone in LDS
+    bool cn = false;  // a Crank-Nicolson step (constant bands) instead of a solve
     size_t lds = 0;
     int wgs = 1;  // workgroups resident per CU at this size
 };
 // The shape AUTO runs for m systems at x (the alignment of x decides whether
 // pairs of systems can move as one access); false if no plan fits.
-bool choose_sep(const sbs_lhs *h, int tc, int64_t m, const void *x, SepChoice *out);
+// cn: shapes for a Crank-Nicolson step of a matrix with constant bands.
+bool choose_sep(const sbs_lhs *h, int tc, int64_t m, const void *x, SepChoice *out, bool cn = false);
 // A given shape (block length lb, VEC, S, flags); false if it cannot run.
 bool sep_shape(const sbs_lhs *h, int tc, int64_t m, const void *x, int lb, int vec, int S, int flags, SepChoice *out);
 // In place on the interleaved (n, m) array x (tc: 0 f64, 1 f32).

@@ -107,6 +107,7 @@ struct SepArgs {
     int fac_bytes, spk_bytes, scf_bytes, sinv_bytes, map_bytes;
     int n, P, Nr, S, ngroups, periodic, flags;
     int64_t m;
+    BandCoef coef;  // Crank-Nicolson steps: the matrix's constant band values
 };
 
 // Z = S^{-1} Yhat for the group on the matrix cores (Yhat = redl + redr, the
@@ -326,7 +327,15 @@ __device__ __forceinline__ void block_sweeps(const typename RowOf<KIND, T>::type
 // same plan).  The separators then overwrite redL, and the corrected rows
 // are stored after all of them are computed (a spike load issued after a
 // store would wait for that store).
-template <int KIND, typename T, int LB, int VEC, int MAXT, bool GF>
+//
+// CN: one Crank-Nicolson step c <- A^{-1} (2I - A) c (Sections 3.2, 4.2) of a
+// matrix whose bands are constant (the values in a.coef): with u = A^{-1} c in
+// registers, row t of the output is 2 u_t - sum_e coef_e u_{t-H+e}.  The rows
+// above the block are the previous block's separators (known to the lane);
+// the first H rows of the next block come through LDS, one more barrier.
+// Values outside the matrix are 0, so the constant coefficients also give
+// the truncated rows at its ends.
+template <int KIND, typename T, int LB, int VEC, int MAXT, bool GF, bool CN = false>
 __global__ __launch_bounds__(MAXT) void k_sep(const unsigned char *__restrict__ blob, SepArgs a, const T *in,
                                               T *out) {
     using Row = typename RowOf<KIND, T>::type;
@@ -360,6 +369,8 @@ __global__ __launch_bounds__(MAXT) void k_sep(const unsigned char *__restrict__ 
     // third buffer): the separators overwrite redL
     const bool alias = GF && (a.flags & 32);
     T *lz = alias ? lredl : reinterpret_cast<T *>(lds + plan_lds + 2 * sep_red_bytes<T>(S, Nr));
+    // CN: the first H rows of every block of the group, [S][P][H]
+    T *ltop = reinterpret_cast<T *>(lds + plan_lds + (alias ? 2 : 3) * sep_red_bytes<T>(S, Nr));
 
 
     const int Ls = S / VEC;  // lanes per block row
@@ -575,9 +586,62 @@ __global__ __launch_bounds__(MAXT) void k_sep(const unsigned char *__restrict__ 
                     if (t >= NI) val = has_sep ? zr[t >= NI ? t - NI : 0][v] : val;
                     v2[v] = val;
                 }
-                if (full || r0 + t < n) store_vec_nt<T, VEC>(dst + (int64_t)t * m, v2);
+                if constexpr (CN) {
+                    // computed here, not sunk past the barrier below (which
+                    // would keep every row's spikes live until then)
+#pragma unroll
+                    for (int v = 0; v < VEC; ++v) {
+                        x[t][v] = v2[v];
+                        asm volatile("" : "+v"(x[t][v]));
+                    }
+                } else if (full || r0 + t < n) {
+                    store_vec_nt<T, VEC>(dst + (int64_t)t * m, v2);
+                }
             }
             pin(zr[0][0]);
+        }
+        if constexpr (CN) {
+            // 5. Crank-Nicolson output rows from the block's solution
+#pragma unroll
+            for (int v = 0; v < VEC; ++v)
+#pragma unroll
+                for (int c = 0; c < H; ++c) ltop[((s0 + v) * P + p) * H + c] = x[c][v];
+            __syncthreads();
+            const bool has_next = a.periodic || p < P - 1;
+            const int pn = p == P - 1 ? 0 : p + 1;
+            T dn[H][VEC];
+#pragma unroll
+            for (int v = 0; v < VEC; ++v)
+#pragma unroll
+                for (int c = 0; c < H; ++c) {
+                    const T t0 = ltop[((s0 + v) * P + pn) * H + c];
+                    dn[c][v] = has_next ? t0 : T(0);
+                }
+            // rows above the block: the previous block's separators (0 above
+            // the first block of a matrix that does not wrap round)
+            const T c0 = (T)a.coef.c[0];
+            // one store pointer stepped row by row (opaque, so that the
+            // rows' addresses are not all formed up front and kept live)
+            T *q = dst;
+#pragma unroll
+            for (int t = 0; t < LB; ++t) {
+                T v2[VEC];
+#pragma unroll
+                for (int v = 0; v < VEC; ++v) {
+                    T ax = T(0);
+#pragma unroll
+                    for (int e = 0; e < NB; ++e) {
+                        const int i = t - H + e;
+                        const T u = i < 0 ? zl[i + H][v] : (i >= LB ? dn[i - LB][v] : x[i][v]);
+                        ax = e == 0 ? c0 * u : fma((T)a.coef.c[e], u, ax);
+                    }
+                    v2[v] = T(2) * x[t][v] - ax;
+                }
+                if (full || r0 + t < n) store_vec_nt<T, VEC>(q, v2);
+                q += m;
+                asm volatile("" : "+v"(q));
+                if (t % G == G - 1) pin(v2[0]);
+            }
         }
         if (g + grid < a.ngroups) load_group(g + grid);
     }
@@ -594,9 +658,9 @@ constexpr int sep_maxt() {
     return LB * VEC * (int)sizeof(T) / 4 <= 64 ? 1024 : 512;
 }
 
-template <int KIND, typename T, int LB, int VEC, bool GF>
+template <int KIND, typename T, int LB, int VEC, bool GF, bool CN = false>
 hipError_t sep_kernel(const void **fn) {
-    auto kern = k_sep<KIND, T, LB, VEC, sep_maxt<T, LB, VEC>(), GF>;
+    auto kern = k_sep<KIND, T, LB, VEC, sep_maxt<T, LB, VEC>(), GF, CN>;
     // once per instantiation; thread-safe static initialisation, so that
     // concurrent first launches from several host threads do not race
     static const hipError_t attr = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
@@ -608,9 +672,20 @@ hipError_t sep_kernel(const void **fn) {
 }
 
 // The shapes built: (LB, VEC) with at most 128 registers of values per lane;
-// with the plan in global memory (GF) the two longest, (32, 2) and (64, 1).
+// with the plan in global memory (GF) the two longest, (32, 2) and (64, 1);
+// Crank-Nicolson steps of pentadiagonal matrices (plan in LDS) (32, 1),
+// (32, 2) and (64, 1).
 template <int KIND, typename T>
-hipError_t sep_kernel_of(int lb, int vec, bool gf, const void **fn, int *maxt) {
+hipError_t sep_kernel_of(int lb, int vec, bool gf, bool cn, const void **fn, int *maxt) {
+    if (cn) {
+        if constexpr (KIND == SBS_PENTA) {
+            if (gf) return hipErrorInvalidValue;
+            if (lb == 32 && vec == 1) return *maxt = sep_maxt<T, 32, 1>(), sep_kernel<KIND, T, 32, 1, false, true>(fn);
+            if (lb == 32 && vec == 2) return *maxt = sep_maxt<T, 32, 2>(), sep_kernel<KIND, T, 32, 2, false, true>(fn);
+            if (lb == 64 && vec == 1) return *maxt = sep_maxt<T, 64, 1>(), sep_kernel<KIND, T, 64, 1, false, true>(fn);
+        }
+        return hipErrorInvalidValue;
+    }
     if (gf) {
         if (lb == 32 && vec == 2) return *maxt = sep_maxt<T, 32, 2>(), sep_kernel<KIND, T, 32, 2, true>(fn);
         if (lb == 64 && vec == 1) return *maxt = sep_maxt<T, 64, 1>(), sep_kernel<KIND, T, 64, 1, true>(fn);
@@ -626,21 +701,25 @@ hipError_t sep_kernel_of(int lb, int vec, bool gf, const void **fn, int *maxt) {
     return hipErrorInvalidValue;
 }
 
-hipError_t sep_fn(int kind, int tc, int lb, int vec, bool gf, const void **fn, int *maxt) {
+hipError_t sep_fn(int kind, int tc, int lb, int vec, bool gf, bool cn, const void **fn, int *maxt) {
     const int k = kind == SBS_PENTA ? SBS_PENTA : SBS_TRI;  // periodic blocks are plain tridiagonal
     if (k == SBS_TRI)
-        return tc == 0 ? sep_kernel_of<SBS_TRI, double>(lb, vec, gf, fn, maxt)
-                       : sep_kernel_of<SBS_TRI, float>(lb, vec, gf, fn, maxt);
-    return tc == 0 ? sep_kernel_of<SBS_PENTA, double>(lb, vec, gf, fn, maxt)
-                   : sep_kernel_of<SBS_PENTA, float>(lb, vec, gf, fn, maxt);
+        return tc == 0 ? sep_kernel_of<SBS_TRI, double>(lb, vec, gf, cn, fn, maxt)
+                       : sep_kernel_of<SBS_TRI, float>(lb, vec, gf, cn, fn, maxt);
+    return tc == 0 ? sep_kernel_of<SBS_PENTA, double>(lb, vec, gf, cn, fn, maxt)
+                   : sep_kernel_of<SBS_PENTA, float>(lb, vec, gf, cn, fn, maxt);
 }
 
 // LDS of one workgroup: the plan (GF: S^{-1} only), the two parts of the
 // separator right-hand sides and (FP64: the matrix-core product's output)
-// the separators, unless `alias` puts them in redL's storage.
-size_t sep_lds(const SepPlan &sp, int tc, int S, bool gf, bool alias) {
+// the separators, unless `alias` puts them in redL's storage; Crank-Nicolson
+// steps add the blocks' first rows after a third buffer.
+// (cn_h: the half band width H of a Crank-Nicolson step, 0 for a solve)
+size_t sep_lds(const SepPlan &sp, int tc, int S, bool gf, bool alias, int cn_h = 0) {
+    const size_t elem = tc == 0 ? 8 : 4;
     const size_t red = tc == 0 ? sep_red_bytes<double>(S, sp.Nr) : sep_red_bytes<float>(S, sp.Nr);
     const size_t plan = gf ? (tc == 0 ? sp.sinv_bytes64 : sp.sinv_bytes32) : sp.blob_bytes(tc);
+    if (cn_h) return plan + 3 * red + ((size_t)S * sp.P * cn_h * elem + 15) / 16 * 16;
     return plan + red * (tc == 0 && !alias ? 3 : 2);
 }
 
@@ -651,20 +730,24 @@ int cu_count(int device) { return device_cus(device); }
 // (or with flags bit 4) only S^{-1} does (GF), and where even that leaves no
 // room for a third FP64 buffer the separators overwrite redL (flags bit 5,
 // which only this function sets).
-bool sep_fit(const sbs_lhs *h, int tc, int64_t m, const void *x, int q, int vec, int S, int flags, SepChoice *c) {
+//
+// cn: a Crank-Nicolson step of a matrix with constant bands (plan in LDS only).
+bool sep_fit(const sbs_lhs *h, int tc, int64_t m, const void *x, int q, int vec, int S, int flags, SepChoice *c,
+             bool cn = false) {
     const SepPlan &sp = h->sep[q];
     const size_t elem = tc == 0 ? 8 : 4;
     if (!sp.ok || m < vec || S < vec || S % vec) return false;
     if (vec == 2 && (m % 2 || reinterpret_cast<uintptr_t>(x) % (2 * elem))) return false;
     flags &= ~32;
     bool gf = (flags & 16) != 0, alias = false;
-    if (!gf && sep_lds(sp, tc, S, false, false) > kMaxPartLdsBytes) gf = true;
-    if (gf && sep_lds(sp, tc, S, true, false) > kMaxPartLdsBytes) alias = tc == 0;
-    const size_t lds = sep_lds(sp, tc, S, gf, alias);
+    if (cn && gf) return false;
+    if (!cn && !gf && sep_lds(sp, tc, S, false, false) > kMaxPartLdsBytes) gf = true;
+    if (!cn && gf && sep_lds(sp, tc, S, true, false) > kMaxPartLdsBytes) alias = tc == 0;
+    const size_t lds = sep_lds(sp, tc, S, gf, alias, cn ? h->kind / 2 : 0);
     if (lds > kMaxPartLdsBytes) return false;
     const void *fn = nullptr;
     int maxt = 0;
-    if (sep_fn(h->kind, tc, sp.lb, vec, gf, &fn, &maxt) != hipSuccess) return false;
+    if (sep_fn(h->kind, tc, sp.lb, vec, gf, cn, &fn, &maxt) != hipSuccess) return false;
     const int threads = (S / vec) * sp.P;
     if (threads > maxt) return false;
     // the separators in redL: one matrix-core tile per wave
@@ -679,6 +762,7 @@ bool sep_fit(const sbs_lhs *h, int tc, int64_t m, const void *x, int q, int vec,
     c->wgs = wgs;
     c->flags = flags | (gf ? 16 : 0) | (alias ? 32 : 0);
     c->gf = gf;
+    c->cn = cn;
     return true;
 }
 
@@ -687,7 +771,7 @@ bool sep_fit(const sbs_lhs *h, int tc, int64_t m, const void *x, int q, int vec,
 // Default launch options: groups in launch order.
 constexpr int kSepDefaultFlags = 0;
 
-bool choose_sep(const sbs_lhs *h, int tc, int64_t m, const void *x, SepChoice *out) {
+bool choose_sep(const sbs_lhs *h, int tc, int64_t m, const void *x, SepChoice *out, bool cn) {
     const size_t elem = tc == 0 ? 8 : 4;
     const int cus = cu_count(h->device);
     SepChoice best;
@@ -696,7 +780,7 @@ bool choose_sep(const sbs_lhs *h, int tc, int64_t m, const void *x, SepChoice *o
         for (int vec = 2; vec >= 1; --vec)
             for (int S = 64; S >= 1; S /= 2) {
                 SepChoice c;
-                if (!sep_fit(h, tc, m, x, q, vec, S, kSepDefaultFlags, &c)) continue;
+                if (!sep_fit(h, tc, m, x, q, vec, S, kSepDefaultFlags, &c, cn)) continue;
                 const int64_t groups = (m + S - 1) / S;
                 const int64_t engaged = std::min<int64_t>(groups, (int64_t)cus * c.wgs);
                 // CUs engaged, the plan held in LDS, rows read in whole
@@ -733,7 +817,7 @@ hipError_t launch_sep(const sbs_lhs *h, const SepChoice &c, int tc, void *x, int
     const SepPlan &sp = h->sep[c.plan];
     const void *fn = nullptr;
     int maxt = 0;
-    if (hipError_t e = sep_fn(h->kind, tc, sp.lb, c.vec, c.gf, &fn, &maxt); e != hipSuccess) return e;
+    if (hipError_t e = sep_fn(h->kind, tc, sp.lb, c.vec, c.gf, c.cn, &fn, &maxt); e != hipSuccess) return e;
     if (c.threads > maxt) return hipErrorInvalidValue;
     const int64_t ngroups = (m + c.S - 1) / c.S;
     if (ngroups > 0x7fffffff) return hipErrorInvalidValue;
@@ -752,6 +836,7 @@ hipError_t launch_sep(const sbs_lhs *h, const SepChoice &c, int tc, void *x, int
     a.periodic = sp.periodic ? 1 : 0;
     a.flags = c.flags;
     a.m = m;
+    a.coef = h->coef;
     const int grid = (int)std::min<int64_t>(ngroups, (int64_t)cu_count(h->device) * std::max(1, c.wgs));
     const unsigned char *blob = static_cast<const unsigned char *>(f64 ? sp.blob64 : sp.blob32);
     void *args[] = {&blob, &a, &x, &x};

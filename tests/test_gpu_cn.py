@@ -92,6 +92,26 @@ def test_cn_constant_bands(kind, n, m, dtype, tol):
                                        if dtype == torch.float32 else C, 2)) <= tol
 
 
+@pytest.mark.parametrize("kind,n,m", [(5, 1024, 8192), (5, 1000, 8192), (5, 2048, 8194), (3, 1000, 8194),
+                                      (13, 1024, 8192)])
+@pytest.mark.parametrize("dtype,tol", [(torch.float64, 1e-12), (torch.float32, 1e-5)])
+def test_cn_constant_bands_large_batches(kind, n, m, dtype, tol):
+    # batches large enough to fill every CU with whole row runs: pentadiagonal
+    # steps run in the separator kernel (the rows above a block are the
+    # previous block's separators, the next block's first rows come through
+    # LDS), with a ragged last block, and in FP32 with twice the systems (64
+    # per workgroup); tridiagonal and periodic steps in the pair form
+    if dtype == torch.float32:
+        m *= 2
+    print(f"case kind={kind} n={n} m={m} dtype={dtype}", flush=True)
+    B = np.array(CONSTANT[kind])[:, None] * np.ones(n)
+    C = np.random.default_rng(n + m + kind).uniform(-1, 1, (n, m))
+    if dtype == torch.float32:
+        C = C.astype(np.float32).astype(np.float64)
+    got = gpu_cn(kind, B, C, 2, dtype)
+    assert colrel(got, oracle.cn_steps(kind, B, C, 2)) <= tol
+
+
 def test_cn_noop_and_errors():
     B = bands(3, 50, 4)
     with sbs.SharedLhs(3, B) as lhs:
