@@ -180,7 +180,11 @@ sbs_status sbs_solve_batch_variant(sbs_handle h, void *rhs, int64_t m,
  *          read the plan's factor rows, spikes and separator rows from
  *          global memory with only S^{-1} in LDS (taken anyway where the
  *          whole plan does not fit the LDS; shapes (lb, vec) = (32, 2) and
- *          (64, 1) only).  Bit 5 is ignored.
+ *          (64, 1) only).  Bit 5 is ignored.  Bit 6: the FP64 product
+ *          with S^{-1} over every column; by default each 16-row tile of
+ *          S^{-1} reads only the columns that hold its nonzero entries (the
+ *          plan sets entries of at most 2^-60 / Nr of their row's largest to
+ *          0), which gives the same result bit for bit.
  * Same arguments and results as sbs_solve_batch otherwise.  A shape that has
  * no plan, exceeds 1024 threads, the register budget or the LDS returns
  * SBS_ERR_INVALID_ARG.

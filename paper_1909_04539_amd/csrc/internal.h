@@ -127,12 +127,17 @@ struct SepPlan {
     //   spk: D*lb rows of {V[0..h), W[0..h)} (0 on separator rows)
     //   scf: D*h rows of 2h+1 coefficients: band row of each separator row,
     //        0 on separator columns and outside the matrix
-    //   sinv: Nr*Nr, row-major (inverse of S)
+    //   sinv: Nr*Nr, row-major (inverse of S; entries that cannot matter
+    //         are 0, and the product reads only the window kofs / kw)
     //   map: P ints
     void *blob64 = nullptr, *blob32 = nullptr;
     size_t fac_bytes64 = 0, spk_bytes64 = 0, scf_bytes64 = 0, sinv_bytes64 = 0;
     size_t fac_bytes32 = 0, spk_bytes32 = 0, scf_bytes32 = 0, sinv_bytes32 = 0;
     size_t map_bytes = 0;
+    // 16-row tile t of S^{-1} has its nonzero entries in columns k0 .. k0 + kw - 1,
+    // k0 = min(max(16t + kofs, 0), max(Nr4 - kw, 0)), Nr4 = Nr rounded up to 4;
+    // kw = 0: every column
+    int kofs = 0, kw = 0;
     RefinePlan refine;
     size_t blob_bytes(int tc) const {
         return (tc == 0 ? fac_bytes64 + spk_bytes64 + scf_bytes64 + sinv_bytes64

@@ -298,7 +298,56 @@ struct SepHostPlan {
     std::vector<double> scf;         // D*h*(2h+1)
     std::vector<double> sinv;        // Nr*Nr
     std::vector<int> map;
+    int kofs = 0, kw = 0;            // window of the S^{-1} product (sep_window)
 };
+
+// Entries of S^{-1} that cannot matter, and the window of columns the
+// kernel's product then reads.  The separators of blocks far apart are
+// coupled only through the spikes, which decay row by row for a diagonally
+// dominant or positive definite matrix, so most of S^{-1} is far below its
+// row's largest entry (for the 1024-row hyperdiffusion matrix in 32-row
+// blocks, entries two separators apart are below 1e-24 of it).  An entry
+// whose magnitude is at most 2^-60 / Nr of its row's largest is set to 0:
+// the dropped part of any z_i = sum_j S^{-1}_ij yhat_j is then at most
+// 2^-60 max_j |S^{-1}_ij| max |yhat|, below 1 / (128 Nr) of the rounding
+// error bound of the product itself.  The product is done in 16-row tiles of
+// S^{-1}; tile t (rows 16t .. 16t + 15) reads columns k0 .. k0 + kw - 1 with
+// k0 = min(max(16t + kofs, 0), max(Nr4 - kw, 0)), Nr4 = Nr rounded up to 4,
+// which holds every nonzero entry of the tile's rows.  kw = 0: every column.
+void sep_window(std::vector<double> &S, int Nr, int &kofs, int &kw) {
+    kofs = kw = 0;
+    if (Nr <= 0) return;
+    for (int i = 0; i < Nr; ++i) {
+        double mx = 0.0;
+        for (int j = 0; j < Nr; ++j) mx = std::max(mx, std::fabs(S[(size_t)i * Nr + j]));
+        const double thr = std::ldexp(mx, -60) / Nr;
+        for (int j = 0; j < Nr; ++j)
+            if (std::fabs(S[(size_t)i * Nr + j]) <= thr) S[(size_t)i * Nr + j] = 0.0;
+    }
+    const int mt = (Nr + 15) / 16, Nr4 = (Nr + 3) / 4 * 4;
+    std::vector<int> lo(mt, Nr), hi(mt, -1);
+    for (int i = 0; i < Nr; ++i)
+        for (int j = 0; j < Nr; ++j)
+            if (S[(size_t)i * Nr + j] != 0.0) {
+                lo[i / 16] = std::min(lo[i / 16], j);
+                hi[i / 16] = std::max(hi[i / 16], j);
+            }
+    int ofs = 0;
+    for (int t = 0; t < mt; ++t) ofs = std::min(ofs, lo[t] - 16 * t);
+    ofs = -((-ofs + 3) / 4 * 4);
+    for (int w = 4; w < Nr4; w += 4) {
+        bool holds = true;
+        for (int t = 0; t < mt && holds; ++t) {
+            const int k0 = std::min(std::max(16 * t + ofs, 0), std::max(Nr4 - w, 0));
+            holds = lo[t] >= k0 && hi[t] < k0 + w;
+        }
+        if (holds) {
+            kofs = ofs;
+            kw = w;
+            return;
+        }
+    }
+}
 
 // The separator plan's own solve of one column, as the kernel runs it:
 // block sweeps (separator rows pass through unchanged), separator
@@ -479,6 +528,7 @@ bool build_sep_plan(int kind, bool periodic, int64_t n, const double *bands, int
         }
     }
     if (Nr > 0 && !invert(S, Nr)) return false;
+    sep_window(S, Nr, hp.kofs, hp.kw);
     hp.lb = lb;
     hp.P = P;
     hp.Nr = Nr;
@@ -593,6 +643,8 @@ void serialise_sep(const SepHostPlan &hp, std::vector<unsigned char> &b64, std::
     pp.lb = hp.lb;
     pp.P = hp.P;
     pp.Nr = hp.Nr;
+    pp.kofs = hp.kofs;
+    pp.kw = hp.kw;
 }
 
 // The one-wave-per-block mixed-precision kernel's copy of a separator plan:

@@ -106,6 +106,7 @@ __device__ __forceinline__ void stage(unsigned char *lds, const unsigned char *b
 struct SepArgs {
     int fac_bytes, spk_bytes, scf_bytes, sinv_bytes, map_bytes;
     int n, P, Nr, S, ngroups, periodic, flags;
+    int kofs, kw;  // window of the S^{-1} product (kw = 0: every column)
     int64_t m;
     BandCoef coef;  // Crank-Nicolson steps: the matrix's constant band values
 };
@@ -116,11 +117,17 @@ struct SepArgs {
 // A[l % 16][l / 16] and B[l / 16][l % 16]; item r of the result is
 // D[4 r + l / 16][l % 16]).  Column s of Yhat / Z is at red / z + s * ldr.
 //
+// The entries of S^{-1} outside a tile's window are 0 (the plan drops
+// entries below 2^-60 / Nr of their row's largest), so the tile reads only
+// columns k0 .. k0 + kw - 1, k0 = min(max(i0 + kofs, 0), max(Nr4 - kw, 0)),
+// and the result is the product over every column bit for bit (the skipped
+// terms are exact zeros); kw = 0 reads every column.
+//
 // ALIAS: z is redl's storage (the LDS holds no third buffer); each wave has
 // at most one tile, and writes it only after every wave has read Yhat.
 template <bool ALIAS>
 __device__ __forceinline__ void sep_mma(const double *sinv, const double *redl, const double *redr, double *z, int Nr,
-                                        int S, int ldr) {
+                                        int S, int ldr, int kofs, int kw) {
     // the thread's coordinates, made opaque at each call: the tile addresses
     // below are formed per call rather than kept live across the group loop
     int tid = threadIdx.x;
@@ -128,6 +135,8 @@ __device__ __forceinline__ void sep_mma(const double *sinv, const double *redl, 
     const int lane = tid % kWave, wave = __builtin_amdgcn_readfirstlane(tid / kWave), nwaves = blockDim.x / kWave;
     const int mt = (Nr + 15) / 16, ntiles = mt * ((S + 15) / 16);
     const int lr = lane % 16, lk = lane / 16;
+    const int Nr4 = (Nr + 3) / 4 * 4, kn = kw ? kw : Nr;
+    auto kfirst = [&](int i0) { return kw ? min(max(i0 + kofs, 0), max(Nr4 - kw, 0)) : 0; };
     if constexpr (ALIAS) {
         const bool have = wave < ntiles;
         const int i0 = (wave % mt) * 16, j0 = (wave / mt) * 16;
@@ -136,7 +145,8 @@ __device__ __forceinline__ void sep_mma(const double *sinv, const double *redl, 
         if (have) {
             const double *arow = sinv + (size_t)min(i, Nr - 1) * Nr;
             const double *bl = redl + min(j, S - 1) * ldr, *br = redr + min(j, S - 1) * ldr;
-            for (int k0 = 0; k0 < Nr; k0 += 4) {
+            const int kb = kfirst(i0);
+            for (int k0 = kb; k0 < kb + kn; k0 += 4) {
                 const int k = k0 + lk, kc = min(k, Nr - 1);
                 const bool kin = k < Nr;
                 const double a = (kin && i < Nr) ? arow[kc] : 0.0;
@@ -160,7 +170,8 @@ __device__ __forceinline__ void sep_mma(const double *sinv, const double *redl, 
         const double *arow = sinv + (size_t)min(i, Nr - 1) * Nr;
         const double *bl = redl + min(j, S - 1) * ldr, *br = redr + min(j, S - 1) * ldr;
         D4 acc = {0.0, 0.0, 0.0, 0.0};
-        for (int k0 = 0; k0 < Nr; k0 += 4) {
+        const int kb = kfirst(i0);
+        for (int k0 = kb; k0 < kb + kn; k0 += 4) {
             const int k = k0 + lk, kc = min(k, Nr - 1);
             const bool kin = k < Nr;
             const double a = (kin && i < Nr) ? arow[kc] : 0.0;
@@ -317,7 +328,8 @@ __device__ __forceinline__ void block_sweeps(const typename RowOf<KIND, T>::type
 
 // flags: bit 0 XCD-grouped order of the groups (the workgroups a chiplet
 // runs at once take adjacent groups); bit 2 workgroups start out of step (see
-// below).  (Issuing the next group's loads into registers while the current
+// below); bit 6 the S^{-1} product over every column instead of the plan's
+// window (same result).  (Issuing the next group's loads into registers while the current
 // group is stored was measured slower: each wave's loads then queue behind
 // its stores.)
 //
@@ -498,10 +510,12 @@ __global__ __launch_bounds__(MAXT) void k_sep(const unsigned char *__restrict__ 
         } else if (MMA && blockDim.x % kWave == 0 &&
                    (!alias || ((Nr + 15) / 16) * ((S + 15) / 16) <= (int)(blockDim.x / kWave))) {
             if constexpr (MMA) {
+                // flags bit 6: every column of S^{-1}
+                const int kw = (a.flags & 64) ? 0 : a.kw;
                 if (alias)
-                    sep_mma<true>(lsinv, lredl, lredr, lz, Nr, S, ldr);
+                    sep_mma<true>(lsinv, lredl, lredr, lz, Nr, S, ldr, a.kofs, kw);
                 else
-                    sep_mma<false>(lsinv, lredl, lredr, lz, Nr, S, ldr);
+                    sep_mma<false>(lsinv, lredl, lredr, lz, Nr, S, ldr, a.kofs, kw);
             }
             __syncthreads();
 #pragma unroll
@@ -835,6 +849,8 @@ hipError_t launch_sep(const sbs_lhs *h, const SepChoice &c, int tc, void *x, int
     a.ngroups = (int)ngroups;
     a.periodic = sp.periodic ? 1 : 0;
     a.flags = c.flags;
+    a.kofs = sp.kofs;
+    a.kw = sp.kw;
     a.m = m;
     a.coef = h->coef;
     const int grid = (int)std::min<int64_t>(ngroups, (int64_t)cu_count(h->device) * std::max(1, c.wgs));

@@ -7,10 +7,13 @@
 // in:  int32 kind, int64 n, int64 m, bands (3 or 5 x n doubles), rhs (n x m)
 // out: per block length 16, 32, 64: int32 lb (0 if no plan), P, D, Nr, then
 //      the n x m solution (only when the plan exists); first for the pair
-//      plans, then for the separator plans; then, for block lengths 32 and
+//      plans, then for the separator plans (whose header is followed, when
+//      the plan exists, by int32 kofs, kw: the window of the S^{-1}
+//      product); then, for block lengths 32 and
 //      64, the mixed-precision form run from the separator plan's copy for
 //      the one-wave-per-block kernel (the right-hand sides rounded to FP32,
 //      two correction rounds): int32 lb (0 if there is no copy), then x
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -101,9 +104,16 @@ void emulate_sep(const sbs_lhs &h, const SepPlan &pp, const double *rhs, int64_t
                 yh[H * p + c] = v;
             }
         }
+        // the product over the window of the row's 16-row tile; an entry
+        // outside the window must be 0
+        const int Nr4 = (Nr + 3) / 4 * 4;
         for (int r = 0; r < Nr; ++r) {
+            const int k0 = pp.kw ? std::min(std::max(r / 16 * 16 + pp.kofs, 0), std::max(Nr4 - pp.kw, 0)) : 0;
+            const int k1 = pp.kw ? std::min(k0 + pp.kw, Nr) : Nr;
             double v = 0.0;
-            for (int k = 0; k < Nr; ++k) v += sinv[(size_t)r * Nr + k] * yh[k];
+            for (int k = k0; k < k1; ++k) v += sinv[(size_t)r * Nr + k] * yh[k];
+            for (int k = 0; k < Nr; ++k)
+                if ((k < k0 || k >= k1) && sinv[(size_t)r * Nr + k] != 0.0) v = NAN;
             z[r] = v;
         }
         for (int p = 0; p < P; ++p) {
@@ -262,6 +272,8 @@ int main(int argc, char **argv) {
         int32_t hdr[4] = {pp.ok ? pp.lb : 0, pp.P, pp.D, pp.Nr};
         std::fwrite(hdr, 4, 4, o);
         if (!pp.ok) continue;
+        const int32_t win[2] = {pp.kofs, pp.kw};
+        std::fwrite(win, 4, 2, o);
         if (kind != SBS_PENTA)
             emulate_sep<TriRow<double>>(h, pp, rhs.data(), m, x.data(), solve_tri_rows);
         else

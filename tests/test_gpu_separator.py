@@ -172,3 +172,41 @@ def test_long_systems_read_the_plan_from_memory(kind, n, m):
         torch.cuda.synchronize()
         assert colrel(x.cpu().numpy(), ref) <= TOL64
     assert ran > 0
+
+
+LONG = [(32, 2, 16), (32, 2, 8), (64, 1, 16), (64, 1, 8), (64, 1, 4)]
+
+
+@pytest.mark.parametrize("kind,n,m,bands,shapes,flags", [
+    (5, 1024, 1024, "hyper", [(32, 2, 32)], 0), (5, 1024, 514, "hyper", [(64, 1, 32)], 0),
+    (5, 1024, 1000, "random", [(32, 2, 32)], 1), (3, 1000, 258, "random", [(32, 2, 32)], 0),
+    (5, 2048, 640, "random", LONG, 16), (5, 3000, 130, "random", LONG, 16),
+    (3, 1024, 256, "slow", [(32, 2, 32)], 0)])
+def test_windowed_separator_product_equals_every_column(kind, n, m, bands, shapes, flags):
+    # The plan drops entries of S^{-1} at most 2^-60 / Nr of their row's
+    # largest, and each 16-row tile of the product reads only the columns
+    # that hold the rest: bit for bit the product over every column (flags
+    # bit 6), and within the parity bar of the oracle.  "slow": the
+    # (-1, 2.01, -1) matrix, whose window is every column.
+    if bands == "hyper":
+        B = W.hyperdiffusion_bands(n, 0.5)
+    elif bands == "slow":
+        B = W.zero_outside(np.stack([-np.ones(n), np.full(n, 2.01), -np.ones(n)]))
+    else:
+        B = bands_for(kind, n, 900 + n)
+    rhs = np.random.default_rng(n + m).uniform(-1, 1, (n, m))
+    ref = oracle.solve(kind, B, rhs)
+    ran = 0
+    with sbs.SharedLhs(kind, B) as h:
+        for lb, vec, S in shapes:
+            print(f"case kind={kind} n={n} m={m} {bands} lb={lb} vec={vec} S={S} flags={flags}", flush=True)
+            win = shape_run(h, rhs, lb, vec, S, flags)
+            if win is None:
+                continue
+            print(f"case kind={kind} n={n} m={m} {bands} lb={lb} vec={vec} S={S} flags={flags | 64}", flush=True)
+            full = shape_run(h, rhs, lb, vec, S, flags | 64)
+            assert full is not None
+            assert np.array_equal(win, full), (lb, vec, S)
+            assert colrel(win, ref) <= TOL64, (lb, vec, S, colrel(win, ref))
+            ran += 1
+    assert ran > 0

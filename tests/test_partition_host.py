@@ -54,16 +54,19 @@ def run_all(exe, tmp_path, kind, B, rhs):
     r = subprocess.run([exe, src, dst], capture_output=True, text=True, timeout=120,
                        env=dict(os.environ, ASAN_OPTIONS="detect_leaks=1", UBSAN_OPTIONS="halt_on_error=1"))
     assert r.returncode == 0, r.stderr
-    plans, refined = [], []
+    plans, refined, windows = [], [], []
     with open(dst, "rb") as f:
-        for _ in range(6):
+        for q in range(6):
             lb, P, D, Nr = struct.unpack("<4i", f.read(16))
+            if q >= 3:
+                windows.append(struct.unpack("<2i", f.read(8)) if lb else None)
             x = np.frombuffer(f.read(8 * n * m), dtype=np.float64).reshape(n, m) if lb else None
             plans.append((lb, P, D, Nr, x))
         for _ in range(2):
             (lb,) = struct.unpack("<i", f.read(4))
             refined.append((lb, np.frombuffer(f.read(8 * n * m), dtype=np.float64).reshape(n, m) if lb else None))
     run_all.refined = refined
+    run_all.windows = windows
     return plans[:3], plans[3:]
 
 
@@ -282,3 +285,41 @@ def test_refine_copy_of_the_plan_solves_like_the_oracle(exe, tmp_path, kind, n):
     for lb, x in got:
         if lb:
             assert colrel(x, ref) <= 1e-12, (lb, colrel(x, ref))
+
+
+@pytest.mark.parametrize("case,lb,widest", [("hyper", 32, 24), ("hyper", 64, 16), ("dominant", 32, 24),
+                                            ("slow", 32, None), ("periodic", 32, None)])
+def test_separator_product_window(exe, tmp_path, case, lb, widest):
+    # Entries of S^{-1} at most 2^-60 / Nr of their row's largest are dropped
+    # and each 16-row tile of the product reads the window of columns that
+    # holds the rest (the emulator turns a nonzero entry outside the window
+    # into NaN).  Where the inverse decays fast between separators (the
+    # hyperdiffusion matrix, a dominant random matrix) the window is a few
+    # separators wide; where it does not (the (-1, 2.01, -1) matrix, whose
+    # inverse falls by a factor of about 25 per 32 rows; a periodic matrix
+    # whose first and last separators are coupled above the threshold) every
+    # column is read (kw = 0).
+    n = 1024
+    kind = 5 if case in ("hyper", "dominant") else 3
+    if case == "hyper":
+        B = W.hyperdiffusion_bands(n, 0.5)
+    elif case == "dominant":
+        B = dominant(5, n, 91)
+    elif case == "slow":
+        B = W.zero_outside(np.stack([-np.ones(n), np.full(n, 2.01), -np.ones(n)]))
+    else:  # periodic diffusion, sigma = 10: the inverse falls by about 2e4 per 32 rows
+        B = np.stack([np.full(n, -10.0), np.full(n, 21.0), np.full(n, -10.0)])
+        kind = 13
+    rhs = np.random.default_rng(5).uniform(-1, 1, (n, 3))
+    ref = oracle.solve(kind, B, rhs)
+    plans = run_sep(exe, tmp_path, kind, B, rhs)
+    q = (16, 32, 64).index(lb)
+    got_lb, P, D, Nr, x = plans[q]
+    assert got_lb == lb
+    kofs, kw = run_all.windows[q]
+    assert kofs <= 0 and kofs % 4 == 0 and kw % 4 == 0
+    if widest is None:
+        assert kw == 0, (kofs, kw)
+    else:
+        assert 0 < kw <= widest, (kofs, kw, Nr)
+    assert colrel(x, ref) <= 1e-13, colrel(x, ref)
