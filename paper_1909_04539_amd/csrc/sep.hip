@@ -117,6 +117,37 @@ struct SepArgs {
 // A[l % 16][l / 16] and B[l / 16][l % 16]; item r of the result is
 // D[4 r + l / 16][l % 16]).  Column s of Yhat / Z is at red / z + s * ldr.
 //
+// One 16 x 16 tile of Z: the lane's row i of S^{-1} and column j of Yhat
+// over columns kb .. kb + kn - 1, four per matrix-core step.  Every operand
+// is read at an index clamped inside the buffers, so that no read is
+// conditional (as branches around each read the steps ran one after
+// another), and the next step's operands are read before the current step's
+// product.  Rows i >= Nr and columns j >= S of the tile hold other rows' and
+// columns' values and are never stored; entries of S^{-1} past column Nr - 1
+// are multiplied by 0 (finite values: the entries of S^{-1}), so the
+// right-hand sides read there add nothing.
+__device__ __forceinline__ D4 sep_tile(const double *sinv, const double *redl, const double *redr, int Nr, int S,
+                                       int ldr, int i, int j, int lk, int kb, int kn) {
+    const double *arow = sinv + (size_t)min(i, Nr - 1) * Nr;
+    const double *bl = redl + min(j, S - 1) * ldr, *br = redr + min(j, S - 1) * ldr;
+    auto opnd = [&](int k0, double &a, double &b) {
+        const int k = k0 + lk, kc = min(k, Nr - 1);
+        a = arow[kc] * (k < Nr ? 1.0 : 0.0);
+        b = bl[kc] + br[kc];
+    };
+    D4 acc = {0.0, 0.0, 0.0, 0.0};
+    double a, b;
+    opnd(kb, a, b);
+    for (int k0 = kb + 4; k0 < kb + kn; k0 += 4) {
+        double an, bn;
+        opnd(k0, an, bn);
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+        a = an;
+        b = bn;
+    }
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+}
+
 // The entries of S^{-1} outside a tile's window are 0 (the plan drops
 // entries below 2^-60 / Nr of their row's largest), so the tile reads only
 // columns k0 .. k0 + kw - 1, k0 = min(max(i0 + kofs, 0), max(Nr4 - kw, 0)),
@@ -142,18 +173,7 @@ __device__ __forceinline__ void sep_mma(const double *sinv, const double *redl, 
         const int i0 = (wave % mt) * 16, j0 = (wave / mt) * 16;
         const int i = i0 + lr, j = j0 + lr;
         D4 acc = {0.0, 0.0, 0.0, 0.0};
-        if (have) {
-            const double *arow = sinv + (size_t)min(i, Nr - 1) * Nr;
-            const double *bl = redl + min(j, S - 1) * ldr, *br = redr + min(j, S - 1) * ldr;
-            const int kb = kfirst(i0);
-            for (int k0 = kb; k0 < kb + kn; k0 += 4) {
-                const int k = k0 + lk, kc = min(k, Nr - 1);
-                const bool kin = k < Nr;
-                const double a = (kin && i < Nr) ? arow[kc] : 0.0;
-                const double b = (kin && j < S) ? bl[kc] + br[kc] : 0.0;
-                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
-            }
-        }
+        if (have) acc = sep_tile(sinv, redl, redr, Nr, S, ldr, i, j, lk, kfirst(i0), kn);
         __syncthreads();
         if (have) {
 #pragma unroll
@@ -167,17 +187,7 @@ __device__ __forceinline__ void sep_mma(const double *sinv, const double *redl, 
     for (int tile = wave; tile < ntiles; tile += nwaves) {
         const int i0 = (tile % mt) * 16, j0 = (tile / mt) * 16;
         const int i = i0 + lr, j = j0 + lr;
-        const double *arow = sinv + (size_t)min(i, Nr - 1) * Nr;
-        const double *bl = redl + min(j, S - 1) * ldr, *br = redr + min(j, S - 1) * ldr;
-        D4 acc = {0.0, 0.0, 0.0, 0.0};
-        const int kb = kfirst(i0);
-        for (int k0 = kb; k0 < kb + kn; k0 += 4) {
-            const int k = k0 + lk, kc = min(k, Nr - 1);
-            const bool kin = k < Nr;
-            const double a = (kin && i < Nr) ? arow[kc] : 0.0;
-            const double b = (kin && j < S) ? bl[kc] + br[kc] : 0.0;
-            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
-        }
+        const D4 acc = sep_tile(sinv, redl, redr, Nr, S, ldr, i, j, lk, kfirst(i0), kn);
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int row = i0 + 4 * r + lk;
