@@ -396,6 +396,9 @@ class _Server:
         assert self.L.sbs_server_register(self.p, h, self.ct.byref(i)) == 0
         return i.value
 
+    def set_fp32_mode(self, mode):
+        assert self.L.sbs_server_set_fp32_mode(self.p, mode) == 0
+
     def submit(self, lhs, ptr, m, dtype):
         tk = self.ct.c_uint64()
         st = self.L.sbs_server_submit(self.p, lhs, ptr, m, dtype, self.ct.byref(tk))
@@ -471,8 +474,10 @@ def bench_serving(args, torch, sbs, W):
     (submit to completion, queueing included) and throughput.  The 0.8
     arrivals are replayed through a plain FP64 FIFO (one sbs_solve_batch per
     request, no coalescing), and the oracle serves the same requests on the
-    host cores."""
-    import threading
+    host cores.  Requests reach the server through its native trace replay
+    (sbs_server_replay: one thread submits at the arrival times, another
+    waits for and releases each request), so the rates are the server's and
+    not a Python client's."""
     count = args.serve_requests
     loads = (0.5, 0.8, 0.95)
     lhss = W.serving_lhs_set()
@@ -497,30 +502,21 @@ def bench_serving(args, torch, sbs, W):
     unknowns = float(sum(lhss[r.lhs].n * r.m for r in trace))
     torch.cuda.synchronize()
 
-    def run(arrivals, reqs=count):
-        tickets = [None] * reqs
-        lat = [0.0] * reqs
-        done = threading.Event()
+    ids_all = np.array([ids[r.lhs] for r in trace], dtype=np.int32)
+    ptr_all = np.array(ptr, dtype=np.uint64)
+    m_all = np.array([r.m for r in trace], dtype=np.int64)
+    dt_all = np.array(dt, dtype=np.int32)
 
-        def waiter():
-            for k in range(reqs):
-                while tickets[k] is None:
-                    time.sleep(0)
-                st, l = srv.wait_release(tickets[k])
-                lat[k] = l
-            done.set()
-
-        th = threading.Thread(target=waiter)
-        th.start()
-        t0 = time.perf_counter()
-        for k in range(reqs):
-            if arrivals is not None:
-                while time.perf_counter() - t0 < arrivals[k]:
-                    pass
-            tickets[k] = srv.submit(ids[trace[k].lhs], ptr[k], trace[k].m, dt[k])
-        done.wait()
-        th.join()
-        return time.perf_counter() - t0, np.array(lat)
+    def run(arrivals, reqs=count, ks=None):
+        # requests ks (default: the first reqs of the trace) in order, through
+        # the library's native replay (submitting thread + waiting thread), so
+        # that no interpreter sits between the arrivals and the server
+        ks = np.arange(reqs) if ks is None else np.asarray(ks)
+        arr = None if arrivals is None else np.asarray(arrivals, dtype=np.float64)[:len(ks)] * 1e6
+        st, lat, elapsed = sbs.sbs_server_replay(srv.p, ids_all[ks], ptr_all[ks], m_all[ks], dt_all[ks], arr)
+        if st:
+            raise RuntimeError(f"sbs_server_replay: {st}")
+        return elapsed, lat
 
     pct = lambda a, q: float(np.percentile(a, q))
     run(None, min(count, 20000))                # warm-up pass
@@ -536,6 +532,27 @@ def bench_serving(args, torch, sbs, W):
         res["loads"][str(rho)] = {"offered_req_per_s": rho * lam_sat, "p50_us": pct(lat, 50), "p99_us": pct(lat, 99),
                                   "max_us": float(lat.max()), "unknowns_per_s": unknowns / span}
     res["launches_per_run"] = (srv.stats(sbs).launches - launches0) / len(loads)
+    # Closed loop per precision (up to 2e4 requests of each), and FP32
+    # requests served as one FP64 sweep of their stored values (the server's
+    # second mode): the mix at saturation and at 0.8 of that saturation.
+    sub = {p: [k for k in range(count) if trace[k].fp32 == p][:20000] for p in (False, True)}
+    usub = {p: float(sum(lhss[trace[k].lhs].n * trace[k].m for k in sub[p])) for p in sub}
+    per = {}
+    for p, name in ((False, "fp64_requests"), (True, "fp32_requests_refined")):
+        span, _ = run(None, ks=sub[p])
+        per[name] = {"requests": len(sub[p]), "unknowns_per_s": usub[p] / span}
+    srv.set_fp32_mode(1)
+    log("  FP32 requests as one FP64 sweep")
+    span, _ = run(None, ks=sub[True])
+    per["fp32_requests_fp64_sweep"] = {"requests": len(sub[True]), "unknowns_per_s": usub[True] / span}
+    res["closed_loop_per_precision"] = per
+    make2, _ = run(None)
+    lam2 = count / make2
+    span, lat = run(base_gaps / (0.8 * lam2))
+    res["fp32_as_fp64_sweep"] = {"saturation_unknowns_per_s": unknowns / make2,
+                                 "0.8": {"offered_req_per_s": 0.8 * lam2, "p50_us": pct(lat, 50),
+                                         "p99_us": pct(lat, 99), "unknowns_per_s": unknowns / span}}
+    srv.set_fp32_mode(0)
     srv.close()
 
     # Plain FP64 FIFO on the 0.8 arrivals: one solve per request, in order.
@@ -560,10 +577,14 @@ def bench_serving(args, torch, sbs, W):
     log("  oracle serving on the host")
     res["cpu_oracle"] = serving_cpu_oracle(lhss, trace, pool64.cpu().numpy(), offs, loads, args.cpu_seconds)
     del pool32, pool64
-    res["note"] = ("latency = submit to completion incl. queueing; rhs device-resident; FP32 requests get the "
+    res["note"] = ("requests submitted and released by the server's native trace replay; "
+                   "latency = submit to completion incl. queueing; rhs device-resident; FP32 requests get the "
                    "mixed-precision solve with 2 corrections (FP64 result); the FIFO baseline solves every "
                    "request in FP64 on one stream without coalescing; cpu_oracle: the oracle on the host cores, "
-                   "FIFO, on a prefix of the same trace at the same loads of its own saturation rate")
+                   "FIFO, on a prefix of the same trace at the same loads of its own saturation rate; "
+                   "closed_loop_per_precision: up to 2e4 requests of one precision each, closed loop; "
+                   "fp32_as_fp64_sweep: the same trace with FP32 requests solved by one FP64 sweep of their "
+                   "stored values (sbs_server_set_fp32_mode), saturation and 0.8 of it")
     return res
 
 

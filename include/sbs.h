@@ -330,7 +330,8 @@ sbs_status sbs_handle_info(sbs_handle h, int32_t *kind, int64_t *n,
  * one kernel) that run on several streams at once, so requests that arrive
  * while others run are admitted and overlap them on the device.
  * FP64 requests get the plain FP64 solve; FP32 requests get the mixed
- * precision solve with 2 corrections.  Either way the result is FP64.
+ * precision solve with 2 corrections (or, after sbs_server_set_fp32_mode,
+ * one FP64 sweep of their stored values).  Either way the result is FP64.
  */
 typedef struct sbs_server sbs_server;
 
@@ -353,6 +354,26 @@ sbs_status sbs_server_create(size_t budget_bytes, int32_t max_streams,
  * owns the handle and must keep it alive until sbs_server_destroy.
  * SBS_TRI and SBS_PENTA handles only (SBS_ERR_INVALID_ARG otherwise). */
 sbs_status sbs_server_register(sbs_server *srv, sbs_handle h, int32_t *lhs_id);
+
+/* How FP32 requests submitted after this call are solved (requests already
+ * submitted keep theirs):
+ *  SBS_SERVE_F32_REFINED     (default) the mixed-precision form of
+ *                            sbs_solve_batch_refined with 2 corrections:
+ *                            FP32 sweeps, FP64 residuals and accumulation;
+ *                            each tile's passes go through HBM (about 104
+ *                            bytes per unknown, more for systems too long
+ *                            for checkpoints) and the arena holds an FP32
+ *                            scratch copy (4 bytes per unknown) besides x.
+ *  SBS_SERVE_F32_FP64_SWEEP  one FP64 sweep of the FP32 values (read and
+ *                            promoted as they are loaded): the FP64 solve of
+ *                            the stored right-hand sides, which is what the
+ *                            refined form converges to, at 16 bytes per
+ *                            unknown (28 for systems too long for
+ *                            checkpoints) and with no scratch.
+ * Errors: SBS_ERR_INVALID_ARG for any other mode. */
+#define SBS_SERVE_F32_REFINED 0
+#define SBS_SERVE_F32_FP64_SWEEP 1
+sbs_status sbs_server_set_fp32_mode(sbs_server *srv, int32_t mode);
 
 /* Queue a request.  rhs: device, n*m elements of dtype (interleaved),
  * read-only, must stay valid until the request completes.  Returns at once
@@ -378,6 +399,23 @@ sbs_status sbs_server_fetch(sbs_server *srv, uint64_t ticket, double *dst, void 
 sbs_status sbs_server_release(sbs_server *srv, uint64_t ticket);
 
 sbs_status sbs_server_stats_get(sbs_server *srv, sbs_server_stats *out);
+
+/* Replay a trace of requests against the server from native threads (a
+ * load generator with no interpreter in the loop).  Request k (matrix
+ * lhs_ids[k], right-hand sides rhs[k] of m[k] systems in dtype[k], as for
+ * sbs_server_submit) is submitted arrival_us[k] microseconds after the call
+ * starts (arrival_us NULL: all at once, a closed loop); a second thread
+ * waits for each request in order and releases it at once (the results are
+ * not kept).  latency_us (optional, count doubles) receives each request's
+ * submit -> completion latency, -1 for a request that was not accepted;
+ * *elapsed_s (optional) the time from the start to the last release.
+ * Returns the first error of any submission, wait or release (the other
+ * requests still run), else SBS_OK.  All arrays are host memory owned by
+ * the caller; the right-hand sides must stay valid until the call returns. */
+sbs_status sbs_server_replay(sbs_server *srv, int64_t count, const int32_t *lhs_ids,
+                             const void *const *rhs, const int64_t *m,
+                             const int32_t *dtype, const double *arrival_us,
+                             double *latency_us, double *elapsed_s);
 
 /* Drain all work, then free the arena and the server. */
 sbs_status sbs_server_destroy(sbs_server *srv);

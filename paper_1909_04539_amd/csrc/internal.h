@@ -277,24 +277,26 @@ sbs_status refined_run(const sbs_lhs *h, const float *b, double *x, int64_t m, i
 
 // Serving: heterogeneous tile launches (see server.cpp).
 struct Tile {
-    const void *fac;            // factor rows of this tile's matrix (type per dtype)
+    const void *fac;            // factor rows of this tile's matrix (FP32 for prec 1, else FP64)
     const BandRow *bands;       // original bands (mixed precision only)
     const void *in;             // rhs of the request
     double *x;                  // FP64 result of the request
     float *scratch;             // FP32 residual scratch (mixed precision only)
     int64_t n, m, col0;         // system range [col0, col0 + 64) of the request
-    int32_t kind, fp32;
+    // prec 0: FP64 request; 1: FP32 request, mixed precision with two
+    // corrections; 2: FP32 request, one FP64 sweep of its stored values
+    int32_t kind, prec;
     int32_t req;                // the request's slot in the launch's completion arrays
     int32_t pad;
 };
 
-// Runs tiles [0, ntiles), all of one kind and precision, with `grid`
+// Runs tiles [0, ntiles), all of one kind and prec, with `grid`
 // persistent waves; *dev_counter must be 0 when the kernel starts.
 // Per-request completion: left[r] holds the number of tiles of request r
 // (device memory); the wave that finishes the last of them sets done[r] = 1
 // (host-visible memory), after every result of the request is visible to the
 // host and to other work on the device.
-hipError_t launch_tiles(int kind, int fp32, const Tile *dev_tiles, int ntiles, int *dev_counter, int *left,
+hipError_t launch_tiles(int kind, int prec, const Tile *dev_tiles, int ntiles, int *dev_counter, int *left,
                         int *done, int grid, hipStream_t stream);
 
 }  // namespace sbs

@@ -1325,7 +1325,24 @@ __device__ __forceinline__ void run_tile_f32(const Tile &t, unsigned char *lds) 
     update_wave(t.x, t.scratch, n, t.m, t.col0);
 }
 
-// One kernel per (kind, precision) group of a launch's tiles.
+// FP32 requests served as one FP64 sweep of their FP32 right-hand sides
+// (the server's second mode for FP32 requests): the same result the
+// mixed-precision solve converges to, the FP64 solve of the stored values,
+// with 12 to 20 bytes per unknown instead of the correction rounds' passes.
+template <int KIND>
+__device__ __forceinline__ void run_tile_f32in(const Tile &t, unsigned char *lds) {
+    const int n = (int)t.n;
+    using Row = typename Rec<KIND, double>::Row;
+    const Row *fac = reinterpret_cast<const Row *>(t.fac);
+    const float *in = reinterpret_cast<const float *>(t.in);
+    if (tile_fits_chunked<KIND, double>(n))
+        sweep_wave<KIND, double, float, double, 32, MODE_CHUNKED>(fac, n, in, t.x, t.m, t.col0, lds);
+    else
+        sweep_wave<KIND, double, float, double, 32, MODE_STREAM>(fac, n, in, t.x, t.m, t.col0, lds);
+}
+
+// One kernel per (kind, precision) group of a launch's tiles (PREC 0: FP64
+// requests, 1: FP32 requests refined, 2: FP32 requests as one FP64 sweep).
 //
 // Control flow in the persistent loop is wave-uniform throughout: every lane
 // issues each atomic (lane 0 adds its amount, the others add 0) and the wave
@@ -1335,7 +1352,7 @@ __device__ __forceinline__ void run_tile_f32(const Tile &t, unsigned char *lds) 
 // results at system scope with its decrement of left[req]; the decrement that
 // takes the count to zero also acquires every earlier one, and the flag store
 // that follows releases them all to the host.
-template <int KIND, int FP32>
+template <int KIND, int PREC>
 __global__ __launch_bounds__(kWave) void k_tiles(const Tile *__restrict__ tiles, int ntiles, int *counter, int *left,
                                                  int *done) {
     __shared__ __align__(16) unsigned char lds[kTileLds];
@@ -1345,8 +1362,10 @@ __global__ __launch_bounds__(kWave) void k_tiles(const Tile *__restrict__ tiles,
         t = __builtin_amdgcn_readfirstlane(t);
         if (t >= ntiles) break;
         const Tile tl = tiles[t];
-        if constexpr (FP32)
+        if constexpr (PREC == 1)
             run_tile_f32<KIND>(tl, lds);
+        else if constexpr (PREC == 2)
+            run_tile_f32in<KIND>(tl, lds);
         else
             run_tile_f64<KIND>(tl, lds);
         const int req = __builtin_amdgcn_readfirstlane(tl.req);
@@ -1888,19 +1907,29 @@ hipError_t launch_refine_step(const sbs_lhs *h, int mode, const float *b, double
     return hipGetLastError();
 }
 
-hipError_t launch_tiles(int kind, int fp32, const Tile *dev_tiles, int ntiles, int *dev_counter, int *left,
+hipError_t launch_tiles(int kind, int prec, const Tile *dev_tiles, int ntiles, int *dev_counter, int *left,
                         int *done, int grid, hipStream_t stream) {
     if (ntiles <= 0) return hipSuccess;
+    if (prec < 0 || prec > 2) return hipErrorInvalidValue;
     if (grid > ntiles) grid = ntiles;
     const dim3 g((unsigned)grid), b(kWave);
-    if (kind == SBS_TRI && !fp32)
-        hipLaunchKernelGGL((k_tiles<SBS_TRI, 0>), g, b, 0, stream, dev_tiles, ntiles, dev_counter, left, done);
-    else if (kind == SBS_TRI)
-        hipLaunchKernelGGL((k_tiles<SBS_TRI, 1>), g, b, 0, stream, dev_tiles, ntiles, dev_counter, left, done);
-    else if (!fp32)
-        hipLaunchKernelGGL((k_tiles<SBS_PENTA, 0>), g, b, 0, stream, dev_tiles, ntiles, dev_counter, left, done);
-    else
-        hipLaunchKernelGGL((k_tiles<SBS_PENTA, 1>), g, b, 0, stream, dev_tiles, ntiles, dev_counter, left, done);
+    const bool tri = kind == SBS_TRI;
+    if (prec == 0) {
+        if (tri)
+            hipLaunchKernelGGL((k_tiles<SBS_TRI, 0>), g, b, 0, stream, dev_tiles, ntiles, dev_counter, left, done);
+        else
+            hipLaunchKernelGGL((k_tiles<SBS_PENTA, 0>), g, b, 0, stream, dev_tiles, ntiles, dev_counter, left, done);
+    } else if (prec == 1) {
+        if (tri)
+            hipLaunchKernelGGL((k_tiles<SBS_TRI, 1>), g, b, 0, stream, dev_tiles, ntiles, dev_counter, left, done);
+        else
+            hipLaunchKernelGGL((k_tiles<SBS_PENTA, 1>), g, b, 0, stream, dev_tiles, ntiles, dev_counter, left, done);
+    } else {
+        if (tri)
+            hipLaunchKernelGGL((k_tiles<SBS_TRI, 2>), g, b, 0, stream, dev_tiles, ntiles, dev_counter, left, done);
+        else
+            hipLaunchKernelGGL((k_tiles<SBS_PENTA, 2>), g, b, 0, stream, dev_tiles, ntiles, dev_counter, left, done);
+    }
     return hipGetLastError();
 }
 

@@ -14,11 +14,13 @@
 // Several slots (streams) run at once, so requests admitted while earlier
 // launches are still running start at once and overlap them on the GPU.
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <condition_variable>
 #include <cstring>
 #include <deque>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <new>
 #include <thread>
@@ -34,7 +36,7 @@ namespace {
 
 constexpr size_t kAlign = 256;
 constexpr int kMaxTilesPerLaunch = 1 << 16;
-constexpr int kGroups = 4;  // (tri, penta) x (fp64, fp32)
+constexpr int kGroups = 6;  // (tri, penta) x (fp64, fp32 refined, fp32 as one fp64 sweep)
 constexpr int kPersistentWaves = 1024;
 
 size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
@@ -83,6 +85,7 @@ struct Req {
     const void *rhs = nullptr;
     int64_t m = 0;
     int32_t dtype = SBS_F64;
+    int32_t prec = 0;  // the tiles' prec (Tile): fixed at submission
     size_t bytes = 0, off = 0;
     double *x = nullptr;
     float *scratch = nullptr;
@@ -118,6 +121,7 @@ struct sbs_server {
     unsigned char *arena_base = nullptr;
     Arena arena{0};
     int max_batch = 4096;
+    int32_t fp32_mode = SBS_SERVE_F32_REFINED;  // how FP32 requests submitted from now on are solved
     std::vector<sbs_lhs *> lhs;
     std::vector<Slot> slots;
 
@@ -193,7 +197,7 @@ void sbs_server::admit() {
         r->off = off;
         const sbs_lhs *h = lhs[r->lhs];
         r->x = reinterpret_cast<double *>(arena_base + off);
-        r->scratch = r->dtype == SBS_F32
+        r->scratch = r->prec == 1
                          ? reinterpret_cast<float *>(arena_base + off + round_up((size_t)h->n * r->m * 8, kAlign))
                          : nullptr;
         r->state = ADMITTED;
@@ -223,13 +227,12 @@ bool sbs_server::launch(Slot &s) {
     for (size_t k = 0; k < take.size(); ++k) {
         Req *r = take[k];
         const sbs_lhs *h = lhs[r->lhs];
-        const int fp32 = r->dtype == SBS_F32;
-        const int g = (h->kind == SBS_PENTA ? 2 : 0) + fp32;
+        const int g = (h->kind == SBS_PENTA ? 3 : 0) + r->prec;
         left[k] = (int)((r->m + kWave - 1) / kWave);
         s.flag_host[k] = 0;  // the slot's previous launch has completed: nothing writes it now
         for (int64_t c = 0; c < r->m; c += kWave) {
             Tile t;
-            t.fac = fp32 ? h->fac32 : h->fac64;
+            t.fac = r->prec == 1 ? h->fac32 : h->fac64;
             t.bands = h->bands;
             t.in = r->rhs;
             t.x = r->x;
@@ -238,7 +241,7 @@ bool sbs_server::launch(Slot &s) {
             t.m = r->m;
             t.col0 = c;
             t.kind = h->kind;
-            t.fp32 = fp32;
+            t.prec = r->prec;
             t.req = (int32_t)k;
             t.pad = 0;
             grp[g].push_back(t);
@@ -257,8 +260,8 @@ bool sbs_server::launch(Slot &s) {
     hipError_t e = hipMemcpyAsync(s.dev, s.host, at, hipMemcpyHostToDevice, s.stream);
     for (int g = 0; g < kGroups && e == hipSuccess; ++g) {
         if (grp[g].empty()) continue;
-        const int kind = g >= 2 ? SBS_PENTA : SBS_TRI;
-        e = launch_tiles(kind, g & 1, reinterpret_cast<const Tile *>(s.dev + offs[g]), (int)grp[g].size(),
+        const int kind = g >= 3 ? SBS_PENTA : SBS_TRI;
+        e = launch_tiles(kind, g % 3, reinterpret_cast<const Tile *>(s.dev + offs[g]), (int)grp[g].size(),
                          reinterpret_cast<int *>(s.dev + g * 64), reinterpret_cast<int *>(s.dev + left_offset()),
                          s.flag_dev, kPersistentWaves, s.stream);
     }
@@ -363,6 +366,13 @@ sbs_status sbs_server_register(sbs_server *srv, sbs_handle h, int32_t *lhs_id) {
     return SBS_OK;
 }
 
+sbs_status sbs_server_set_fp32_mode(sbs_server *srv, int32_t mode) {
+    if (!srv || (mode != SBS_SERVE_F32_REFINED && mode != SBS_SERVE_F32_FP64_SWEEP)) return SBS_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lk(srv->mu);
+    srv->fp32_mode = mode;
+    return SBS_OK;
+}
+
 sbs_status sbs_server_submit(sbs_server *srv, int32_t lhs_id, const void *rhs, int64_t m, int32_t dtype,
                              uint64_t *ticket) {
     if (!srv || !ticket || m < 1 || (dtype != SBS_F64 && dtype != SBS_F32) || !rhs) return SBS_ERR_INVALID_ARG;
@@ -381,7 +391,8 @@ sbs_status sbs_server_submit(sbs_server *srv, int32_t lhs_id, const void *rhs, i
     }
     const sbs_lhs *h = srv->lhs[lhs_id];
     const size_t nm = (size_t)h->n * (size_t)m;
-    r->bytes = round_up(nm * 8, kAlign) + (dtype == SBS_F32 ? round_up(nm * 4, kAlign) : 0);
+    const int32_t prec = dtype == SBS_F64 ? 0 : (srv->fp32_mode == SBS_SERVE_F32_FP64_SWEEP ? 2 : 1);
+    r->bytes = round_up(nm * 8, kAlign) + (prec == 1 ? round_up(nm * 4, kAlign) : 0);
     if (r->bytes > srv->budget) {
         ++srv->rejected;
         delete r;
@@ -392,6 +403,7 @@ sbs_status sbs_server_submit(sbs_server *srv, int32_t lhs_id, const void *rhs, i
     r->rhs = rhs;
     r->m = m;
     r->dtype = dtype;
+    r->prec = prec;
     r->t_submit = Clock::now();
     srv->reqs[r->ticket] = r;
     srv->queue.push_back(r);
@@ -447,6 +459,53 @@ sbs_status sbs_server_release(sbs_server *srv, uint64_t ticket) {
     ++srv->kicks;
     srv->cv_sched.notify_one();
     return SBS_OK;
+}
+
+sbs_status sbs_server_replay(sbs_server *srv, int64_t count, const int32_t *lhs_ids, const void *const *rhs,
+                             const int64_t *m, const int32_t *dtype, const double *arrival_us, double *latency_us,
+                             double *elapsed_s) {
+    if (!srv || count < 0 || (count > 0 && (!lhs_ids || !rhs || !m || !dtype))) return SBS_ERR_INVALID_ARG;
+    std::vector<uint64_t> ticket((size_t)count, 0);
+    std::unique_ptr<std::atomic<int>[]> posted(new (std::nothrow) std::atomic<int>[(size_t)count]);
+    if (count > 0 && !posted) return SBS_ERR_NO_MEMORY;
+    for (int64_t k = 0; k < count; ++k) posted[k].store(0, std::memory_order_relaxed);
+    std::atomic<int> first_error{SBS_OK};
+    auto note = [&](sbs_status st) {
+        int ok = SBS_OK;
+        if (st != SBS_OK) first_error.compare_exchange_strong(ok, (int)st);
+    };
+    const auto t0 = Clock::now();
+    Clock::time_point t_end = t0;
+    // waits for and releases the requests in order, as the submitter posts them
+    std::thread waiter([&] {
+        for (int64_t k = 0; k < count; ++k) {
+            int p;
+            while ((p = posted[k].load(std::memory_order_acquire)) == 0) std::this_thread::yield();
+            if (p < 0) {
+                if (latency_us) latency_us[k] = -1.0;
+                continue;
+            }
+            double lat = -1.0;
+            note(sbs_server_wait(srv, ticket[k], -1, nullptr, &lat));
+            note(sbs_server_release(srv, ticket[k]));
+            if (latency_us) latency_us[k] = lat;
+        }
+        t_end = Clock::now();
+    });
+    for (int64_t k = 0; k < count; ++k) {
+        if (arrival_us) {
+            const auto due = t0 + std::chrono::duration_cast<Clock::duration>(
+                                      std::chrono::duration<double, std::micro>(arrival_us[k]));
+            while (Clock::now() < due) {
+            }
+        }
+        const sbs_status st = sbs_server_submit(srv, lhs_ids[k], rhs[k], m[k], dtype[k], &ticket[k]);
+        note(st);
+        posted[k].store(st == SBS_OK ? 1 : -1, std::memory_order_release);
+    }
+    waiter.join();
+    if (elapsed_s) *elapsed_s = std::chrono::duration<double>(t_end - t0).count();
+    return (sbs_status)first_error.load();
 }
 
 sbs_status sbs_server_stats_get(sbs_server *srv, sbs_server_stats *out) {

@@ -24,6 +24,7 @@ INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 
 SBS_TRI, SBS_PENTA, SBS_TRI_PERIODIC = 3, 5, 13
 SBS_F64, SBS_F32 = 0, 1
+SERVE_F32_REFINED, SERVE_F32_FP64_SWEEP = 0, 1  # sbs_server_set_fp32_mode
 VARIANT_AUTO, VARIANT_RESIDENT, VARIANT_CHUNKED, VARIANT_STREAM, VARIANT_PARTITION = 0, 1, 2, 3, 4
 
 STATUS = {0: "SBS_OK", 1: "SBS_ERR_INVALID_ARG", 2: "SBS_ERR_ZERO_PIVOT", 3: "SBS_ERR_NONFINITE",
@@ -91,6 +92,9 @@ def lib() -> ctypes.CDLL:
         "sbs_server_release": ([vp, ctypes.c_uint64], i32),
         "sbs_server_fetch": ([vp, ctypes.c_uint64, vp, vp], i32),
         "sbs_server_stats_get": ([vp, P(ServerStats)], i32),
+        "sbs_server_set_fp32_mode": ([vp, i32], i32),
+        "sbs_server_replay": ([vp, i64, P(i32), P(vp), P(i64), P(i32), P(ctypes.c_double), P(ctypes.c_double),
+                               P(ctypes.c_double)], i32),
         "sbs_server_destroy": ([vp], i32),
         "sbs_probe_linear": ([i32, vp, vp, i64, i32, i32, vp], i32),
         "sbs_probe_blocks": ([vp, i64, i64, i32, i32, i32, i32, vp], i32),
@@ -303,6 +307,27 @@ def sbs_adi_step(hy: int, hx: int, grid: torch.Tensor, work: torch.Tensor, strea
         raise ValueError("work must hold ny*nx float64 values")
     _check(lib().sbs_adi_step(hy, hx, grid.data_ptr(), work.data_ptr(), ny, nx, _stream(stream)), "sbs_adi_step")
     return grid
+
+
+def sbs_server_replay(srv, lhs_ids, rhs_ptrs, m, dtype, arrival_us=None):
+    """sbs_server_replay over numpy arrays (one entry per request): returns
+    (status, latency_us array, elapsed seconds).  srv is the server pointer
+    (ctypes.c_void_p); rhs_ptrs are device addresses."""
+    import numpy as np
+    n = len(lhs_ids)
+    ids = np.ascontiguousarray(lhs_ids, dtype=np.int32)
+    ptrs = (ctypes.c_void_p * max(n, 1))(*[int(p) for p in rhs_ptrs])
+    ms = np.ascontiguousarray(m, dtype=np.int64)
+    dts = np.ascontiguousarray(dtype, dtype=np.int32)
+    arr = None if arrival_us is None else np.ascontiguousarray(arrival_us, dtype=np.float64)
+    lat = np.empty(max(n, 1), dtype=np.float64)
+    el = ctypes.c_double()
+    dp = ctypes.POINTER(ctypes.c_double)
+    st = lib().sbs_server_replay(
+        srv, n, ids.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), ptrs,
+        ms.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), dts.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+        None if arr is None else arr.ctypes.data_as(dp), lat.ctypes.data_as(dp), ctypes.byref(el))
+    return st, lat[:n], el.value
 
 
 class SharedLhs:

@@ -130,18 +130,20 @@ namespace sbs {
 // tile a "wave" takes one from the request's count of tiles left (acquire and
 // release), and the one that takes the last raises the request's flag with a
 // release store; the host reads the flag with an acquire load.
-hipError_t launch_tiles(int kind, int fp32, const Tile *tiles, int ntiles, int *counter, int *left, int *done, int,
+hipError_t launch_tiles(int kind, int prec, const Tile *tiles, int ntiles, int *counter, int *left, int *done, int,
                         hipStream_t s) {
     s->push([=] {
         for (int t = 0; t < ntiles; ++t) {
             const Tile &tl = tiles[t];
-            if (tl.kind != kind || tl.fp32 != fp32) std::abort();  // a launch holds one (kind, precision) group
+            if (tl.kind != kind || tl.prec != prec) std::abort();  // a launch holds one (kind, prec) group
+            // FP32 requests: the refined tiles use their scratch, the FP64-sweep tiles have none
+            if ((prec == 1) != (tl.scratch != nullptr)) std::abort();
             std::this_thread::sleep_for(std::chrono::microseconds(20));
             const int64_t j1 = tl.col0 + 64 < tl.m ? tl.col0 + 64 : tl.m;
             for (int64_t i = 0; i < tl.n; ++i)
                 for (int64_t j = tl.col0; j < j1; ++j) {
                     const int64_t k = i * tl.m + j;
-                    tl.x[k] = tl.fp32 ? (double)static_cast<const float *>(tl.in)[k]
+                    tl.x[k] = tl.prec ? (double)static_cast<const float *>(tl.in)[k]
                                       : static_cast<const double *>(tl.in)[k];
                 }
             const int before = __atomic_fetch_sub(&left[tl.req], 1, __ATOMIC_ACQ_REL);

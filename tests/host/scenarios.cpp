@@ -267,6 +267,94 @@ void churn() {
     std::printf("churn: %d requests in %lu launches\n", count, (unsigned long)st.launches);
 }
 
+// FP32 requests submitted before and after sbs_server_set_fp32_mode keep the
+// mode they were submitted with: the refined ones reserve an FP32 scratch copy
+// next to x and run as prec-1 tiles with it, the FP64-sweep ones reserve x
+// only and run as prec-2 tiles without scratch (the mock device checks the
+// tiles' prec and scratch).
+void modes() {
+    const int64_t n = 100, m = 70;
+    const size_t x_bytes = (size_t)((n * m * 8 + 255) / 256 * 256), s_bytes = (size_t)((n * m * 4 + 255) / 256 * 256);
+    sbs_server *srv = nullptr;
+    CHECK(sbs_server_create(64u << 20, 2, 0, &srv) == SBS_OK);
+    CHECK(sbs_server_set_fp32_mode(srv, 2) == SBS_ERR_INVALID_ARG);
+    CHECK(sbs_server_set_fp32_mode(srv, -1) == SBS_ERR_INVALID_ARG);
+    CHECK(sbs_server_set_fp32_mode(nullptr, SBS_SERVE_F32_REFINED) == SBS_ERR_INVALID_ARG);
+    Lhs L(srv, {n, n});
+    std::mt19937_64 g(11);
+    std::vector<Input> in;
+    std::vector<uint64_t> tk;
+    for (int r = 0; r < 12; ++r) in.push_back(make_input(g, n, m, r % 3 == 2 ? SBS_F64 : SBS_F32));
+    for (int r = 0; r < 12; ++r) {
+        if (r == 6) CHECK(sbs_server_set_fp32_mode(srv, SBS_SERVE_F32_FP64_SWEEP) == SBS_OK);
+        uint64_t t = 0;
+        CHECK(sbs_server_submit(srv, L.id[r % 2], in[r].ptr(), m, in[r].dtype, &t) == SBS_OK);
+        tk.push_back(t);
+    }
+    size_t want = 0;
+    for (int r = 0; r < 12; ++r) want += x_bytes + (in[r].dtype == SBS_F32 && r < 6 ? s_bytes : 0);
+    const double *x;
+    double lat;
+    for (int r = 0; r < 12; ++r) {
+        CHECK(sbs_server_wait(srv, tk[r], 20000000, &x, &lat) == SBS_OK);
+        CHECK(result_matches(x, in[r]));
+    }
+    sbs_server_stats st;
+    CHECK(sbs_server_stats_get(srv, &st) == SBS_OK);
+    CHECK(st.completed == 12 && st.bytes_reserved == want);
+    for (int r = 0; r < 12; ++r) CHECK(sbs_server_release(srv, tk[r]) == SBS_OK);
+    CHECK(sbs_server_stats_get(srv, &st) == SBS_OK && st.bytes_reserved == 0);
+    CHECK(sbs_server_destroy(srv) == SBS_OK);
+    std::printf("modes: 12 requests, %zu bytes reserved at the peak\n", want);
+}
+
+// The native trace replay: requests submitted at their arrival times by the
+// calling thread, waited for and released in order by a second one; every
+// latency filled in, nothing left reserved, a refused request reported as the
+// first error with latency -1 while the others still run.
+void replay() {
+    sbs_server *srv = nullptr;
+    CHECK(sbs_server_create(64u << 20, 3, 0, &srv) == SBS_OK);
+    Lhs L(srv, {50, 90, 130});
+    std::mt19937_64 g(5);
+    const int count = 300;
+    std::vector<Input> in;
+    std::vector<int32_t> ids(count), dts(count);
+    std::vector<const void *> ptrs(count);
+    std::vector<int64_t> ms(count);
+    std::vector<double> arr(count), lat(count, -2.0);
+    for (int r = 0; r < count; ++r) {
+        in.push_back(make_input(g, L.h[r % 3].n, 1 + (int64_t)(g() % 150), r % 2 ? SBS_F32 : SBS_F64));
+        ids[r] = L.id[r % 3];
+        ptrs[r] = in[r].ptr();
+        ms[r] = in[r].m;
+        dts[r] = in[r].dtype;
+        arr[r] = 50.0 * r;
+    }
+    double el = -1;
+    CHECK(sbs_server_replay(srv, count, ids.data(), ptrs.data(), ms.data(), dts.data(), arr.data(), lat.data(),
+                            &el) == SBS_OK);
+    CHECK(el >= 50e-6 * (count - 1));
+    for (int r = 0; r < count; ++r) CHECK(lat[r] >= 0);
+    sbs_server_stats st;
+    CHECK(sbs_server_stats_get(srv, &st) == SBS_OK);
+    CHECK(st.completed == (uint64_t)count && st.bytes_reserved == 0 && st.in_flight == 0);
+    // closed loop, with one request refused (m = 0)
+    ms[7] = 0;
+    CHECK(sbs_server_replay(srv, count, ids.data(), ptrs.data(), ms.data(), dts.data(), nullptr, lat.data(), &el) ==
+          SBS_ERR_INVALID_ARG);
+    CHECK(lat[7] == -1.0);
+    for (int r = 0; r < count; ++r)
+        if (r != 7) CHECK(lat[r] >= 0);
+    CHECK(sbs_server_stats_get(srv, &st) == SBS_OK);
+    CHECK(st.completed == (uint64_t)(2 * count - 1) && st.bytes_reserved == 0);
+    CHECK(sbs_server_replay(srv, 0, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, &el) == SBS_OK);
+    CHECK(sbs_server_replay(nullptr, 1, ids.data(), ptrs.data(), ms.data(), dts.data(), nullptr, nullptr, nullptr) ==
+          SBS_ERR_INVALID_ARG);
+    CHECK(sbs_server_destroy(srv) == SBS_OK);
+    std::printf("replay: %d requests, %.3f s\n", count, el);
+}
+
 }  // namespace
 
 int main(int argc, char **argv) {
@@ -277,6 +365,8 @@ int main(int argc, char **argv) {
     else if (s == "shutdown") shutdown();
     else if (s == "early") early();
     else if (s == "churn") churn();
+    else if (s == "modes") modes();
+    else if (s == "replay") replay();
     else {
         std::fprintf(stderr, "unknown scenario '%s'\n", s.c_str());
         return 2;

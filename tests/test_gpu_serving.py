@@ -29,6 +29,9 @@ class Server:
         assert self.L.sbs_server_register(self.p, h, ctypes.byref(i)) == 0
         return i.value
 
+    def set_fp32_mode(self, mode):
+        return self.L.sbs_server_set_fp32_mode(self.p, mode)
+
     def submit(self, lhs, t):
         tk = ctypes.c_uint64()
         st = self.L.sbs_server_submit(self.p, lhs, t.data_ptr(), t.shape[1],
@@ -151,6 +154,74 @@ def test_every_served_result_matches_the_oracle_alone_and_in_the_mix():
         ref = alone(hs[r.lhs], lhss[r.lhs].kind, rhs[k])
         torch.cuda.synchronize()
         assert np.array_equal(ref.cpu().numpy(), mix[k]), (k, r)
+    srv.close()
+    for h in hs:
+        h.close()
+
+
+def test_fp32_requests_as_one_fp64_sweep():
+    # The server's second mode for FP32 requests: one FP64 sweep of the
+    # stored FP32 values.  Every result against the oracle of the FP64
+    # promotion at 1e-12, the same bits alone and in the mix, and the same
+    # bits as the plain entry point's FP64 sweep of the promoted values;
+    # requests submitted before the switch keep the refined form.
+    lhss, hs = make_lhs_set(8, 40, 1500, seed=5)
+    rng = np.random.default_rng(98)
+    for kind, n in ((3, 5000), (5, 6000)):  # long enough to stream instead of checkpointing
+        B = W.tri_dominant_bands(rng, n) if kind == 3 else W.hyperdiffusion_bands(n, 0.7)
+        lhss.append(W.Lhs(kind, B))
+        hs.append(sbs.SharedLhs(kind, B))
+    srv = Server(budget=4 << 30, streams=4)
+    assert srv.set_fp32_mode(7) == 1
+    ids = [srv.register(h.handle) for h in hs]
+    trace = W.serving_trace(rate_hz=1e6, count=400, n_lhs=len(hs), m_max=200, seed=3)
+    rhs_np = [W.request_rhs(r, lhss[r.lhs].n) for r in trace]
+    rhs = [torch.from_numpy(x).to(DEV) for x in rhs_np]
+    assert any(lhss[r.lhs].n > 4096 and r.fp32 for r in trace)
+    torch.cuda.synchronize()
+    assert srv.set_fp32_mode(sbs.SERVE_F32_FP64_SWEEP) == 0
+    mix = serve_all(srv, ids, trace, rhs, lhss)
+    for k, r in enumerate(trace):
+        err = col_err(mix[k], oracle_of(lhss[r.lhs], rhs_np[k]))
+        assert err <= 1e-12, (k, r, err)
+        if r.fp32:
+            assert err <= 1e-13, (k, r, err)  # no FP32 arithmetic on the way
+            x = rhs[k].double()
+            sbs.sbs_solve_batch_variant(hs[r.lhs].handle, x, sbs.VARIANT_STREAM)
+            torch.cuda.synchronize()
+            assert np.array_equal(x.cpu().numpy(), mix[k]), (k, r)
+    for k in range(0, len(trace), 7):
+        assert np.array_equal(serve_all(srv, ids, [trace[k]], [rhs[k]], lhss)[0], mix[k]), k
+    # back to the refined form: a request submitted now is refined again
+    k = next(i for i, r in enumerate(trace) if r.fp32)
+    assert srv.set_fp32_mode(sbs.SERVE_F32_REFINED) == 0
+    again = serve_all(srv, ids, [trace[k]], [rhs[k]], lhss)[0]
+    ref = alone(hs[trace[k].lhs], lhss[trace[k].lhs].kind, rhs[k])
+    torch.cuda.synchronize()
+    assert col_err(again, ref.cpu().numpy()) <= 1e-12
+    srv.close()
+    for h in hs:
+        h.close()
+
+
+def test_native_replay_of_a_trace():
+    # the load generator the benchmark uses: 500 requests submitted at their
+    # Poisson arrival times from a native thread, each waited for and
+    # released by another; every latency is filled in and nothing stays
+    # reserved
+    lhss, hs = make_lhs_set(6, 40, 900, seed=2)
+    srv = Server(budget=2 << 30, streams=4)
+    ids = [srv.register(h.handle) for h in hs]
+    trace = W.serving_trace(rate_hz=2e4, count=500, n_lhs=len(hs), m_max=256, seed=8)
+    rhs = [torch.from_numpy(W.request_rhs(r, lhss[r.lhs].n)).to(DEV) for r in trace]
+    torch.cuda.synchronize()
+    st, lat, el = sbs.sbs_server_replay(
+        srv.p, [ids[r.lhs] for r in trace], [t.data_ptr() for t in rhs], [r.m for r in trace],
+        [sbs.SBS_F32 if r.fp32 else sbs.SBS_F64 for r in trace], [r.t_arrival * 1e6 for r in trace])
+    assert st == 0, st
+    assert np.all(lat >= 0) and el >= trace[-1].t_arrival
+    s = srv.stats()
+    assert s.completed == len(trace) and s.bytes_reserved == 0 and s.in_flight == 0
     srv.close()
     for h in hs:
         h.close()

@@ -27,7 +27,7 @@ def exe(tmp_path_factory):
     return out
 
 
-@pytest.mark.parametrize("scenario", ["mix", "budget", "errors", "shutdown", "early", "churn"])
+@pytest.mark.parametrize("scenario", ["mix", "budget", "errors", "shutdown", "early", "churn", "modes", "replay"])
 def test_scheduler_scenario(exe, scenario):
     env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:abort_on_error=0", UBSAN_OPTIONS="halt_on_error=1")
     r = subprocess.run([exe, scenario], capture_output=True, text=True, timeout=120, env=env)
