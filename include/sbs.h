@@ -360,10 +360,11 @@ sbs_status sbs_server_register(sbs_server *srv, sbs_handle h, int32_t *lhs_id);
  *  SBS_SERVE_F32_REFINED     (default) the mixed-precision form of
  *                            sbs_solve_batch_refined with 2 corrections:
  *                            FP32 sweeps, FP64 residuals and accumulation;
- *                            each tile's passes go through HBM (about 104
+ *                            each tile's passes go through HBM (about 84
  *                            bytes per unknown, more for systems too long
- *                            for checkpoints) and the arena holds an FP32
- *                            scratch copy (4 bytes per unknown) besides x.
+ *                            for checkpoints) and the arena holds three
+ *                            FP32 scratch arrays (12 bytes per unknown)
+ *                            besides x.
  *  SBS_SERVE_F32_FP64_SWEEP  one FP64 sweep of the FP32 values (read and
  *                            promoted as they are loaded): the FP64 solve of
  *                            the stored right-hand sides, which is what the

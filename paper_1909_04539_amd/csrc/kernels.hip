@@ -1092,6 +1092,9 @@ __global__ __launch_bounds__(MAXT) void k_part_refine(const unsigned char *__res
 // computed.
 //  MODE 0: r_i = fl32(b_i - (A x)_i)
 //  MODE 1: x_i += delta_i for every row, then r from the updated x
+//  MODE 2: x is FP32 (the first solve's result x0) and delta the first
+//          correction: r from x = fl64(x0 + delta), which is not stored
+//          (the same values MODE 1 would store and use)
 // (A x)_i is summed left to right over the row's coefficients, in FP64.
 constexpr int kResRows = 16;  // RL: rows per residual chunk
 constexpr size_t kResLds = 2 * kResRows * sizeof(BandRow);  // band rows of two chunks
@@ -1100,28 +1103,30 @@ constexpr size_t kResLds = 2 * kResRows * sizeof(BandRow);  // band rows of two 
 // last H rows are the next chunk's first, re-read from cache: row i's
 // residual needs x_{i+H}), b of rows r0 .. r0+RL-1.  Rows at or beyond n read
 // as 0.
-template <int H, int MODE>
+template <int H, int MODE, typename XT = double>
 struct ResChunk {
     static constexpr int RL = kResRows;
-    double x[RL + H];
+    XT x[RL + H];
     float d[RL + H], b[RL];
-    __device__ __forceinline__ void load(const char *px, const char *pd, const char *pb, uint32_t l8, uint32_t l4,
-                                         int r0, int n, int64_t rs8, int64_t rs4) {
+    __device__ __forceinline__ void load(const char *px, const char *pd, const char *pb, uint32_t lx, uint32_t l4,
+                                         int r0, int n, int64_t rsx, int64_t rs4) {
 #pragma unroll
         for (int t = 0; t < RL + H; ++t) {
             const bool in = r0 + t < n;
-            x[t] = in ? ld<double>(px + (int64_t)(r0 + t) * rs8, l8) : 0.0;
-            if constexpr (MODE == 1) d[t] = in ? ld<float>(pd + (int64_t)(r0 + t) * rs4, l4) : 0.0f;
+            x[t] = in ? ld<XT>(px + (int64_t)(r0 + t) * rsx, lx) : XT(0);
+            if constexpr (MODE >= 1) d[t] = in ? ld<float>(pd + (int64_t)(r0 + t) * rs4, l4) : 0.0f;
             if (t < RL) b[t] = in ? ld<float>(pb + (int64_t)(r0 + t) * rs4, l4) : 0.0f;
         }
     }
 };
 
-template <int KIND, int MODE>
+template <int KIND, int MODE, typename XT = double>
 __device__ __forceinline__ void residual_wave(const BandRow *__restrict__ bands, int64_t n64,
-                                              const float *__restrict__ b, double *__restrict__ x,
+                                              const float *__restrict__ b, XT *__restrict__ x,
                                               const float *dl, float *r, int64_t m, int64_t j0,
                                               unsigned char *lds) {
+    static_assert(MODE != 1 || sizeof(XT) == 8, "MODE 1 stores x in FP64");
+    static_assert(MODE != 2 || sizeof(XT) == 4, "MODE 2 reads x0 in FP32");
     // dl and r may be the same buffer: a chunk's delta values are loaded
     // before any residual of that chunk is stored, and the H rows past the
     // chunk are loaded with the next chunk, before its residuals are stored.
@@ -1136,12 +1141,12 @@ __device__ __forceinline__ void residual_wave(const BandRow *__restrict__ bands,
     j0 = (int64_t)uni64((uint64_t)j0);
     const int n = __builtin_amdgcn_readfirstlane((int)n64);
     const int jl = (j0 + lane < m) ? lane : (int)(m - 1 - j0);
-    const uint32_t l4 = (uint32_t)jl * 4, l8 = (uint32_t)jl * 8;
+    const uint32_t l4 = (uint32_t)jl * 4, lx = (uint32_t)jl * (uint32_t)sizeof(XT);
     const char *pb = reinterpret_cast<const char *>(b + j0);
     char *px = reinterpret_cast<char *>(x + j0);
     const char *pd = reinterpret_cast<const char *>(dl + j0);
     char *pr = reinterpret_cast<char *>(r + j0);
-    const int64_t rs4 = m * 4, rs8 = m * 8;
+    const int64_t rs4 = m * 4, rsx = m * (int64_t)sizeof(XT);
     const int K = (n + RL - 1) / RL;
     auto brow = [&](int k) { return reinterpret_cast<const BandRow *>(lds + (k & 1) * CBB); };
     FacRegs<CBB> bv;  // band rows of a chunk on their way to LDS
@@ -1150,26 +1155,26 @@ __device__ __forceinline__ void residual_wave(const BandRow *__restrict__ bands,
     double prev[H];
 #pragma unroll
     for (int q = 0; q < H; ++q) prev[q] = 0.0;
-    ResChunk<H, MODE> cur, nxt;
+    ResChunk<H, MODE, XT> cur, nxt;
     bv.load(bands, lane);
-    cur.load(px, pd, pb, l8, l4, 0, n, rs8, rs4);
+    cur.load(px, pd, pb, lx, l4, 0, n, rsx, rs4);
     bv.stage(lds, lane);
     if (K > 1) bv.load(bands + RL, lane);
     for (int k = 0; k < K; ++k) {
         const int r0 = k * RL;
         const bool more = k + 1 < K;
-        if (more) nxt.load(px, pd, pb, l8, l4, r0 + RL, n, rs8, rs4);
+        if (more) nxt.load(px, pd, pb, lx, l4, r0 + RL, n, rsx, rs4);
         // the chunk's x (and the H rows after it), updated by delta
         double xs[RL + H];
 #pragma unroll
         for (int t = 0; t < RL + H; ++t) {
-            xs[t] = cur.x[t];
-            if constexpr (MODE == 1) xs[t] += (double)cur.d[t];
+            xs[t] = (double)cur.x[t];
+            if constexpr (MODE >= 1) xs[t] += (double)cur.d[t];
         }
         if constexpr (MODE == 1) {
 #pragma unroll
             for (int t = 0; t < RL; ++t)
-                if (r0 + t < n) st<double>(px + (int64_t)(r0 + t) * rs8, l8, xs[t]);
+                if (r0 + t < n) st<double>(px + (int64_t)(r0 + t) * rsx, lx, xs[t]);
         }
         const BandRow *br = brow(k);
 #pragma unroll
@@ -1200,44 +1205,51 @@ __global__ __launch_bounds__(kWave) void k_residual(const BandRow *__restrict__ 
     residual_wave<KIND, MODE>(bands, n, b, x, dl, r, m, (int64_t)blockIdx.x * kWave, lds);
 }
 
-// x += delta over one wave's 64 systems (final correction inside a tile),
-// U rows per batch with the next batch's loads in flight.
-__device__ __forceinline__ void update_wave(double *x, const float *dl, int64_t n64, int64_t m, int64_t j0) {
-    constexpr int U = 16;
+// x = fl64(fl64(x0 + d1) + d2) over one wave's 64 systems: the refined
+// tile's result from the first solve's FP32 values and the two FP32
+// corrections (the same values as x += d1, then x += d2 in FP64), U rows per
+// batch with the next batch's loads in flight.
+__device__ __forceinline__ void finish_wave(double *x, const float *x0, const float *d1, const float *d2,
+                                            int64_t n64, int64_t m, int64_t j0) {
+    constexpr int U = 8;
     const int lane = threadIdx.x;
     x = uni(x);
-    dl = uni(dl);
+    x0 = uni(x0);
+    d1 = uni(d1);
+    d2 = uni(d2);
     m = (int64_t)uni64((uint64_t)m);
     j0 = (int64_t)uni64((uint64_t)j0);
     const int n = __builtin_amdgcn_readfirstlane((int)n64);
     const int jl = (j0 + lane < m) ? lane : (int)(m - 1 - j0);
     char *px = reinterpret_cast<char *>(x + j0);
-    const char *pd = reinterpret_cast<const char *>(dl + j0);
+    const char *p0 = reinterpret_cast<const char *>(x0 + j0), *p1 = reinterpret_cast<const char *>(d1 + j0),
+               *p2 = reinterpret_cast<const char *>(d2 + j0);
     const uint32_t l4 = (uint32_t)jl * 4, l8 = (uint32_t)jl * 8;
     const int64_t rs4 = m * 4, rs8 = m * 8;
-    double xc[U], xn[U];
-    float dc[U], dn[U];
-    auto load = [&](double (&xb)[U], float (&db)[U], int r0) {
+    float c[3][U], nx[3][U];
+    auto load = [&](float (&v)[3][U], int r0) {
 #pragma unroll
         for (int t = 0; t < U; ++t) {
             const bool in = r0 + t < n;
-            xb[t] = in ? ld<double>(px + (int64_t)(r0 + t) * rs8, l8) : 0.0;
-            db[t] = in ? ld<float>(pd + (int64_t)(r0 + t) * rs4, l4) : 0.0f;
+            const int64_t o = (int64_t)(r0 + t) * rs4;
+            v[0][t] = in ? ld<float>(p0 + o, l4) : 0.0f;
+            v[1][t] = in ? ld<float>(p1 + o, l4) : 0.0f;
+            v[2][t] = in ? ld<float>(p2 + o, l4) : 0.0f;
         }
     };
-    load(xc, dc, 0);
+    load(c, 0);
     for (int r0 = 0; r0 < n; r0 += U) {
         const bool more = r0 + U < n;
-        if (more) load(xn, dn, r0 + U);
+        if (more) load(nx, r0 + U);
 #pragma unroll
         for (int t = 0; t < U; ++t)
-            if (r0 + t < n) st<double>(px + (int64_t)(r0 + t) * rs8, l8, xc[t] + (double)dc[t]);
+            if (r0 + t < n)
+                st<double>(px + (int64_t)(r0 + t) * rs8, l8, ((double)c[0][t] + (double)c[1][t]) + (double)c[2][t]);
         if (more) {
 #pragma unroll
-            for (int t = 0; t < U; ++t) {
-                xc[t] = xn[t];
-                dc[t] = dn[t];
-            }
+            for (int q = 0; q < 3; ++q)
+#pragma unroll
+                for (int t = 0; t < U; ++t) c[q][t] = nx[q][t];
         }
     }
 }
@@ -1295,34 +1307,33 @@ __device__ __forceinline__ void tile_sweep_f32(const typename Rec<KIND, float>::
     sweep_wave<KIND, float, float, Tout, 32, MODE>(fac, n, in, out, m, j0, lds);
 }
 
-template <int KIND, int MODE>
-__device__ __forceinline__ void tile_residual(const BandRow *bands, int64_t n, const float *b, double *x,
-                                           float *r, int64_t m, int64_t j0, unsigned char *lds) {
-    residual_wave<KIND, MODE>(bands, n, b, x, r, r, m, j0, lds);
-}
-
+// The refined tile keeps its intermediate values in FP32 in three n x m
+// scratch arrays: x0 (the first solve), d1 (the first correction), r / d2
+// (the second residual, then the second correction); x = fl64(x0 + d1) is
+// formed where the second residual reads it and x = fl64(fl64(x0 + d1) + d2)
+// at the end, the values an FP64 x updated in place would take (84 bytes per
+// unknown with checkpointed sweeps, against 104 with x in FP64 throughout).
 template <int KIND>
 __device__ __forceinline__ void run_tile_f32(const Tile &t, unsigned char *lds) {
     const int n = (int)t.n;
     using Row = typename Rec<KIND, float>::Row;
     const Row *fac = reinterpret_cast<const Row *>(t.fac);
     const float *b = reinterpret_cast<const float *>(t.in);
+    const int64_t nm = t.n * t.m;
+    float *x0 = t.scratch, *d1 = t.scratch + nm, *d2 = t.scratch + 2 * nm;
     const bool chunk = tile_fits_chunked<KIND, float>(n);
-    if (chunk)
-        tile_sweep_f32<KIND, double, MODE_CHUNKED>(fac, n, b, t.x, t.m, t.col0, lds);
-    else
-        tile_sweep_f32<KIND, double, MODE_STREAM>(fac, n, b, t.x, t.m, t.col0, lds);
-    for (int pass = 0; pass < 2; ++pass) {
-        if (pass == 0)
-            tile_residual<KIND, 0>(t.bands, n, b, t.x, t.scratch, t.m, t.col0, lds);
-        else
-            tile_residual<KIND, 1>(t.bands, n, b, t.x, t.scratch, t.m, t.col0, lds);
+    auto solve = [&](const float *in, float *out) {
         if (chunk)
-            tile_sweep_f32<KIND, float, MODE_CHUNKED>(fac, n, t.scratch, t.scratch, t.m, t.col0, lds);
+            tile_sweep_f32<KIND, float, MODE_CHUNKED>(fac, n, in, out, t.m, t.col0, lds);
         else
-            tile_sweep_f32<KIND, float, MODE_STREAM>(fac, n, t.scratch, t.scratch, t.m, t.col0, lds);
-    }
-    update_wave(t.x, t.scratch, n, t.m, t.col0);
+            tile_sweep_f32<KIND, float, MODE_STREAM>(fac, n, in, out, t.m, t.col0, lds);
+    };
+    solve(b, x0);
+    residual_wave<KIND, 0, float>(t.bands, n, b, x0, d1, d1, t.m, t.col0, lds);
+    solve(d1, d1);
+    residual_wave<KIND, 2, float>(t.bands, n, b, x0, d1, d2, t.m, t.col0, lds);
+    solve(d2, d2);
+    finish_wave(t.x, x0, d1, d2, n, t.m, t.col0);
 }
 
 // FP32 requests served as one FP64 sweep of their FP32 right-hand sides

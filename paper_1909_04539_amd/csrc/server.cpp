@@ -392,7 +392,8 @@ sbs_status sbs_server_submit(sbs_server *srv, int32_t lhs_id, const void *rhs, i
     const sbs_lhs *h = srv->lhs[lhs_id];
     const size_t nm = (size_t)h->n * (size_t)m;
     const int32_t prec = dtype == SBS_F64 ? 0 : (srv->fp32_mode == SBS_SERVE_F32_FP64_SWEEP ? 2 : 1);
-    r->bytes = round_up(nm * 8, kAlign) + (prec == 1 ? round_up(nm * 4, kAlign) : 0);
+    // refined FP32 requests: three FP32 scratch arrays (x0, d1, r / d2) besides x
+    r->bytes = round_up(nm * 8, kAlign) + (prec == 1 ? round_up(nm * 12, kAlign) : 0);
     if (r->bytes > srv->budget) {
         ++srv->rejected;
         delete r;

@@ -268,13 +268,13 @@ void churn() {
 }
 
 // FP32 requests submitted before and after sbs_server_set_fp32_mode keep the
-// mode they were submitted with: the refined ones reserve an FP32 scratch copy
-// next to x and run as prec-1 tiles with it, the FP64-sweep ones reserve x
+// mode they were submitted with: the refined ones reserve three FP32 scratch
+// arrays next to x and run as prec-1 tiles with them, the FP64-sweep ones reserve x
 // only and run as prec-2 tiles without scratch (the mock device checks the
 // tiles' prec and scratch).
 void modes() {
     const int64_t n = 100, m = 70;
-    const size_t x_bytes = (size_t)((n * m * 8 + 255) / 256 * 256), s_bytes = (size_t)((n * m * 4 + 255) / 256 * 256);
+    const size_t x_bytes = (size_t)((n * m * 8 + 255) / 256 * 256), s_bytes = (size_t)((n * m * 12 + 255) / 256 * 256);
     sbs_server *srv = nullptr;
     CHECK(sbs_server_create(64u << 20, 2, 0, &srv) == SBS_OK);
     CHECK(sbs_server_set_fp32_mode(srv, 2) == SBS_ERR_INVALID_ARG);
