@@ -340,6 +340,15 @@ sbs_status sbs_server_create(size_t budget_bytes, int32_t max_streams, int32_t m
         else if (hipHostGetDevicePointer(reinterpret_cast<void **>(&sl.flag_dev), sl.flag_host, 0) != hipSuccess)
             st = SBS_ERR_DEVICE;
     }
+    if (st == SBS_OK) {
+        // no exception crosses the C ABI: a thread that cannot be started is
+        // reported as a lack of resources
+        try {
+            s->worker = std::thread([s] { s->loop(); });
+        } catch (...) {
+            st = SBS_ERR_NO_MEMORY;
+        }
+    }
     if (st != SBS_OK) {
         for (Slot &sl : s->slots) {
             if (sl.dev) (void)hipFree(sl.dev);
@@ -352,7 +361,6 @@ sbs_status sbs_server_create(size_t budget_bytes, int32_t max_streams, int32_t m
         delete s;
         return st;
     }
-    s->worker = std::thread([s] { s->loop(); });
     *out = s;
     return SBS_OK;
 }
@@ -361,8 +369,12 @@ sbs_status sbs_server_register(sbs_server *srv, sbs_handle h, int32_t *lhs_id) {
     if (!srv || !h || !lhs_id) return SBS_ERR_INVALID_ARG;
     if (h->kind != SBS_TRI && h->kind != SBS_PENTA) return SBS_ERR_INVALID_ARG;  // tiles cover the banded kinds
     std::lock_guard<std::mutex> lk(srv->mu);
-    *lhs_id = (int32_t)srv->lhs.size();
-    srv->lhs.push_back(h);
+    try {
+        srv->lhs.push_back(h);
+    } catch (...) {  // no exception crosses the C ABI
+        return SBS_ERR_NO_MEMORY;
+    }
+    *lhs_id = (int32_t)srv->lhs.size() - 1;
     return SBS_OK;
 }
 
@@ -406,8 +418,14 @@ sbs_status sbs_server_submit(sbs_server *srv, int32_t lhs_id, const void *rhs, i
     r->dtype = dtype;
     r->prec = prec;
     r->t_submit = Clock::now();
-    srv->reqs[r->ticket] = r;
-    srv->queue.push_back(r);
+    try {
+        srv->reqs[r->ticket] = r;
+        srv->queue.push_back(r);
+    } catch (...) {  // no exception crosses the C ABI
+        srv->reqs.erase(r->ticket);
+        delete r;
+        return SBS_ERR_NO_MEMORY;
+    }
     ++srv->submitted;
     *ticket = r->ticket;
     ++srv->kicks;
@@ -466,7 +484,12 @@ sbs_status sbs_server_replay(sbs_server *srv, int64_t count, const int32_t *lhs_
                              const int64_t *m, const int32_t *dtype, const double *arrival_us, double *latency_us,
                              double *elapsed_s) {
     if (!srv || count < 0 || (count > 0 && (!lhs_ids || !rhs || !m || !dtype))) return SBS_ERR_INVALID_ARG;
-    std::vector<uint64_t> ticket((size_t)count, 0);
+    std::vector<uint64_t> ticket;
+    try {
+        ticket.assign((size_t)count, 0);
+    } catch (...) {  // no exception crosses the C ABI
+        return SBS_ERR_NO_MEMORY;
+    }
     std::unique_ptr<std::atomic<int>[]> posted(new (std::nothrow) std::atomic<int>[(size_t)count]);
     if (count > 0 && !posted) return SBS_ERR_NO_MEMORY;
     for (int64_t k = 0; k < count; ++k) posted[k].store(0, std::memory_order_relaxed);
@@ -478,7 +501,8 @@ sbs_status sbs_server_replay(sbs_server *srv, int64_t count, const int32_t *lhs_
     const auto t0 = Clock::now();
     Clock::time_point t_end = t0;
     // waits for and releases the requests in order, as the submitter posts them
-    std::thread waiter([&] {
+    std::thread waiter;
+    auto wait_all = [&] {
         for (int64_t k = 0; k < count; ++k) {
             int p;
             while ((p = posted[k].load(std::memory_order_acquire)) == 0) std::this_thread::yield();
@@ -492,7 +516,12 @@ sbs_status sbs_server_replay(sbs_server *srv, int64_t count, const int32_t *lhs_
             if (latency_us) latency_us[k] = lat;
         }
         t_end = Clock::now();
-    });
+    };
+    try {
+        waiter = std::thread(wait_all);
+    } catch (...) {  // no exception crosses the C ABI
+        return SBS_ERR_NO_MEMORY;
+    }
     for (int64_t k = 0; k < count; ++k) {
         if (arrival_us) {
             const auto due = t0 + std::chrono::duration_cast<Clock::duration>(
