@@ -487,8 +487,9 @@ def test_adi_step_with_pentadiagonal_rows(ny, nx):
 @pytest.mark.parametrize("ny,nx", [(64, 2048), (333, 1024), (1000, 96), (257, 64), (100, 65), (40, 1001)])
 def test_adi_rows_equal_the_transposed_path(ny, nx):
     # The x-direction solve reads the grid's rows in place when the x-matrix
-    # has a partition plan; it must give the bits of transpose, interleaved
-    # solve, transpose back (the same plan and arithmetic).
+    # has a partition plan (pair form); it must give the bits of transpose,
+    # interleaved solve, transpose back where the interleaved solve takes the
+    # pair form too (the same plan and arithmetic), else agree to 1e-13.
     By = W.diffusion_bands(ny, 0.5)
     Bx = bands_for(3, nx, nx)
     g = np.random.default_rng(ny + nx).uniform(-1, 1, (ny, nx))
@@ -500,10 +501,14 @@ def test_adi_rows_equal_the_transposed_path(ny, nx):
         R = torch.from_numpy(g.copy()).to(DEV)
         hy.solve(R)
         T = sbs.sbs_transpose(R)
+        form = sbs.sbs_partition_shape(hx.handle, T)[0]
         hx.solve(T)
         R = sbs.sbs_transpose(T)
         torch.cuda.synchronize()
-        assert torch.equal(G, R)
+        if form == 0:
+            assert torch.equal(G, R)
+        else:
+            assert colrel(G.cpu().numpy(), R.cpu().numpy()) <= 1e-13
         ref = oracle.adi_step(By, Bx, g)
         assert colrel(G.cpu().numpy(), ref) <= TOL64
 
