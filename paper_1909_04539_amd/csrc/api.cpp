@@ -115,13 +115,14 @@ int pick_uncached(const sbs_lhs *h, int t, int64_t m, const void *rhs, bool for_
     const bool part = sbs::choose_partition(h, t, m, pc);
     if (sep && !sc->gf && sbs::sep_fills(h, t, m, *sc)) return 1;
     // too few systems to fill the chip with whole row runs: where the pair
-    // form would take 64-row blocks, the separator form's 32-row blocks with
-    // two systems per lane and 16 per workgroup (plan in LDS) finish sooner
-    // (tridiagonal n = 2048, m = 2048: 15.4 against 19.0 us; pentadiagonal
-    // n = 1024, m = 2048: 11.7 against 16.5 us; tridiagonal n = 2048,
-    // m = 8192: 63.7 against 67.8 us); against shorter pair blocks it was
-    // not faster throughout
-    if (part && t == 0 && h->part[pc->plan].lb == 64) {
+    // form would take 64-row blocks of at most 16 systems (128-byte runs),
+    // the separator form's 32-row blocks with two systems per lane and 16
+    // per workgroup (plan in LDS) finish sooner (tridiagonal n = 2048,
+    // m = 2048: 15.4 against 19.0 us; pentadiagonal n = 1024, m = 2048: 11.7
+    // against 16.5 us; tridiagonal n = 2048, m = 8192: 63.7 against
+    // 67.8 us); against shorter pair blocks it was not faster throughout,
+    // and where the pair form has 256-byte runs those are worth more
+    if (part && t == 0 && h->part[pc->plan].lb == 64 && pc->S <= 16) {
         sbs::SepChoice alt;
         if (sbs::sep_shape(h, t, m, rhs, 32, 2, 16, 0, &alt) && !alt.gf) {
             *sc = alt;
