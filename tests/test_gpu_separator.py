@@ -210,3 +210,37 @@ def test_windowed_separator_product_equals_every_column(kind, n, m, bands, shape
             assert colrel(win, ref) <= TOL64, (lb, vec, S, colrel(win, ref))
             ran += 1
     assert ran > 0
+
+
+@pytest.mark.parametrize("kind,n,m,bands,want", [
+    (3, 2048, 2048, "adi", (1, 32, 2, 16)), (5, 1024, 2048, "hyper", (1, 32, 2, 16)),
+    (5, 1024, 65536, "random", None), (5, 1024, 65536, "hyper", (1, 32, 2, 32)),
+    (3, 256, 1024, "random", (0, 16, 1, 16))])
+def test_auto_shape_for_latency_bound_batches(kind, n, m, bands, want):
+    # Where the pair form would take 64-row blocks of at most 16 systems
+    # (128-byte runs: too few systems to fill the chip), AUTO takes the
+    # separator form with 32-row blocks, two systems per lane and 16 per
+    # workgroup; pair shapes with 256-byte runs, pair shapes of shorter
+    # blocks and separator shapes that fill the chip stay as they were.
+    if bands == "adi":
+        B = W.diffusion_bands(n, 0.5)  # the ADI step's y matrix
+    elif bands == "hyper":
+        B = W.hyperdiffusion_bands(n, 0.5)
+    else:
+        B = bands_for(kind, n, 40 + n)
+    with sbs.SharedLhs(kind, B) as h:
+        x = torch.empty((n, m), dtype=torch.float64, device=DEV)
+        got = sbs.sbs_partition_shape(h.handle, x)
+        print(f"AUTO shape kind={kind} n={n} m={m} {bands}: {got}", flush=True)
+        if want is None:  # a shape that fills the chip with 256-byte runs
+            assert got[3] * 8 >= 256, got
+        else:
+            assert tuple(got) == want
+        if m <= 2048:
+            rhs = np.random.default_rng(n).uniform(-1, 1, (n, m))
+            x.copy_(torch.from_numpy(rhs))
+            h.solve(x)
+            torch.cuda.synchronize()
+            cols = np.r_[0, 1, 15, 16, 17, m // 2, m - 2, m - 1]
+            ref = oracle.solve(kind, B, rhs[:, cols])
+            assert colrel(x[:, torch.from_numpy(cols).to(DEV)].cpu().numpy(), ref) <= TOL64
