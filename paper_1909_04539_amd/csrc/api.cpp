@@ -129,6 +129,18 @@ int pick_uncached(const sbs_lhs *h, int t, int64_t m, const void *rhs, bool for_
             return 1;
         }
     }
+    // pentadiagonal, where the pair form would take 32-row blocks of at most
+    // 16 systems: 16-row separator blocks, one system per lane, 16 per
+    // workgroup (n = 512, m = 4096: 10.0 against 11.7 us; n = 384,
+    // m = 2048: 8.7 against 10.2 us; n = 512, m = 1024: 8.9 against 9.5 us;
+    // for tridiagonal matrices the two were even)
+    if (part && t == 0 && h->kind == SBS_PENTA && h->part[pc->plan].lb == 32 && pc->S <= 16) {
+        sbs::SepChoice alt;
+        if (sbs::sep_shape(h, t, m, rhs, 16, 1, 16, 0, &alt) && !alt.gf) {
+            *sc = alt;
+            return 1;
+        }
+    }
     if (part) return 2;
     const size_t elem = t == 0 ? 8 : 4;
     if (sep && (!for_auto || !sc->gf || (size_t)sc->S * elem >= 128)) return 1;

@@ -215,13 +215,16 @@ def test_windowed_separator_product_equals_every_column(kind, n, m, bands, shape
 @pytest.mark.parametrize("kind,n,m,bands,want", [
     (3, 2048, 2048, "adi", (1, 32, 2, 16)), (5, 1024, 2048, "hyper", (1, 32, 2, 16)),
     (5, 1024, 65536, "random", None), (5, 1024, 65536, "hyper", (1, 32, 2, 32)),
-    (3, 256, 1024, "random", (0, 16, 1, 16))])
+    (3, 256, 1024, "random", (0, 16, 1, 16)), (5, 512, 4096, "hyper", (1, 16, 1, 16)),
+    (5, 384, 2048, "hyper", (1, 16, 1, 16)), (3, 1024, 4096, "random", (0, 32, 1, 16))])
 def test_auto_shape_for_latency_bound_batches(kind, n, m, bands, want):
     # Where the pair form would take 64-row blocks of at most 16 systems
     # (128-byte runs: too few systems to fill the chip), AUTO takes the
     # separator form with 32-row blocks, two systems per lane and 16 per
-    # workgroup; pair shapes with 256-byte runs, pair shapes of shorter
-    # blocks and separator shapes that fill the chip stay as they were.
+    # workgroup; for pentadiagonal matrices, where it would take 32-row pair
+    # blocks of at most 16 systems, 16-row separator blocks with one system
+    # per lane.  Pair shapes with 256-byte runs, other pair shapes and
+    # separator shapes that fill the chip stay as they were.
     if bands == "adi":
         B = W.diffusion_bands(n, 0.5)  # the ADI step's y matrix
     elif bands == "hyper":
