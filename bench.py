@@ -357,13 +357,13 @@ def bench_refined(args, torch, sbs, W):
     lhs = sbs.SharedLhs(3, wl.bands)
     work = torch.empty(sbs.sbs_refined_workspace_bytes(lhs.handle, m), dtype=torch.uint8, device="cuda:0")
     step = lambda: lhs.solve_refined(b, sweeps=2, x=x, work=work)
-    wall, dev = timed_steps(step, 5, 2, torch)
+    wall, dev = timed_steps(step, 20, 3, torch)
     u = n * m
     out = {"workload": "tri_refine_f32in_f64out_n512_m1048576", "unknowns_per_s": u / dev, "ms_per_solve": dev * 1e3,
            "hbm_frac_12B_io_min": round(12 * u / dev / 1e9 / HBM_PEAK_GBS, 4)}
     # plain FP64 on the same shape, for comparison
     x.copy_(b)
-    wall, dev64 = timed_steps(lambda: lhs.solve(x), 5, 2, torch)
+    wall, dev64 = timed_steps(lambda: lhs.solve(x), 20, 3, torch)
     out["plain_f64_unknowns_per_s"] = u / dev64
     out["plain_f64_hbm_frac_16B"] = round(16 * u / dev64 / 1e9 / HBM_PEAK_GBS, 4)
     # accuracy on sampled columns against the FP64 oracle of double(b32)

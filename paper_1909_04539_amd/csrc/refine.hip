@@ -304,13 +304,13 @@ __global__ __launch_bounds__(MAXT) void k_refine_wave(const unsigned char *__res
         if (full) {
 #pragma unroll
             for (int t = 0; t < LB; ++t) {
-                w[t] = __builtin_nontemporal_load(src);
+                w[t] = *src;
                 src = step(src, m);
             }
         } else {
 #pragma unroll
             for (int t = 0; t < LB; ++t) {
-                w[t] = r0 + t < n ? __builtin_nontemporal_load(src) : 0.0f;
+                w[t] = r0 + t < n ? *src : 0.0f;
                 src = step(src, m);
             }
         }
